@@ -1,0 +1,232 @@
+"""Benchmark: gradients/s of the batched complex64 adjoint path on one MI355X.
+
+Workload (one step): quantum circuit learning at 20 qubits -- 64 data samples, each circuit RY(arcsin x_k)
+on every qubit followed by 8 hardware-efficient layers (RY all, RZ all, CNOT ladder; 320 shared
+parameters), observable Z_0, MSE loss against y = sin(pi x) + noise. One step = parameters into the
+batch, forward pass of all 64 circuits (states, FP64 expectation reductions), loss on the device, and
+the adjoint backward sweep that returns dL/dtheta: one full gradient. Inputs are synthetic and seeded.
+
+Also reported: the same gradient by the parameter-shift rule on the same GPU (64 x 641 circuits through
+the same batched engine, measured in full), by the plain per-circuit path (one global-memory pass per
+gate, one circuit in flight; timed on a subset and extrapolated), the circuit-eval rate, the roofline
+position of the dominant kernel (per-launch HIP events on the stream the kernels run on), and the CPU
+oracle timed on the host on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--layers L] [--no-cpu] [--no-ps]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ["kernels.hip", "engine.h"]:
+        with open(os.path.join(ROOT, "paper_2406_03466_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def summarize_launches(recs):
+    per = {}
+    for r in recs:
+        k = per.setdefault(r["kernel"], {"launches": 0, "ms": 0.0, "bytes": 0})
+        k["launches"] += 1
+        k["ms"] += r["ms"]
+        k["bytes"] += r["bytes"]
+    for k in per.values():
+        k["avg_ms"] = k["ms"] / k["launches"]
+        k["avg_bytes"] = k["bytes"] / k["launches"]
+        k["gbs"] = (k["avg_bytes"] / 1e9) / (k["avg_ms"] / 1e3) if k["avg_ms"] > 0 else 0.0
+    return per
+
+
+def cpu_baseline(wl_full, max_seconds: float = 20.0):
+    """The oracle (plain complex128 CPU simulator) on a bounded sample: adjoint gradients of the first k
+    samples of the same workload, scaled to full gradients per second."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    k = threads
+    sub = wl_full.subset(range(k))
+    e, _, _, _ = oracle.expectations(sub, nthreads=threads)
+    up = 2.0 * (e - sub.extra["y"]) / wl_full.B
+    t0 = time.time()
+    oracle.grad_adjoint(sub, up, nthreads=threads)
+    dt = time.time() - t0
+    used = oracle.max_threads(threads)
+    return {"value": (k / wl_full.B) / dt, "unit": "gradients/s", "cores": used, "kind": "oracle",
+            "sample": f"oracle adjoint gradient of {k} of the {wl_full.B} samples (complex128, {used} threads), "
+                      f"{dt:.1f} s, scaled by {k}/{wl_full.B}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--layers", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ps", action="store_true")
+    ap.add_argument("--tile-qubits", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the whole batch is one GPU's share; "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2406_03466_amd import qvpu
+    from paper_2406_03466_amd import workloads as W
+    from paper_2406_03466_amd.autograd import expectation
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = W.config3(args.layers)
+    stream = torch.cuda.current_stream(dev)
+    opts = {"graph": False, "launch_events": True}
+    if args.tile_qubits:
+        opts["tile_qubits"] = args.tile_qubits
+    ctx = qvpu.Context(0, stream.cuda_stream, json.dumps(opts))
+    batch = qvpu.Batch(ctx, wl, qvpu.QV_C64)
+    theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev, requires_grad=True)
+    y = torch.tensor(wl.extra["y"], dtype=torch.float64, device=dev)
+
+    def step():
+        theta.grad = None
+        f = expectation(theta, batch)
+        loss = torch.mean((f - y) ** 2)
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    recs = []
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    batch.launch_log()  # drop the warm-up records
+    t_start.record(stream)
+    for _ in range(args.steps):
+        step()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    recs = batch.launch_log()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    grads_per_s = 1000.0 / ms_step
+    per = summarize_launches(recs)
+    dom = max(per, key=lambda k: per[k]["ms"])
+    d = per[dom]
+    achieved = d["gbs"]
+    kernel_sym = {"tile_adj": "k_tile<float,true>", "tile": "k_tile<float,false>"}.get(dom, dom)
+    workload_tag = f"qcl20_L{args.layers}"
+    traffic = pmc_traffic(dom, workload_tag)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_sym,
+                "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
+                "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
+    # forward-only circuit evals/s (the 64 circuits of one forward pass)
+    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("init", "tile", "expect", "finalize")) / args.steps
+    circuit_evals_per_s = wl.B / (fwd_ms / 1e3)
+
+    extra = {}
+    if not args.no_ps:
+        # parameter-shift gradient through the same batched tiled engine, measured in full
+        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False}))
+        b_ps = qvpu.Batch(ctx_ps, wl, qvpu.QV_C64)
+        with torch.no_grad():
+            f = expectation(theta.detach(), batch)
+            up = (2.0 * (f - y) / wl.B).contiguous()
+        g_buf = torch.empty(wl.n_grad(), dtype=torch.float64, device=dev)
+        b_ps.gradient(qvpu.QV_PARAM_SHIFT, upstream=up, grad=g_buf)  # warm-up (plans, buffers)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        b_ps.gradient(qvpu.QV_PARAM_SHIFT, upstream=up, grad=g_buf)
+        torch.cuda.synchronize()
+        ps_s = time.time() - t0
+        g_ad = theta.grad.detach().clone() if theta.grad is not None else None
+        n_ps_circ = wl.B * (2 * int(np.sum(wl.circuit(0)["param"] >= 0)) + 1)
+        extra["param_shift_tiled"] = {"gradients_per_s": 1.0 / ps_s, "seconds": ps_s, "circuits": n_ps_circ,
+                                      "measured": "full gradient"}
+        if g_ad is not None:
+            scale = float(torch.sum(torch.abs(up)).item())
+            extra["adjoint_vs_param_shift_max_abs_diff_over_scale"] = float(
+                torch.max(torch.abs(g_ad - g_buf)).item() / max(scale, 1e-300))
+        del b_ps, ctx_ps
+        # plain per-circuit path: one global-memory pass per gate, one circuit in flight, on a subset
+        sub = wl.subset([0])
+        ctx_pl = qvpu.Context(0, stream.cuda_stream,
+                              json.dumps({"graph": False, "engine": "stride", "n-virtual-qpus": 1}))
+        b_pl = qvpu.Batch(ctx_pl, sub, qvpu.QV_C64)
+        b_pl.expectations(want_terms=False)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        b_pl.expectations(want_terms=False)
+        torch.cuda.synchronize()
+        one_circ_s = time.time() - t0
+        ps_plain_s = one_circ_s * n_ps_circ
+        extra["param_shift_plain"] = {"gradients_per_s": 1.0 / ps_plain_s, "seconds": ps_plain_s,
+                                      "circuits": n_ps_circ,
+                                      "measured": f"extrapolated: one circuit timed ({one_circ_s * 1e3:.2f} ms) "
+                                                  f"x {n_ps_circ} circuits"}
+        extra["adjoint_speedup_vs_param_shift_tiled"] = grads_per_s * ps_s
+        extra["adjoint_speedup_vs_param_shift_plain"] = grads_per_s * ps_plain_s
+        del b_pl, ctx_pl
+
+    out = {
+        "metric": "gradients/s (adjoint vs param-shift) at 20q; circuit evals/s; HBM GB/s vs peak",
+        "value": round(grads_per_s, 3),
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded; the paper's datasets are not published)",
+        "config": {"workload": f"qcl20_L{args.layers}_S64: quantum circuit learning, 20 qubits, 64 samples, "
+                               f"RY(arcsin x) encoding + {args.layers} HEA layers ({wl.n_grad()} params), "
+                               f"<Z_0>, MSE loss, adjoint gradient, complex64 with FP64 reductions",
+                   "qubits": 20, "layers": args.layers, "samples": 64, "params": wl.n_grad(),
+                   "precision": "c64", "tile_qubits": args.tile_qubits or "auto"},
+        "roofline": roofline,
+        "circuit_evals_per_s": round(circuit_evals_per_s, 1),
+        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1)}
+                    for k, v in per.items()},
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    out.update(extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

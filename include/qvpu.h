@@ -1,0 +1,204 @@
+/*
+ * qvpu.h - C interface of the qvpu library: batched state-vector execution of parameterised quantum
+ * circuits on one AMD MI355X (gfx950), with weighted Pauli-sum expectations and gradients.
+ *
+ * The operation follows the paper's problem statement (Section 3.2 and Section 4.1): a caller submits a
+ * collection of circuits, every circuit is executed from |0...0>, and the result consolidated for each
+ * circuit is the expectation value <0|U(theta)^dagger P_t U(theta)|0> of each Pauli string P_t of an
+ * observable H = sum_t c_t P_t, plus the weighted sum E = sum_t c_t <P_t> (Eq. 1). Results are returned
+ * in the caller's circuit and term order, exactly as if the circuits had run one after another
+ * (Section 3.2). Gradients dE/dtheta are produced by the parameter-shift rule the paper uses
+ * (Section 4.1, Section 4.2) or by the adjoint method (one forward and one reverse sweep).
+ *
+ * One process drives one GPU; the whole batch is that GPU's share of the paper's array of virtual QPUs.
+ *
+ * Conventions
+ *   - qubit q is bit q of the amplitude index (qubit 0 is the least significant bit);
+ *   - RX/RY/RZ(a) = exp(-i a sigma / 2) with sigma = X/Y/Z; H, X, Y, Z, S = diag(1, i),
+ *     T = diag(1, e^{i pi/4}) as in any textbook; CNOT(control q0, target q1); CZ(q0, q1);
+ *   - a Pauli string is a pair of masks (xmask, zmask): X where only x is set, Z where only z is set,
+ *     Y where both are set; its phase convention is P|b> = i^{popcount(x&z)} (-1)^{popcount(b&z)} |b^x>;
+ *   - states are never renormalised; expectations are <psi|P|psi>.
+ *
+ * Precision
+ *   QV_C64:  complex64 amplitudes, FP32 gate arithmetic; expectation reductions, the norm and the
+ *            adjoint inner products are accumulated in FP64.
+ *   QV_C128: complex128 amplitudes, FP64 everywhere.
+ *
+ * Errors
+ *   Every function returns a qv_status. A failing call leaves every object unchanged; qv_last_error()
+ *   returns a message describing the most recent failure on the calling thread. Device faults surface
+ *   as QV_E_DEVICE at the next call that synchronises. Nothing throws across this interface.
+ *
+ * Ownership and streams
+ *   Input arrays belong to the caller and are copied during the call. Output arrays are allocated by the
+ *   caller, either in host memory or in device memory of the context's device (flag *_on_device).
+ *   All device work of a context is ordered on the context's stream (the caller's HIP stream, or a
+ *   stream the library creates when NULL is passed). Calls that write host outputs return after the
+ *   results are in place; calls that write device outputs return once the work is enqueued.
+ *   A context and its batches must be used from one thread at a time.
+ */
+#ifndef QVPU_H
+#define QVPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QV_OK = 0,
+    QV_E_INVALID = -1,     /* malformed argument (bad qubit, NULL pointer, non-finite angle, ...) */
+    QV_E_OOM = -2,         /* device memory for states would exceed what the device can hold */
+    QV_E_DEVICE = -3,      /* a HIP runtime error, with hipGetErrorString in the message */
+    QV_E_UNSUPPORTED = -4, /* valid request the library does not implement */
+    QV_E_STATE = -5        /* call out of order (e.g. gradient of a batch without parameters) */
+} qv_status;
+
+typedef enum { QV_C64 = 0, QV_C128 = 1 } qv_precision;
+
+typedef enum { QV_ADJOINT = 0, QV_PARAM_SHIFT = 1 } qv_grad_method;
+
+typedef enum {
+    QV_H = 0, QV_X = 1, QV_Y = 2, QV_Z = 3, QV_S = 4, QV_T = 5,
+    QV_RX = 6, QV_RY = 7, QV_RZ = 8, QV_CNOT = 9, QV_CZ = 10
+} qv_gate_kind;
+
+/* One gate, 24 bytes. One-qubit gates act on q0 (q1 ignored). CNOT: control q0, target q1. CZ: q0, q1.
+ * For RX/RY/RZ, param >= 0 makes the angle theta[param] of the circuit's parameter vector (trainable);
+ * param = -1 makes it the fixed value `angle`. Other kinds ignore param and angle (param must be -1). */
+typedef struct {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1;
+    int32_t param;
+    double angle;
+} qv_gate;
+
+typedef struct {
+    int64_t passes;            /* tile passes executed by the last call (forward + reverse) */
+    int64_t launches;          /* kernel launches recorded for the last call */
+    int64_t algorithmic_bytes; /* state bytes read + written by the last call's passes and reductions */
+    double kernel_ms;          /* device time of the last call, from HIP events on the context stream */
+    double norm_err_max;       /* max |<psi|psi> - 1| over the batch after the last forward call */
+} qv_stats;
+
+/* Kernels named in launch records. */
+typedef enum {
+    QV_K_INIT = 0,          /* psi = |0...0> */
+    QV_K_TILE = 1,          /* LDS tile pass, forward */
+    QV_K_TILE_ADJ = 2,      /* LDS tile pass, adjoint reverse sweep (psi and lambda) */
+    QV_K_STRIDE = 3,        /* one gate straight from global memory, forward */
+    QV_K_STRIDE_ADJ = 4,    /* one gate straight from global memory, adjoint */
+    QV_K_EXPECT = 5,        /* Pauli-string expectation partial sums */
+    QV_K_FINALIZE = 6,      /* term values and energies from partial sums */
+    QV_K_LAMBDA = 7,        /* adjoint seed lambda = w H psi */
+    QV_K_GRAD_REDUCE = 8,   /* adjoint gradient from partial sums */
+    QV_K_SHIFT_COMBINE = 9  /* parameter-shift gradient from shifted energies */
+} qv_kernel_id;
+
+/* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
+ * algorithmic state traffic of the launch: for a gate pass 2 * (state bytes) per circuit (read + write),
+ * 4 * for an adjoint pass (psi and lambda), one state read per term group for expectations. */
+typedef struct {
+    int32_t kernel;  /* qv_kernel_id */
+    int32_t level;   /* pass level within the call, -1 for other kernels */
+    int64_t bytes;
+    double ms;
+} qv_launch_rec;
+
+typedef struct qv_ctx_s *qv_ctx;
+typedef struct qv_batch_s *qv_batch;
+
+/* Creates a context on HIP device `device`. hip_stream is a hipStream_t (NULL: the library creates a
+ * stream of default priority). options_json is NULL or a flat JSON object; recognised keys:
+ *   "n-virtual-qpus" : int >= 1   how many circuits may be in flight at once (default: all); results do
+ *                                 not depend on it (the paper's option of the same name, Section 3.2);
+ *   "engine"         : "tiled" (default; LDS tile passes) or "stride" (one global-memory pass per gate);
+ *   "tile_qubits"    : int 6..14 or "auto" (default "auto": the autotuner's choice);
+ *   "launch"         : "levels" (one launch per pass level, default) or "persistent";
+ *   "graph"          : true (default) to capture each call's launches in a hipGraph and replay it;
+ *   "launch_events"  : true to time every launch with a HIP event pair (only with "graph": false);
+ *                      the records of the last call are read with qv_batch_launch_log. */
+qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_json, qv_ctx *out);
+
+/* Points the context at another hipStream_t (NULL: the library's own stream). */
+qv_status qv_ctx_set_stream(qv_ctx ctx, void *hip_stream);
+
+qv_status qv_ctx_destroy(qv_ctx ctx);
+
+/* Submits a batch of circuits and its observable (Section 3.2: a vector of circuits executed on one
+ * buffer; Section 4.1: a Hamiltonian given as a weighted sum of Pauli strings).
+ *   n_circuits          B >= 1
+ *   n_qubits[B]         1 <= n <= 34
+ *   gate_offsets[B+1]   circuit b owns gates[gate_offsets[b] .. gate_offsets[b+1]), offsets monotone, [0] = 0
+ *   n_params[B]         parameters of each circuit; every gate param must be < n_params[b]
+ *   params_shared       nonzero: all circuits read one vector theta[n_params[0]] (all n_params equal);
+ *                       zero: circuit b reads its own slice, concatenated in circuit order
+ *   term_offsets        obs_shared nonzero: [2], every circuit uses terms [term_offsets[0], term_offsets[1]);
+ *                       obs_shared zero: [B+1], circuit b uses terms [term_offsets[b], term_offsets[b+1])
+ *   xmask, zmask, coeff one entry per term; masks must be < 2^n of the circuits that use them
+ *   precision           QV_C64 or QV_C128
+ * On success *out receives the batch. Nothing is executed until qv_batch_expectations or
+ * qv_batch_gradient is called. Returns QV_E_OOM when the states (and, for gradients, one extra state
+ * per circuit) cannot fit on the device. */
+qv_status qv_batch_create(qv_ctx ctx, int32_t n_circuits, const int32_t *n_qubits, const int64_t *gate_offsets,
+                          const qv_gate *gates, const int32_t *n_params, int32_t params_shared,
+                          const int64_t *term_offsets, const uint64_t *xmask, const uint64_t *zmask,
+                          const double *coeff, int32_t obs_shared, qv_precision precision, qv_batch *out);
+
+/* Runs every check qv_batch_create performs, without a context or a device. Returns the status and sets
+ * the message qv_batch_create would set. */
+qv_status qv_validate_batch(int32_t n_circuits, const int32_t *n_qubits, const int64_t *gate_offsets,
+                            const qv_gate *gates, const int32_t *n_params, int32_t params_shared,
+                            const int64_t *term_offsets, const uint64_t *xmask, const uint64_t *zmask,
+                            const double *coeff, int32_t obs_shared, qv_precision precision);
+
+/* Sets the parameter vector: n_params[0] doubles when shared, else sum of n_params. theta is a host
+ * pointer, or a device pointer when theta_on_device is nonzero. Host values are checked to be finite. */
+qv_status qv_batch_set_params(qv_batch batch, const double *theta, int32_t theta_on_device);
+
+/* Executes every circuit from |0...0> and writes energies[B] (E_b = sum_t c_t <P_t>) and, when
+ * term_values is not NULL, the expectation of every term in term order: for a shared observable
+ * B*T values, circuit-major; otherwise sum_b T_b values in the order of the term arrays.
+ * The final states stay on the device for a following adjoint gradient. */
+qv_status qv_batch_expectations(qv_batch batch, double *energies, double *term_values, int32_t out_on_device);
+
+/* Gradient of L = sum_b w_b E_b with w = upstream[B] (NULL: all ones). grad receives n_params[0] values
+ * when parameters are shared (summed over circuits), else sum n_params values (circuit b's own slice).
+ * QV_ADJOINT runs the forward pass, seeds lambda_b = w_b H psi_b and sweeps the gates backwards,
+ * accumulating Im <lambda|G_k|psi> for every trainable gate exp(-i a G_k / 2) in FP64.
+ * QV_PARAM_SHIFT evaluates, for every trainable gate occurrence, the circuit with that angle moved by
+ * +pi/2 and -pi/2 and adds w_b (E+ - E-)/2 (the rule the paper applies in Section 4.1 and 4.2); a
+ * parameter that drives several gates receives the sum over its gates. When energies is not NULL the
+ * forward energies are written too. upstream, grad and energies are device pointers when on_device. */
+qv_status qv_batch_gradient(qv_batch batch, qv_grad_method method, const double *upstream, double *grad,
+                            double *energies, int32_t on_device);
+
+/* Copies the final state of circuit b after the last forward pass: 2^n complex numbers, interleaved
+ * (re, im), float for QV_C64 and double for QV_C128. */
+qv_status qv_batch_state(qv_batch batch, int32_t circuit, void *out, int32_t out_on_device);
+
+qv_status qv_batch_stats(qv_batch batch, qv_stats *out);
+
+/* Launch records of the qv_batch_expectations / qv_batch_gradient calls made since the records were
+ * last read, for a context created with "launch_events": true and "graph": false. Writes the number of
+ * pending records to *n_records and at most max_records of them to out (waiting for their work to
+ * finish); when every pending record fits in out they are consumed, otherwise they stay pending (call
+ * with max_records = 0 to query the count). */
+qv_status qv_batch_launch_log(qv_batch batch, qv_launch_rec *out, int32_t max_records, int32_t *n_records);
+
+qv_status qv_batch_destroy(qv_batch batch);
+
+/* Message of the last failure on the calling thread ("" if none); valid until the next call. */
+const char *qv_last_error(void);
+
+/* Library version string. */
+const char *qv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QVPU_H */

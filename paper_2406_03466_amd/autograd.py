@@ -1,0 +1,36 @@
+"""torch.autograd.Function over a qvpu batch: forward returns the energies E_b(theta) of every circuit,
+backward returns dL/dtheta from one adjoint reverse sweep (qv_batch_gradient with QV_ADJOINT) seeded
+with the upstream gradient dL/dE_b. Tensors stay on the device; torch's current stream orders the work."""
+from __future__ import annotations
+
+import torch
+
+from . import qvpu
+
+
+class ExpectationFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, batch: "qvpu.Batch"):
+        if theta.dtype != torch.float64 or not theta.is_cuda:
+            raise TypeError("theta must be a float64 tensor on the batch's device")
+        th = theta.detach().contiguous()
+        batch.ctx.set_stream(torch.cuda.current_stream(theta.device).cuda_stream)
+        batch.set_params(th)
+        energies = torch.empty(batch.B, dtype=torch.float64, device=theta.device)
+        batch.expectations(energies, None)
+        ctx.batch = batch
+        ctx.n_theta = th.numel()
+        return energies
+
+    @staticmethod
+    def backward(ctx, grad_energies: torch.Tensor):
+        batch = ctx.batch
+        up = grad_energies.detach().to(torch.float64).contiguous()
+        grad = torch.empty(batch.n_grad, dtype=torch.float64, device=up.device)
+        batch.ctx.set_stream(torch.cuda.current_stream(up.device).cuda_stream)
+        batch.gradient(qvpu.QV_ADJOINT, upstream=up, grad=grad)
+        return grad, None
+
+
+def expectation(theta: torch.Tensor, batch: "qvpu.Batch") -> torch.Tensor:
+    return ExpectationFn.apply(theta, batch)

@@ -1,0 +1,180 @@
+// Device-side data layout shared by the host planner (qvpu_api.cpp) and the HIP kernels (kernels.hip).
+//
+// A batch holds B circuits. Each circuit's state is a contiguous array of 2^n interleaved (re, im)
+// amplitudes inside one pool, qubit q being bit q of the index. Circuits that share a gate structure
+// share one plan: a list of passes. A pass gathers a tile of 2^t amplitudes (the t "local" qubits vary,
+// the other n - t qubits are fixed per tile) into LDS, applies a run of gates whose qubits are all local,
+// and writes the tile back. All passes at the same position of their circuits' plans form a level;
+// one kernel launch runs a level for every circuit.
+#pragma once
+#include <stdint.h>
+
+#include "qvpu.h"
+
+namespace qv {
+
+constexpr int kMaxTileQubits = 14;   // 2^14 complex64 = 128 KiB of LDS
+constexpr int kBlock = 256;          // threads per workgroup for every kernel
+constexpr int kMaxGroupTerms = 8;    // Pauli terms evaluated together by one expectation item
+constexpr int kExpChunkLog2 = 12;    // amplitude pairs per expectation workgroup (4096)
+constexpr int kStrideGroupsPerBlock = 1024;
+
+enum OpFlags : uint8_t { OP_TRAIN = 1 };
+
+// One gate inside a pass, with its qubits translated to tile-local bit positions.
+struct DevOp {
+    int32_t gate;        // gate index within its circuit (angle and parameter are read per circuit)
+    uint8_t kind;        // qv_gate_kind
+    uint8_t p0, p1;      // local positions of q0 / q1
+    uint8_t flags;       // OP_TRAIN when the gate's angle is a trainable parameter
+    int32_t train_slot;  // position among the pass's trainable gates (adjoint partial sums), else -1
+    int32_t pad;
+};
+static_assert(sizeof(DevOp) == 16, "DevOp layout");
+
+struct DevPass {
+    uint64_t local_mask;  // qubits of the tile
+    int32_t t;            // number of local qubits
+    int32_t op_begin;     // into the op array
+    int32_t n_ops;
+    int32_t n_train;      // trainable ops in the pass
+    int32_t stride;       // 1: stride pass (one gate straight from global memory), 0: LDS tile pass
+    int32_t pad;
+    int8_t lq[16];        // local position -> qubit, ascending
+};
+
+struct DevCirc {
+    int64_t state_off;    // amplitude offset of this circuit's state in the pool
+    int64_t gate_off;     // offset of its gate records
+    int64_t param_base;   // offset of its parameters in theta
+    int32_t n;            // qubits
+    int32_t shift_gate;   // parameter-shift variant: index of the gate whose angle is moved, -1 none
+    double shift;         // the move (+pi/2 or -pi/2)
+    int32_t base_circ;    // the batch circuit this entry evaluates (variants point at their base)
+    int32_t pad;
+};
+
+// One (circuit, pass) of a level launch; blocks [first_block, next segment's first_block) run it.
+struct Seg {
+    int64_t first_block;
+    int64_t partial_base; // adjoint: base slot of this (circuit, pass) in the partial-sum array
+    int32_t circ;
+    int32_t pass;
+};
+
+// Expectation work: one Pauli x-mask group of one circuit. Blocks [first_block, ...) cover its chunks.
+struct DevGroup {
+    uint64_t xmask;
+    int64_t first_block;
+    int64_t partial_base; // partials[partial_base + chunk * n_terms + j]
+    int32_t circ;
+    int32_t n_terms;
+    int32_t term_begin;   // into DevTerm array
+    int32_t chunk_log2;   // pairs (or amplitudes when xmask == 0) per block
+};
+
+struct DevTerm {
+    uint64_t zmask;
+    int32_t ny;           // popcount(x & z) mod 4
+    int32_t pad;
+};
+
+// Where the partial sums of one output value live: sum over c < count of partials[base + c * stride].
+struct PartialRef {
+    int64_t base;
+    int32_t count;
+    int32_t stride;
+};
+
+// Term of an observable, as used to seed the adjoint vector lambda = w H psi.
+struct DevObsTerm {
+    uint64_t xmask, zmask;
+    double coeff;
+    int32_t ny;
+    int32_t pad;
+};
+
+// Launch parameters for one level of tile passes.
+struct LevelArgs {
+    const Seg *segs;
+    int32_t n_segs;
+    int32_t lds_t;        // largest tile of the level (LDS sizing)
+    int64_t n_blocks;
+    const DevPass *passes;
+    const DevOp *ops;
+    const DevCirc *circs;
+    const qv_gate *gates;
+    const double *theta;
+    void *psi;
+    void *lam;
+    double *partials;
+};
+
+struct ExpArgs {
+    const DevGroup *groups;
+    int32_t n_groups;
+    int64_t n_blocks;
+    const DevTerm *terms;
+    const DevCirc *circs;
+    const void *psi;
+    double *partials;
+};
+
+struct FinalizeArgs {
+    int32_t n_circ;
+    const int64_t *tv_begin;     // [n_circ + 1] output term ranges
+    const PartialRef *term_refs; // per output term
+    const double *coeff;         // per output term
+    const PartialRef *norm_refs; // per circuit
+    const double *partials;      // expectation partial sums
+    double *term_values;         // out
+    double *energies;            // out
+    double *norms;               // out (may be NULL)
+};
+
+struct LambdaArgs {
+    const DevCirc *circs;
+    int32_t n_circ;
+    const int64_t *first_block;  // [n_circ + 1] block prefix (4096 amplitudes per block)
+    const int64_t *obs_begin;    // [n_circ + 1] ranges into obs
+    const DevObsTerm *obs;
+    const double *upstream;      // [B] or NULL (weights 1)
+    const void *psi;
+    void *lam;
+    int64_t n_blocks;
+};
+
+struct GradReduceArgs {
+    int32_t n_out;
+    const int64_t *ref_begin;    // [n_out + 1]
+    const PartialRef *refs;
+    const double *partials;
+    double *grad;
+};
+
+// Parameter-shift combination: grad[g] = sum over its occurrences of w_b (E+ - E-) / 2.
+struct ShiftCombineArgs {
+    int32_t n_out;
+    const int64_t *occ_begin;    // [n_out + 1]
+    const int32_t *occ_plus;     // variant index of E+
+    const int32_t *occ_minus;    // variant index of E-
+    const int32_t *occ_circ;     // batch circuit of the occurrence (for the upstream weight)
+    const double *energies;      // variant energies
+    const double *upstream;      // [B] or NULL
+    double *grad;
+};
+
+// Launchers (kernels.hip). All return hipSuccess or the launch error.
+int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream);
+int launch_stride_level(const LevelArgs &a, int precision, int adjoint, void *stream);
+int launch_init_states(void *psi, const DevCirc *circs, const int64_t *first_block, int32_t n_circ,
+                       int64_t n_blocks, int precision, void *stream);
+int launch_expectation(const ExpArgs &a, int precision, void *stream);
+int launch_finalize(const FinalizeArgs &a, void *stream);
+int launch_lambda(const LambdaArgs &a, int precision, void *stream);
+int launch_grad_reduce(const GradReduceArgs &a, void *stream);
+int launch_shift_combine(const ShiftCombineArgs &a, void *stream);
+int launch_fill(double *p, int64_t n, double v, void *stream);
+int prepare_kernels();  // raises the dynamic-LDS limits; call once per device
+
+}  // namespace qv

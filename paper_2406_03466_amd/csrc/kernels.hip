@@ -1,0 +1,644 @@
+// HIP kernels for gfx950 (MI355X): gate passes over batches of state vectors, Pauli-string expectation
+// reductions in FP64, the adjoint seed lambda = w H psi, and the deterministic reductions behind
+// gradients.
+//
+// What the kernels compute (the paper's Eq. 1 evaluated directly, Section 4.1):
+//   * a one-qubit gate U on qubit q maps every amplitude pair (i, i | 2^q) with bit q of i clear to
+//     (u00 a + u01 b, u10 a + u11 b); CNOT swaps the pair where the control bit is set; CZ negates
+//     amplitudes where both bits are set;
+//   * <P> for P = (x, z) is sum_b conj(psi[b ^ x]) i^{ny} (-1)^{popcount(b & z)} psi[b], taken over
+//     pairs {b, b ^ x} as 2 Re[...] when x != 0;
+//   * the adjoint sweep (Jones and Gacon 2020) un-applies gates from psi and lambda and adds
+//     Im <lambda| G |psi> for every trainable gate exp(-i a G / 2).
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+
+namespace qv {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) Cx {
+    R re, im;
+};
+
+struct M2d {  // 2x2 complex matrix in double: m[row*2+col]
+    double re[4], im[4];
+};
+
+__device__ __forceinline__ uint32_t insert0(uint32_t x, int p)
+{
+    return ((x >> p) << (p + 1)) | (x & ((1u << p) - 1u));
+}
+
+__device__ __forceinline__ uint64_t insert0_64(uint64_t x, int p)
+{
+    return ((x >> p) << (p + 1)) | (x & ((1ull << p) - 1ull));
+}
+
+// Scatters the low bits of v into the set bits of mask (lowest first).
+__device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask)
+{
+    uint64_t r = 0;
+    while (mask) {
+        uint64_t low = mask & (~mask + 1);
+        if (v & 1) r |= low;
+        v >>= 1;
+        mask &= mask - 1;
+    }
+    return r;
+}
+
+__device__ __forceinline__ int parity64(uint64_t v) { return __popcll(v) & 1; }
+
+// Matrix of a one-qubit gate (textbook definitions; rotations are exp(-i a sigma / 2)).
+__device__ inline void gate_matrix(int kind, double a, M2d &m)
+{
+    for (int k = 0; k < 4; k++) { m.re[k] = 0.0; m.im[k] = 0.0; }
+    double s, c;
+    sincos(0.5 * a, &s, &c);
+    const double r = 0.70710678118654752440;
+    switch (kind) {
+    case QV_H: m.re[0] = r; m.re[1] = r; m.re[2] = r; m.re[3] = -r; break;
+    case QV_X: m.re[1] = 1; m.re[2] = 1; break;
+    case QV_Y: m.im[1] = -1; m.im[2] = 1; break;
+    case QV_Z: m.re[0] = 1; m.re[3] = -1; break;
+    case QV_S: m.re[0] = 1; m.im[3] = 1; break;
+    case QV_T: m.re[0] = 1; m.re[3] = r; m.im[3] = r; break;
+    case QV_RX: m.re[0] = c; m.im[1] = -s; m.im[2] = -s; m.re[3] = c; break;
+    case QV_RY: m.re[0] = c; m.re[1] = -s; m.re[2] = s; m.re[3] = c; break;
+    case QV_RZ: m.re[0] = c; m.im[0] = -s; m.re[3] = c; m.im[3] = s; break;
+    default: m.re[0] = 1; m.re[3] = 1; break;
+    }
+}
+
+// Conjugate transpose in place.
+__device__ inline void dagger(M2d &m)
+{
+    double r1 = m.re[1], i1 = m.im[1];
+    m.re[1] = m.re[2]; m.im[1] = -m.im[2];
+    m.re[2] = r1; m.im[2] = -i1;
+    m.im[0] = -m.im[0];
+    m.im[3] = -m.im[3];
+}
+
+template <typename R>
+struct M2 {
+    R re[4], im[4];
+};
+
+template <typename R>
+__device__ __forceinline__ M2<R> narrow(const M2d &m)
+{
+    M2<R> o;
+    for (int k = 0; k < 4; k++) { o.re[k] = (R)m.re[k]; o.im[k] = (R)m.im[k]; }
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ void apply2(const M2<R> &m, Cx<R> &a, Cx<R> &b)
+{
+    Cx<R> x = a, y = b;
+    a.re = m.re[0] * x.re - m.im[0] * x.im + m.re[1] * y.re - m.im[1] * y.im;
+    a.im = m.re[0] * x.im + m.im[0] * x.re + m.re[1] * y.im + m.im[1] * y.re;
+    b.re = m.re[2] * x.re - m.im[2] * x.im + m.re[3] * y.re - m.im[3] * y.im;
+    b.im = m.re[2] * x.im + m.im[2] * x.re + m.re[3] * y.im + m.im[3] * y.re;
+}
+
+// Im <lambda| G |psi> restricted to one amplitude pair (a0, a1) of psi and (l0, l1) of lambda, where G is
+// the generator (X, Y or Z) of a rotation on the pair's qubit. FP64.
+template <typename R>
+__device__ __forceinline__ double gen_inner(int kind, Cx<R> a0, Cx<R> a1, Cx<R> l0, Cx<R> l1)
+{
+    const double a0r = a0.re, a0i = a0.im, a1r = a1.re, a1i = a1.im;
+    const double l0r = l0.re, l0i = l0.im, l1r = l1.re, l1i = l1.im;
+    if (kind == QV_RX)
+        return (l0r * a1i - l0i * a1r) + (l1r * a0i - l1i * a0r);
+    if (kind == QV_RY)
+        return -(l0r * a1r + l0i * a1i) + (l1r * a0r + l1i * a0i);
+    return (l0r * a0i - l0i * a0r) - (l1r * a1i - l1i * a1r);
+}
+
+// Sum over the workgroup (kBlock threads); the result is valid in thread 0. red holds kBlock/64 doubles.
+__device__ inline double block_sum(double v, double *red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; w++) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ int find_block(const T *arr, int n, int64_t blk)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (arr[mid].first_block <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int find_prefix(const int64_t *pre, int n, int64_t blk)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double op_angle(const LevelArgs &a, const DevCirc &C, const DevOp &op, int &kind)
+{
+    const qv_gate g = a.gates[C.gate_off + op.gate];
+    kind = g.kind;
+    double ang = g.param >= 0 ? a.theta[C.param_base + g.param] : g.angle;
+    if (op.gate == C.shift_gate) ang += C.shift;
+    return ang;
+}
+
+// ------------------------------------------------------------------------------------------------------
+// LDS tile pass. One workgroup owns one tile: the 2^t amplitudes whose non-local bits equal the tile's
+// index. The lowest `lowc` local qubits are qubits 0..lowc-1, so each run of 2^lowc amplitudes is
+// contiguous in HBM and the gather/scatter is coalesced.
+// ------------------------------------------------------------------------------------------------------
+template <typename R, bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
+    const int64_t tile = blk - sg.first_block;
+    const DevPass P = a.passes[sg.pass];
+    const DevCirc C = a.circs[sg.circ];
+    const int n = C.n, t = P.t, lowc = P.pad;
+    const uint32_t T = 1u << t;
+    const int TL = 1 << (a.lds_t);
+
+    Cx<R> *sp = reinterpret_cast<Cx<R> *>(smem);
+    Cx<R> *sl = sp + (ADJ ? TL : 0);
+    uint64_t *segtab = reinterpret_cast<uint64_t *>(sp + (ADJ ? 2 * TL : TL));
+    const int tab_bits = a.lds_t > 3 ? a.lds_t - 3 : 0;
+    double *red = reinterpret_cast<double *>(segtab + (1 << tab_bits));
+
+    const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    const uint64_t base = deposit((uint64_t)tile, full & ~P.local_mask);
+    const uint64_t himask = P.local_mask & ~((1ull << lowc) - 1ull);
+    const uint32_t nh = 1u << (t - lowc);
+    for (uint32_t h = threadIdx.x; h < nh; h += kBlock) segtab[h] = deposit(h, himask);
+    __syncthreads();
+
+    Cx<R> *gpsi = reinterpret_cast<Cx<R> *>(a.psi) + C.state_off;
+    Cx<R> *glam = ADJ ? reinterpret_cast<Cx<R> *>(a.lam) + C.state_off : nullptr;
+    const uint32_t lmask = (1u << lowc) - 1u;
+    for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+        const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+        sp[e] = gpsi[g];
+        if (ADJ) sl[e] = glam[g];
+    }
+    __syncthreads();
+
+    for (int k0 = 0; k0 < P.n_ops; k0++) {
+        const int k = ADJ ? P.n_ops - 1 - k0 : k0;
+        const DevOp op = a.ops[P.op_begin + k];
+        int kind;
+        const double ang = op_angle(a, C, op, kind);
+        if (kind == QV_CNOT || kind == QV_CZ) {
+            const uint32_t bc = 1u << op.p0, bt = 1u << op.p1;
+            const int plo = op.p0 < op.p1 ? op.p0 : op.p1, phi = op.p0 < op.p1 ? op.p1 : op.p0;
+            for (uint32_t i = threadIdx.x; i < (T >> 2); i += kBlock) {
+                const uint32_t i00 = insert0(insert0(i, plo), phi);
+                if (kind == QV_CNOT) {
+                    const uint32_t i10 = i00 | bc, i11 = i00 | bc | bt;
+                    Cx<R> x = sp[i10]; sp[i10] = sp[i11]; sp[i11] = x;
+                    if (ADJ) { Cx<R> y = sl[i10]; sl[i10] = sl[i11]; sl[i11] = y; }
+                } else {
+                    const uint32_t i11 = i00 | bc | bt;
+                    sp[i11].re = -sp[i11].re; sp[i11].im = -sp[i11].im;
+                    if (ADJ) { sl[i11].re = -sl[i11].re; sl[i11].im = -sl[i11].im; }
+                }
+            }
+        } else {
+            const int p = op.p0;
+            const uint32_t bit = 1u << p;
+            if (ADJ && (op.flags & OP_TRAIN)) {
+                double acc = 0.0;
+                for (uint32_t i = threadIdx.x; i < (T >> 1); i += kBlock) {
+                    const uint32_t i0 = insert0(i, p), i1 = i0 | bit;
+                    acc += gen_inner<R>(kind, sp[i0], sp[i1], sl[i0], sl[i1]);
+                }
+                const double s = block_sum(acc, red);
+                if (threadIdx.x == 0) a.partials[sg.partial_base + tile * P.n_train + op.train_slot] = s;
+            }
+            M2d md;
+            gate_matrix(kind, ang, md);
+            if (ADJ) dagger(md);
+            const M2<R> m = narrow<R>(md);
+            for (uint32_t i = threadIdx.x; i < (T >> 1); i += kBlock) {
+                const uint32_t i0 = insert0(i, p), i1 = i0 | bit;
+                Cx<R> x = sp[i0], y = sp[i1];
+                apply2(m, x, y);
+                sp[i0] = x; sp[i1] = y;
+                if (ADJ) {
+                    Cx<R> u = sl[i0], v = sl[i1];
+                    apply2(m, u, v);
+                    sl[i0] = u; sl[i1] = v;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+        const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+        gpsi[g] = sp[e];
+        if (ADJ) glam[g] = sl[e];
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Stride pass: one gate straight from global memory. Each block handles kStrideGroupsPerBlock amplitude
+// pairs (one-qubit gates) or quads (two-qubit gates); op.p0/op.p1 hold the gate's qubits.
+// ------------------------------------------------------------------------------------------------------
+template <typename R, bool ADJ>
+__global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
+    const int64_t chunk = blk - sg.first_block;
+    const DevPass P = a.passes[sg.pass];
+    const DevCirc C = a.circs[sg.circ];
+    const int n = C.n;
+    const DevOp op = a.ops[P.op_begin];
+    int kind;
+    const double ang = op_angle(a, C, op, kind);
+    Cx<R> *gpsi = reinterpret_cast<Cx<R> *>(a.psi) + C.state_off;
+    Cx<R> *glam = ADJ ? reinterpret_cast<Cx<R> *>(a.lam) + C.state_off : nullptr;
+    const uint64_t g0 = (uint64_t)chunk * kStrideGroupsPerBlock;
+    if (kind == QV_CNOT || kind == QV_CZ) {
+        const uint64_t ngroups = 1ull << (n - 2);
+        const uint64_t bc = 1ull << op.p0, bt = 1ull << op.p1;
+        const int plo = op.p0 < op.p1 ? op.p0 : op.p1, phi = op.p0 < op.p1 ? op.p1 : op.p0;
+        for (uint32_t e = threadIdx.x; e < kStrideGroupsPerBlock; e += kBlock) {
+            const uint64_t gi = g0 + e;
+            if (gi >= ngroups) break;
+            const uint64_t i00 = insert0_64(insert0_64(gi, plo), phi);
+            if (kind == QV_CNOT) {
+                const uint64_t i10 = i00 | bc, i11 = i00 | bc | bt;
+                Cx<R> x = gpsi[i10], y = gpsi[i11];
+                gpsi[i10] = y; gpsi[i11] = x;
+                if (ADJ) { Cx<R> u = glam[i10], v = glam[i11]; glam[i10] = v; glam[i11] = u; }
+            } else {
+                const uint64_t i11 = i00 | bc | bt;
+                Cx<R> x = gpsi[i11]; x.re = -x.re; x.im = -x.im; gpsi[i11] = x;
+                if (ADJ) { Cx<R> u = glam[i11]; u.re = -u.re; u.im = -u.im; glam[i11] = u; }
+            }
+        }
+        return;
+    }
+    const uint64_t ngroups = 1ull << (n - 1);
+    const int p = op.p0;
+    const uint64_t bit = 1ull << p;
+    M2d md;
+    gate_matrix(kind, ang, md);
+    if (ADJ) dagger(md);
+    const M2<R> m = narrow<R>(md);
+    double acc = 0.0;
+    for (uint32_t e = threadIdx.x; e < kStrideGroupsPerBlock; e += kBlock) {
+        const uint64_t gi = g0 + e;
+        if (gi >= ngroups) break;
+        const uint64_t i0 = insert0_64(gi, p), i1 = i0 | bit;
+        Cx<R> x = gpsi[i0], y = gpsi[i1];
+        if (ADJ) {
+            Cx<R> u = glam[i0], v = glam[i1];
+            if (op.flags & OP_TRAIN) acc += gen_inner<R>(kind, x, y, u, v);
+            apply2(m, u, v);
+            glam[i0] = u; glam[i1] = v;
+        }
+        apply2(m, x, y);
+        gpsi[i0] = x; gpsi[i1] = y;
+    }
+    if (ADJ && (op.flags & OP_TRAIN)) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) a.partials[sg.partial_base + chunk * P.n_train + op.train_slot] = s;
+    }
+}
+
+// psi_b = |0...0> for every circuit; blocks cover 4096 amplitudes each.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_init(Cx<R> *psi, const DevCirc *circs, const int64_t *first_block,
+                                                 int32_t n_circ)
+{
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(first_block, n_circ, blk);
+    const DevCirc C = circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t e0 = (uint64_t)(blk - first_block[c]) * 4096ull;
+    Cx<R> *st = psi + C.state_off;
+    for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
+        const uint64_t i = e0 + e;
+        if (i >= dim) break;
+        Cx<R> v;
+        v.re = (i == 0) ? (R)1 : (R)0;
+        v.im = (R)0;
+        st[i] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Pauli expectations. A block handles 2^chunk_log2 pairs {b, b ^ x} (or amplitudes when x == 0) of one
+// x-mask group and writes one FP64 partial sum per term of the group.
+// ------------------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const DevGroup G = a.groups[find_block(a.groups, a.n_groups, blk)];
+    const int64_t chunk = blk - G.first_block;
+    const DevCirc C = a.circs[G.circ];
+    const Cx<R> *st = reinterpret_cast<const Cx<R> *>(a.psi) + C.state_off;
+    const int nt = G.n_terms;
+    uint64_t z[kMaxGroupTerms];
+    int ny[kMaxGroupTerms];
+    double acc[kMaxGroupTerms];
+#pragma unroll
+    for (int j = 0; j < kMaxGroupTerms; j++) {
+        z[j] = j < nt ? a.terms[G.term_begin + j].zmask : 0;
+        ny[j] = j < nt ? a.terms[G.term_begin + j].ny : 0;
+        acc[j] = 0.0;
+    }
+    const uint64_t x = G.xmask;
+    const uint32_t per = 1u << G.chunk_log2;
+    const uint64_t i0 = (uint64_t)chunk << G.chunk_log2;
+    if (x == 0) {
+        const uint64_t dim = 1ull << C.n;
+        for (uint32_t e = threadIdx.x; e < per; e += kBlock) {
+            const uint64_t b = i0 + e;
+            if (b >= dim) break;
+            const Cx<R> v = st[b];
+            const double w = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+#pragma unroll
+            for (int j = 0; j < kMaxGroupTerms; j++)
+                if (j < nt) acc[j] += parity64(b & z[j]) ? -w : w;
+        }
+    } else {
+        const int h = 63 - __clzll(x);
+        const uint64_t npairs = 1ull << (C.n - 1);
+        for (uint32_t e = threadIdx.x; e < per; e += kBlock) {
+            const uint64_t i = i0 + e;
+            if (i >= npairs) break;
+            const uint64_t b = insert0_64(i, h);
+            const Cx<R> a0 = st[b], a1 = st[b ^ x];
+            // w = conj(psi[b ^ x]) psi[b]
+            const double wr = (double)a1.re * (double)a0.re + (double)a1.im * (double)a0.im;
+            const double wi = (double)a1.re * (double)a0.im - (double)a1.im * (double)a0.re;
+#pragma unroll
+            for (int j = 0; j < kMaxGroupTerms; j++) {
+                if (j < nt) {
+                    const int q = ny[j];
+                    double re = (q == 0) ? wr : (q == 1) ? -wi : (q == 2) ? -wr : wi;
+                    re *= 2.0;
+                    acc[j] += parity64(b & z[j]) ? -re : re;
+                }
+            }
+        }
+    }
+    for (int j = 0; j < nt; j++) {
+        const double s = block_sum(acc[j], red);
+        if (threadIdx.x == 0) a.partials[G.partial_base + chunk * nt + j] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a)
+{
+    const double *partials = a.partials;
+    const int b = blockIdx.x;
+    const int64_t t0 = a.tv_begin[b], t1 = a.tv_begin[b + 1];
+    for (int64_t o = t0 + threadIdx.x; o < t1; o += kBlock) {
+        const PartialRef r = a.term_refs[o];
+        double s = 0.0;
+        for (int32_t c = 0; c < r.count; c++) s += partials[r.base + (int64_t)c * r.stride];
+        a.term_values[o] = s;
+    }
+    if (threadIdx.x == 0 && a.norm_refs && a.norms) {
+        const PartialRef r = a.norm_refs[b];
+        double s = 0.0;
+        for (int32_t c = 0; c < r.count; c++) s += partials[r.base + (int64_t)c * r.stride];
+        a.norms[b] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int64_t o = t0; o < t1; o++) e += a.coeff[o] * a.term_values[o];
+        a.energies[b] = e;
+    }
+}
+
+// lambda_b[o] = w_b sum_t c_t (P_t psi_b)[o], (P psi)[o] = i^{ny} (-1)^{popcount((o^x) & z)} psi[o ^ x].
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
+{
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * 4096ull;
+    const Cx<R> *st = reinterpret_cast<const Cx<R> *>(a.psi) + C.state_off;
+    Cx<R> *lam = reinterpret_cast<Cx<R> *>(a.lam) + C.state_off;
+    const double w = a.upstream ? a.upstream[C.base_circ] : 1.0;
+    const int64_t tb = a.obs_begin[c], te = a.obs_begin[c + 1];
+    for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
+        const uint64_t o = o0 + e;
+        if (o >= dim) break;
+        double sr = 0.0, si = 0.0;
+        for (int64_t t = tb; t < te; t++) {
+            const DevObsTerm term = a.obs[t];
+            const uint64_t b = o ^ term.xmask;
+            const Cx<R> v = st[b];
+            double vr = v.re, vi = v.im, pr, pi;
+            switch (term.ny) {
+            case 0: pr = vr; pi = vi; break;
+            case 1: pr = -vi; pi = vr; break;
+            case 2: pr = -vr; pi = -vi; break;
+            default: pr = vi; pi = -vr; break;
+            }
+            const double cf = parity64(b & term.zmask) ? -term.coeff : term.coeff;
+            sr += cf * pr;
+            si += cf * pi;
+        }
+        Cx<R> out;
+        out.re = (R)(w * sr);
+        out.im = (R)(w * si);
+        lam[o] = out;
+    }
+}
+
+// grad[g] = sum over refs of g of sum_c partials[base + c * stride], one block per output.
+__global__ __launch_bounds__(kBlock) void k_grad_reduce(GradReduceArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int g = blockIdx.x;
+    double s = 0.0;
+    for (int64_t r = a.ref_begin[g]; r < a.ref_begin[g + 1]; r++) {
+        const PartialRef ref = a.refs[r];
+        for (int32_t c = threadIdx.x; c < ref.count; c += kBlock) s += a.partials[ref.base + (int64_t)c * ref.stride];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) a.grad[g] = s;
+}
+
+__global__ void k_shift_combine(ShiftCombineArgs a)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n_out) return;
+    double s = 0.0;
+    for (int64_t k = a.occ_begin[g]; k < a.occ_begin[g + 1]; k++) {
+        const double w = a.upstream ? a.upstream[a.occ_circ[k]] : 1.0;
+        s += w * 0.5 * (a.energies[a.occ_plus[k]] - a.energies[a.occ_minus[k]]);
+    }
+    a.grad[g] = s;
+}
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------------------
+static size_t tile_lds_bytes(int lds_t, int amp_bytes, int adjoint)
+{
+    const int tab_bits = lds_t > 3 ? lds_t - 3 : 0;
+    return (size_t)(adjoint ? 2 : 1) * ((size_t)1 << lds_t) * amp_bytes + ((size_t)8 << tab_bits) +
+           sizeof(double) * (kBlock / 64);
+}
+
+int prepare_kernels()
+{
+    const int lim = 160 * 1024;
+    hipError_t e = hipSuccess;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<float, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<float, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<double, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<double, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    return e;
+}
+
+int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int amp = precision == QV_C64 ? 8 : 16;
+    const size_t lds = tile_lds_bytes(a.lds_t, amp, adjoint);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    dim3 grid((unsigned)a.n_blocks), block(kBlock);
+    if (precision == QV_C64) {
+        if (adjoint) hipLaunchKernelGGL((k_tile<float, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_tile<float, false>), grid, block, lds, s, a);
+    } else {
+        if (adjoint) hipLaunchKernelGGL((k_tile<double, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_tile<double, false>), grid, block, lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+int launch_stride_level(const LevelArgs &a, int precision, int adjoint, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    dim3 grid((unsigned)a.n_blocks), block(kBlock);
+    if (precision == QV_C64) {
+        if (adjoint) hipLaunchKernelGGL((k_stride<float, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_stride<float, false>), grid, block, 0, s, a);
+    } else {
+        if (adjoint) hipLaunchKernelGGL((k_stride<double, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_stride<double, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+int launch_init_states(void *psi, const DevCirc *circs, const int64_t *first_block, int32_t n_circ,
+                       int64_t n_blocks, int precision, void *stream)
+{
+    if (n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision == QV_C64)
+        hipLaunchKernelGGL((k_init<float>), dim3((unsigned)n_blocks), dim3(kBlock), 0, s,
+                           reinterpret_cast<Cx<float> *>(psi), circs, first_block, n_circ);
+    else
+        hipLaunchKernelGGL((k_init<double>), dim3((unsigned)n_blocks), dim3(kBlock), 0, s,
+                           reinterpret_cast<Cx<double> *>(psi), circs, first_block, n_circ);
+    return hipGetLastError();
+}
+
+int launch_expectation(const ExpArgs &a, int precision, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision == QV_C64)
+        hipLaunchKernelGGL((k_expect<float>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_expect<double>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_finalize(const FinalizeArgs &a, void *stream)
+{
+    if (a.n_circ <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.n_circ), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_lambda(const LambdaArgs &a, int precision, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision == QV_C64)
+        hipLaunchKernelGGL((k_lambda<float>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_lambda<double>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_grad_reduce(const GradReduceArgs &a, void *stream)
+{
+    if (a.n_out <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)a.n_out), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_shift_combine(const ShiftCombineArgs &a, void *stream)
+{
+    if (a.n_out <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_shift_combine, dim3((unsigned)((a.n_out + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_fill(double *p, int64_t n, double v, void *stream)
+{
+    if (n <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace qv

@@ -1,0 +1,47 @@
+// Pass planner: turns a circuit's gate list into passes (see engine.h). Host only.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "engine.h"
+
+namespace qv {
+
+struct PlanInput {
+    int n = 0;
+    std::vector<int> kinds, q0, q1;   // q1 = -1 for one-qubit gates
+    std::vector<bool> trainable;
+};
+
+struct PlanOp {
+    int gate;        // index in the circuit
+    int kind;
+    int q0, q1;      // qubits (global)
+    int train_slot;  // position among the pass's trainable gates, -1 if fixed
+};
+
+struct PlanPass {
+    uint64_t local_mask = 0;
+    int t = 0;
+    int lowc = 0;     // local qubits 0..lowc-1 are qubits 0..lowc-1 (contiguous runs in memory)
+    int stride = 0;   // 1: a single gate applied straight from global memory
+    int n_train = 0;
+    std::vector<int> lq;      // local position -> qubit (ascending)
+    std::vector<PlanOp> ops;  // in program order
+};
+
+struct Plan {
+    std::vector<PlanPass> passes;
+};
+
+// LDS tile plan with tiles of at most `tile_qubits` qubits, the lowest `lowc` qubits always local.
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc);
+
+// One stride pass per gate.
+Plan plan_stride(const PlanInput &in);
+
+// Appends a plan's passes and ops in device form.
+void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops);
+
+}  // namespace qv

@@ -1,0 +1,1250 @@
+// Host side of the qvpu C interface: validation, pass planning, device layout of a batch, hipGraph
+// capture and replay. Every arithmetic step of the path runs in the HIP kernels of kernels.hip; this
+// file only decides what to launch and in which order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "engine.h"
+#include "planner.h"
+#include "qvpu.h"
+
+using namespace qv;
+
+// ---------------------------------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static qv_status fail(qv_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+static qv_status ok()
+{
+    g_err.clear();
+    return QV_OK;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (hipError_t)(expr);                                                            \
+        if (e_ != hipSuccess) return fail(QV_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------------------------
+// Options: a flat JSON object with string, number and boolean values.
+// ---------------------------------------------------------------------------------------------------------
+static bool parse_options(const char *js, std::map<std::string, std::string> &out, std::string &err)
+{
+    if (!js) return true;
+    const char *p = js;
+    auto ws = [&]() { while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') p++; };
+    auto str = [&](std::string &s) -> bool {
+        if (*p != '"') return false;
+        p++;
+        while (*p && *p != '"') s.push_back(*p++);
+        if (*p != '"') return false;
+        p++;
+        return true;
+    };
+    ws();
+    if (*p == 0) return true;
+    if (*p != '{') { err = "options must be a JSON object"; return false; }
+    p++;
+    ws();
+    if (*p == '}') return true;
+    for (;;) {
+        ws();
+        std::string k, v;
+        if (!str(k)) { err = "expected a quoted key"; return false; }
+        ws();
+        if (*p != ':') { err = "expected ':' after key " + k; return false; }
+        p++;
+        ws();
+        if (*p == '"') {
+            if (!str(v)) { err = "unterminated string for key " + k; return false; }
+        } else {
+            while (*p && *p != ',' && *p != '}' && *p != ' ' && *p != '\n') v.push_back(*p++);
+            if (v.empty()) { err = "missing value for key " + k; return false; }
+        }
+        out[k] = v;
+        ws();
+        if (*p == ',') { p++; continue; }
+        if (*p == '}') { p++; break; }
+        err = "expected ',' or '}'";
+        return false;
+    }
+    ws();
+    if (*p) { err = "trailing characters after the options object"; return false; }
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Context and batch objects
+// ---------------------------------------------------------------------------------------------------------
+struct qv_ctx_s {
+    int device = 0;
+    hipStream_t user_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int engine_stride = 0;      // 0: LDS tiles, 1: one global pass per gate
+    int tile_qubits = 0;        // 0: automatic
+    int graph = 1;
+    int n_vqpu = 0;             // 0: all circuits in flight
+    int launch_events = 0;      // 1: record a HIP event pair around every launch (eager mode)
+    hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+};
+
+// A device buffer owned by a batch.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DBuf() { if (p) (void)hipFree(p); }
+    hipError_t alloc(size_t b)
+    {
+        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        if (b == 0) b = 8;
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    template <typename T>
+    hipError_t upload(const std::vector<T> &v)
+    {
+        hipError_t e = alloc(v.size() * sizeof(T));
+        if (e != hipSuccess) return e;
+        if (!v.empty()) e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        return e;
+    }
+    template <typename T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+struct Level {
+    int64_t seg_off;
+    int32_t n_segs;
+    int64_t n_blocks;
+    int32_t lds_t;
+    int32_t stride;
+    int64_t bytes;    // algorithmic state bytes moved by the launch (read + write)
+};
+
+// Per-launch HIP event log (context option "launch_events"; eager launches only, no graph).
+struct LaunchLog {
+    std::vector<hipEvent_t> pool;
+    std::vector<qv_launch_rec> recs;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    ~LaunchLog() { for (auto e : pool) (void)hipEventDestroy(e); }
+    void clear() { recs.clear(); ev.clear(); used = 0; }
+    hipEvent_t next()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+
+template <typename F>
+static int logged(LaunchLog *log, hipStream_t s, int kernel, int level, int64_t bytes, F launch)
+{
+    if (!log) return launch();
+    hipEvent_t a = log->next(), b = log->next();
+    if (!a || !b) return launch();
+    (void)hipEventRecord(a, s);
+    int e = launch();
+    (void)hipEventRecord(b, s);
+    qv_launch_rec r;
+    r.kernel = kernel;
+    r.level = level;
+    r.bytes = bytes;
+    r.ms = 0.0;
+    log->recs.push_back(r);
+    log->ev.emplace_back(a, b);
+    return e;
+}
+
+// Everything needed to run one set of device circuits (the batch itself, or a chunk of parameter-shift
+// variants): per-circuit records, the launch levels, and the expectation / gradient reductions.
+struct ExecSet {
+    int n_circ = 0;
+    std::vector<DevCirc> circs;
+    std::vector<int> plan_of;                  // plan id per device circuit
+    int64_t state_amps = 0;                    // amplitudes in this set's pool
+    // forward and reverse levels
+    std::vector<Seg> segs;
+    std::vector<Level> fwd, rev;
+    int64_t partial_count = 0;                 // adjoint partial sums
+    // init
+    std::vector<int64_t> init_first_block;
+    int64_t init_blocks = 0;
+    // expectation
+    std::vector<DevGroup> groups;
+    std::vector<DevTerm> terms;
+    int64_t exp_blocks = 0;
+    int64_t exp_partials = 0;
+    std::vector<int64_t> tv_begin;
+    std::vector<PartialRef> term_refs, norm_refs;
+    std::vector<double> out_coeff;
+    // adjoint seed
+    std::vector<int64_t> lam_first_block, obs_begin;
+    std::vector<DevObsTerm> obs;
+    int64_t lam_blocks = 0;
+    // gradient reduction
+    std::vector<int64_t> gref_begin;
+    std::vector<PartialRef> grefs;
+    int64_t algo_bytes_fwd = 0, algo_bytes_rev = 0, passes_fwd = 0, passes_rev = 0;
+    int64_t init_bytes = 0, exp_bytes = 0, lam_bytes = 0;
+
+    // device copies
+    DBuf d_circs, d_segs, d_init_fb, d_groups, d_terms, d_tv_begin, d_term_refs, d_norm_refs, d_coeff;
+    DBuf d_lam_fb, d_obs_begin, d_obs, d_gref_begin, d_grefs;
+    DBuf d_exp_partials, d_adj_partials;
+};
+
+struct qv_batch_s {
+    qv_ctx ctx = nullptr;
+    int B = 0;
+    qv_precision prec = QV_C64;
+    int amp_bytes = 8;
+    std::vector<int32_t> nq;
+    std::vector<int64_t> goff;
+    std::vector<qv_gate> gates;
+    std::vector<int32_t> nparams;
+    int params_shared = 0;
+    int64_t n_theta = 0, n_grad = 0;
+    std::vector<int64_t> toff;
+    std::vector<uint64_t> xm, zm;
+    std::vector<double> cf;
+    int obs_shared = 0;
+    int64_t n_tv = 0;
+
+    std::vector<Plan> plans;
+    std::vector<int> plan_of;          // per circuit
+    int tile_qubits = 0;
+
+    ExecSet main;
+    // parameter-shift chunks
+    std::vector<std::unique_ptr<ExecSet>> ps_chunks;
+    std::vector<int64_t> ps_chunk_var0;    // first variant index of each chunk
+    int64_t n_occ = 0;
+    std::vector<int64_t> occ_begin;
+    std::vector<int32_t> occ_plus, occ_minus, occ_circ;
+    bool ps_ready = false;
+
+    DBuf d_gates, d_theta, d_psi, d_lam, d_energies, d_tv, d_norms, d_grad, d_upstream;
+    DBuf d_ps_psi, d_ps_energies, d_ps_tv, d_occ_begin, d_occ_plus, d_occ_minus, d_occ_circ;
+
+    bool theta_set = false;
+    bool fwd_valid = false;
+
+    hipGraphExec_t g_fwd = nullptr, g_adj = nullptr, g_ps = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    LaunchLog log;
+    qv_stats last{};
+};
+
+// ---------------------------------------------------------------------------------------------------------
+// Validation (host only)
+// ---------------------------------------------------------------------------------------------------------
+static bool is_rotation(int k) { return k == QV_RX || k == QV_RY || k == QV_RZ; }
+static bool is_two_qubit(int k) { return k == QV_CNOT || k == QV_CZ; }
+
+static qv_status validate(int32_t B, const int32_t *nq, const int64_t *goff, const qv_gate *gates,
+                          const int32_t *np, int32_t params_shared, const int64_t *toff, const uint64_t *xm,
+                          const uint64_t *zm, const double *cf, int32_t obs_shared, qv_precision prec)
+{
+    if (B < 1) return fail(QV_E_INVALID, "n_circuits must be >= 1 (got %d)", B);
+    if (!nq || !goff || !np || !toff) return fail(QV_E_INVALID, "n_qubits, gate_offsets, n_params and term_offsets must not be NULL");
+    if (prec != QV_C64 && prec != QV_C128) return fail(QV_E_INVALID, "precision must be QV_C64 or QV_C128 (got %d)", (int)prec);
+    if (goff[0] != 0) return fail(QV_E_INVALID, "gate_offsets[0] must be 0 (got %lld)", (long long)goff[0]);
+    for (int b = 0; b < B; b++) {
+        if (nq[b] < 1 || nq[b] > 34) return fail(QV_E_INVALID, "circuit %d: n_qubits must be in [1, 34] (got %d)", b, nq[b]);
+        if (goff[b + 1] < goff[b]) return fail(QV_E_INVALID, "gate_offsets must be non-decreasing (circuit %d)", b);
+        if (np[b] < 0) return fail(QV_E_INVALID, "circuit %d: n_params must be >= 0", b);
+        if (params_shared && np[b] != np[0]) return fail(QV_E_INVALID, "params_shared requires equal n_params (circuit %d)", b);
+    }
+    if (goff[B] > 0 && !gates) return fail(QV_E_INVALID, "gates must not be NULL");
+    for (int b = 0; b < B; b++) {
+        const int n = nq[b];
+        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
+            const qv_gate &g = gates[k];
+            const long long kl = (long long)(k - goff[b]);
+            if (g.kind < QV_H || g.kind > QV_CZ) return fail(QV_E_INVALID, "circuit %d gate %lld: unknown kind %d", b, kl, g.kind);
+            if (g.q0 < 0 || g.q0 >= n) return fail(QV_E_INVALID, "circuit %d gate %lld: qubit %d out of range [0, %d)", b, kl, g.q0, n);
+            if (is_two_qubit(g.kind)) {
+                if (g.q1 < 0 || g.q1 >= n) return fail(QV_E_INVALID, "circuit %d gate %lld: qubit %d out of range [0, %d)", b, kl, g.q1, n);
+                if (g.q1 == g.q0) return fail(QV_E_INVALID, "circuit %d gate %lld: both qubits are %d", b, kl, g.q0);
+            }
+            if (is_rotation(g.kind)) {
+                if (g.param < -1 || g.param >= np[b])
+                    return fail(QV_E_INVALID, "circuit %d gate %lld: param %d out of range [-1, %d)", b, kl, g.param, np[b]);
+                if (g.param == -1 && !std::isfinite(g.angle))
+                    return fail(QV_E_INVALID, "circuit %d gate %lld: non-finite angle", b, kl);
+            } else if (g.param != -1) {
+                return fail(QV_E_INVALID, "circuit %d gate %lld: only RX/RY/RZ take a parameter", b, kl);
+            }
+        }
+    }
+    const int nto = obs_shared ? 1 : B;
+    if (toff[0] < 0) return fail(QV_E_INVALID, "term_offsets[0] must be >= 0");
+    for (int i = 0; i < nto; i++)
+        if (toff[i + 1] < toff[i]) return fail(QV_E_INVALID, "term_offsets must be non-decreasing");
+    const int64_t tt = toff[nto];
+    if (tt > toff[0] && (!xm || !zm || !cf)) return fail(QV_E_INVALID, "xmask, zmask and coeff must not be NULL");
+    for (int b = 0; b < B; b++) {
+        const int64_t t0 = obs_shared ? toff[0] : toff[b], t1 = obs_shared ? toff[1] : toff[b + 1];
+        const uint64_t lim = nq[b] >= 64 ? ~0ull : ((1ull << nq[b]) - 1ull);
+        for (int64_t t = t0; t < t1; t++) {
+            if ((xm[t] & ~lim) || (zm[t] & ~lim))
+                return fail(QV_E_INVALID, "term %lld has a qubit outside circuit %d's %d qubits", (long long)t, b, nq[b]);
+            if (!std::isfinite(cf[t])) return fail(QV_E_INVALID, "term %lld: non-finite coefficient", (long long)t);
+        }
+    }
+    return QV_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// ExecSet construction
+// ---------------------------------------------------------------------------------------------------------
+static int64_t tiles_of(const DevCirc &c, const Plan &pl, int p)
+{
+    const PlanPass &pp = pl.passes[p];
+    if (pp.stride) {
+        const int k = pp.t;
+        const int64_t groups = (int64_t)1 << (c.n - k);
+        return (groups + kStrideGroupsPerBlock - 1) / kStrideGroupsPerBlock;
+    }
+    return (int64_t)1 << (c.n - pp.t);
+}
+
+// Builds the launch levels (forward and reverse) and the adjoint partial-sum layout of a set.
+// Circuits are launched in waves of at most `wave` circuits; every wave runs all its levels before the
+// next wave starts. Results do not depend on the wave size.
+static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std::vector<int> &pass_base, int wave,
+                         int amp_bytes)
+{
+    es.segs.clear(); es.fwd.clear(); es.rev.clear();
+    es.partial_count = 0;
+    es.algo_bytes_fwd = es.algo_bytes_rev = es.passes_fwd = es.passes_rev = 0;
+    const int N = es.n_circ;
+    if (wave <= 0 || wave > N) wave = N;
+    // partial bases per (circuit, pass)
+    std::vector<std::vector<int64_t>> pbase(N);
+    for (int c = 0; c < N; c++) {
+        const Plan &pl = plans[es.plan_of[c]];
+        pbase[c].resize(pl.passes.size());
+        for (size_t p = 0; p < pl.passes.size(); p++) {
+            pbase[c][p] = es.partial_count;
+            es.partial_count += tiles_of(es.circs[c], pl, (int)p) * pl.passes[p].n_train;
+        }
+        const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
+        es.algo_bytes_fwd += 2 * S * (int64_t)pl.passes.size();
+        es.algo_bytes_rev += 4 * S * (int64_t)pl.passes.size();
+        es.passes_fwd += (int64_t)pl.passes.size();
+        es.passes_rev += (int64_t)pl.passes.size();
+    }
+    for (int w0 = 0; w0 < N; w0 += wave) {
+        const int w1 = std::min(N, w0 + wave);
+        int maxp = 0;
+        for (int c = w0; c < w1; c++) maxp = std::max(maxp, (int)plans[es.plan_of[c]].passes.size());
+        for (int dir = 0; dir < 2; dir++) {
+            for (int L = 0; L < maxp; L++) {
+                Level lv{(int64_t)es.segs.size(), 0, 0, 0, -1, 0};
+                for (int c = w0; c < w1; c++) {
+                    const Plan &pl = plans[es.plan_of[c]];
+                    const int np = (int)pl.passes.size();
+                    if (L >= np) continue;
+                    const int p = dir == 0 ? L : np - 1 - L;
+                    Seg s;
+                    s.first_block = lv.n_blocks;
+                    s.partial_base = pbase[c][p];
+                    s.circ = c;
+                    s.pass = pass_base[es.plan_of[c]] + p;
+                    es.segs.push_back(s);
+                    lv.n_segs++;
+                    lv.n_blocks += tiles_of(es.circs[c], pl, p);
+                    lv.lds_t = std::max(lv.lds_t, pl.passes[p].t);
+                    lv.bytes += (dir == 0 ? 2 : 4) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
+                    const int st = pl.passes[p].stride;
+                    lv.stride = st;  // a level never mixes engines: the engine is chosen per batch
+                }
+                if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
+            }
+        }
+    }
+    // init blocks
+    es.init_first_block.assign(N + 1, 0);
+    for (int c = 0; c < N; c++)
+        es.init_first_block[c + 1] = es.init_first_block[c] + ((((int64_t)1 << es.circs[c].n) + 4095) / 4096);
+    es.init_blocks = es.init_first_block[N];
+    es.init_bytes = 0;
+    for (int c = 0; c < N; c++) es.init_bytes += ((int64_t)1 << es.circs[c].n) * amp_bytes;
+}
+
+struct ObsView {
+    const int64_t *toff;
+    const uint64_t *xm, *zm;
+    const double *cf;
+    int obs_shared;
+};
+
+// Expectation work items of a set. Terms of a circuit are grouped by x-mask (first appearance order),
+// each group split into items of at most kMaxGroupTerms terms; an identity term carries the norm.
+// out_base[c] is the first output slot of device circuit c; obs_of[c] the batch circuit whose terms it uses.
+static void build_expectation(ExecSet &es, const ObsView &ov, const std::vector<int> &obs_of,
+                              const std::vector<int64_t> &out_base, int64_t n_out, bool with_norm, int amp_bytes)
+{
+    es.exp_bytes = 0;
+    es.groups.clear(); es.terms.clear(); es.term_refs.assign(n_out, PartialRef{0, 0, 1});
+    es.norm_refs.assign(es.n_circ, PartialRef{0, 0, 1});
+    es.out_coeff.assign(n_out, 0.0);
+    es.tv_begin.assign(es.n_circ + 1, 0);
+    es.exp_blocks = 0;
+    es.exp_partials = 0;
+    for (int c = 0; c < es.n_circ; c++) {
+        const int b = obs_of[c];
+        const int n = es.circs[c].n;
+        const int64_t t0 = ov.obs_shared ? ov.toff[0] : ov.toff[b];
+        const int64_t t1 = ov.obs_shared ? ov.toff[1] : ov.toff[b + 1];
+        es.tv_begin[c] = out_base[c];
+        es.tv_begin[c + 1] = out_base[c] + (t1 - t0);
+        // group terms by xmask; -1 marks the norm
+        std::vector<uint64_t> gx;
+        std::vector<std::vector<int64_t>> gt;
+        std::unordered_map<uint64_t, int> gi;
+        auto add = [&](uint64_t x, int64_t t) {
+            auto it = gi.find(x);
+            int id;
+            if (it == gi.end()) { id = (int)gx.size(); gi[x] = id; gx.push_back(x); gt.emplace_back(); }
+            else id = it->second;
+            gt[id].push_back(t);
+        };
+        for (int64_t t = t0; t < t1; t++) add(ov.xm[t], t);
+        if (with_norm) add(0, -1);
+        for (size_t g = 0; g < gx.size(); g++) {
+            const uint64_t x = gx[g];
+            const int clog = std::min(kExpChunkLog2, x ? n - 1 : n);
+            const int64_t items = x ? ((int64_t)1 << (n - 1)) : ((int64_t)1 << n);
+            const int64_t nchunks = std::max<int64_t>(1, items >> clog);
+            for (size_t j0 = 0; j0 < gt[g].size(); j0 += kMaxGroupTerms) {
+                const int nt = (int)std::min<size_t>(kMaxGroupTerms, gt[g].size() - j0);
+                DevGroup G;
+                G.xmask = x;
+                G.first_block = es.exp_blocks;
+                G.partial_base = es.exp_partials;
+                G.circ = c;
+                G.n_terms = nt;
+                G.term_begin = (int32_t)es.terms.size();
+                G.chunk_log2 = clog;
+                for (int j = 0; j < nt; j++) {
+                    const int64_t t = gt[g][j0 + j];
+                    const uint64_t z = t >= 0 ? ov.zm[t] : 0;
+                    DevTerm dt;
+                    dt.zmask = z;
+                    dt.ny = __builtin_popcountll(x & z) & 3;
+                    dt.pad = 0;
+                    es.terms.push_back(dt);
+                    PartialRef r{G.partial_base + j, (int32_t)nchunks, nt};
+                    if (t >= 0) {
+                        const int64_t o = out_base[c] + (t - t0);
+                        es.term_refs[o] = r;
+                        es.out_coeff[o] = ov.cf[t];
+                    } else {
+                        es.norm_refs[c] = r;
+                    }
+                }
+                es.groups.push_back(G);
+                es.exp_blocks += nchunks;
+                es.exp_bytes += ((int64_t)1 << n) * amp_bytes;
+                es.exp_partials += nchunks * nt;
+            }
+        }
+    }
+}
+
+static void build_lambda(ExecSet &es, const ObsView &ov, const std::vector<int> &obs_of, int amp_bytes)
+{
+    es.lam_bytes = 0;
+    es.lam_first_block.assign(es.n_circ + 1, 0);
+    es.obs_begin.assign(es.n_circ + 1, 0);
+    es.obs.clear();
+    for (int c = 0; c < es.n_circ; c++) {
+        const int b = obs_of[c];
+        const int64_t t0 = ov.obs_shared ? ov.toff[0] : ov.toff[b];
+        const int64_t t1 = ov.obs_shared ? ov.toff[1] : ov.toff[b + 1];
+        for (int64_t t = t0; t < t1; t++) {
+            DevObsTerm o;
+            o.xmask = ov.xm[t];
+            o.zmask = ov.zm[t];
+            o.coeff = ov.cf[t];
+            o.ny = __builtin_popcountll(ov.xm[t] & ov.zm[t]) & 3;
+            o.pad = 0;
+            es.obs.push_back(o);
+        }
+        es.obs_begin[c + 1] = (int64_t)es.obs.size();
+        es.lam_bytes += (1 + (t1 - t0)) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
+        es.lam_first_block[c + 1] = es.lam_first_block[c] + ((((int64_t)1 << es.circs[c].n) + 4095) / 4096);
+    }
+    es.lam_blocks = es.lam_first_block[es.n_circ];
+}
+
+// Gradient references: for output g, every trainable gate occurrence that reads it.
+static void build_grad_refs(ExecSet &es, const qv_batch_s &bt, const std::vector<int> &pass_base)
+{
+    (void)pass_base;
+    std::vector<std::vector<PartialRef>> per(bt.n_grad);
+    // reconstruct partial bases in the same order as build_levels
+    int64_t base = 0;
+    for (int c = 0; c < es.n_circ; c++) {
+        const Plan &pl = bt.plans[es.plan_of[c]];
+        const int b = es.circs[c].base_circ;
+        for (size_t p = 0; p < pl.passes.size(); p++) {
+            const PlanPass &pp = pl.passes[p];
+            const int64_t tiles = tiles_of(es.circs[c], pl, (int)p);
+            for (const PlanOp &op : pp.ops) {
+                if (op.train_slot < 0) continue;
+                const qv_gate &g = bt.gates[bt.goff[b] + op.gate];
+                int64_t out = g.param;
+                if (!bt.params_shared) {
+                    int64_t pb = 0;
+                    for (int i = 0; i < b; i++) pb += bt.nparams[i];
+                    out += pb;
+                }
+                per[out].push_back(PartialRef{base + op.train_slot, (int32_t)tiles, pp.n_train});
+            }
+            base += tiles * pp.n_train;
+        }
+    }
+    es.gref_begin.assign(bt.n_grad + 1, 0);
+    es.grefs.clear();
+    for (int64_t g = 0; g < bt.n_grad; g++) {
+        for (auto &r : per[g]) es.grefs.push_back(r);
+        es.gref_begin[g + 1] = (int64_t)es.grefs.size();
+    }
+}
+
+static hipError_t upload_set(ExecSet &es, bool adjoint_parts)
+{
+    hipError_t e;
+    if ((e = es.d_circs.upload(es.circs)) != hipSuccess) return e;
+    if ((e = es.d_segs.upload(es.segs)) != hipSuccess) return e;
+    if ((e = es.d_init_fb.upload(es.init_first_block)) != hipSuccess) return e;
+    if ((e = es.d_groups.upload(es.groups)) != hipSuccess) return e;
+    if ((e = es.d_terms.upload(es.terms)) != hipSuccess) return e;
+    if ((e = es.d_tv_begin.upload(es.tv_begin)) != hipSuccess) return e;
+    if ((e = es.d_term_refs.upload(es.term_refs)) != hipSuccess) return e;
+    if ((e = es.d_norm_refs.upload(es.norm_refs)) != hipSuccess) return e;
+    if ((e = es.d_coeff.upload(es.out_coeff)) != hipSuccess) return e;
+    if ((e = es.d_exp_partials.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, es.exp_partials))) != hipSuccess) return e;
+    if (adjoint_parts) {
+        if ((e = es.d_lam_fb.upload(es.lam_first_block)) != hipSuccess) return e;
+        if ((e = es.d_obs_begin.upload(es.obs_begin)) != hipSuccess) return e;
+        if ((e = es.d_obs.upload(es.obs)) != hipSuccess) return e;
+        if ((e = es.d_gref_begin.upload(es.gref_begin)) != hipSuccess) return e;
+        if ((e = es.d_grefs.upload(es.grefs)) != hipSuccess) return e;
+        if ((e = es.d_adj_partials.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, es.partial_count))) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Launch sequences
+// ---------------------------------------------------------------------------------------------------------
+struct DevPlans {
+    DBuf passes, ops;
+    std::vector<int> pass_base;
+};
+
+static std::unordered_map<const qv_batch_s *, std::unique_ptr<DevPlans>> g_devplans;
+
+static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPlans &dp, const Level &lv,
+                            void *psi, void *lam)
+{
+    LevelArgs a;
+    a.segs = es.d_segs.as<Seg>() + lv.seg_off;
+    a.n_segs = lv.n_segs;
+    a.lds_t = lv.lds_t;
+    a.n_blocks = lv.n_blocks;
+    a.passes = dp.passes.as<DevPass>();
+    a.ops = dp.ops.as<DevOp>();
+    a.circs = es.d_circs.as<DevCirc>();
+    a.gates = bt.d_gates.as<qv_gate>();
+    a.theta = bt.d_theta.as<double>();
+    a.psi = psi;
+    a.lam = lam;
+    a.partials = es.d_adj_partials.as<double>();
+    return a;
+}
+
+static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, void *psi, double *energies,
+                           double *tv, double *norms, hipStream_t s, LaunchLog *log)
+{
+    int e = logged(log, s, QV_K_INIT, -1, es.init_bytes, [&] {
+        return launch_init_states(psi, es.d_circs.as<DevCirc>(), es.d_init_fb.as<int64_t>(), es.n_circ,
+                                  es.init_blocks, bt.prec, s);
+    });
+    if (e) return e;
+    for (size_t L = 0; L < es.fwd.size(); L++) {
+        const Level &lv = es.fwd[L];
+        LevelArgs a = level_args(bt, es, dp, lv, psi, nullptr);
+        e = logged(log, s, lv.stride ? QV_K_STRIDE : QV_K_TILE, (int)L, lv.bytes, [&] {
+            return lv.stride ? launch_stride_level(a, bt.prec, 0, s) : launch_level(a, bt.prec, 0, s);
+        });
+        if (e) return e;
+    }
+    ExpArgs ea;
+    ea.groups = es.d_groups.as<DevGroup>();
+    ea.n_groups = (int32_t)es.groups.size();
+    ea.n_blocks = es.exp_blocks;
+    ea.terms = es.d_terms.as<DevTerm>();
+    ea.circs = es.d_circs.as<DevCirc>();
+    ea.psi = psi;
+    ea.partials = es.d_exp_partials.as<double>();
+    e = logged(log, s, QV_K_EXPECT, -1, es.exp_bytes, [&] { return launch_expectation(ea, bt.prec, s); });
+    if (e) return e;
+    FinalizeArgs fa;
+    fa.n_circ = es.n_circ;
+    fa.tv_begin = es.d_tv_begin.as<int64_t>();
+    fa.term_refs = es.d_term_refs.as<PartialRef>();
+    fa.coeff = es.d_coeff.as<double>();
+    fa.norm_refs = norms ? es.d_norm_refs.as<PartialRef>() : nullptr;
+    fa.partials = es.d_exp_partials.as<double>();
+    fa.term_values = tv;
+    fa.energies = energies;
+    fa.norms = norms;
+    return logged(log, s, QV_K_FINALIZE, -1, 0, [&] { return launch_finalize(fa, s); });
+}
+
+static int enqueue_adjoint(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, hipStream_t s, LaunchLog *log)
+{
+    LambdaArgs la;
+    la.circs = es.d_circs.as<DevCirc>();
+    la.n_circ = es.n_circ;
+    la.first_block = es.d_lam_fb.as<int64_t>();
+    la.obs_begin = es.d_obs_begin.as<int64_t>();
+    la.obs = es.d_obs.as<DevObsTerm>();
+    la.upstream = bt.d_upstream.as<double>();
+    la.psi = bt.d_psi.p;
+    la.lam = bt.d_lam.p;
+    la.n_blocks = es.lam_blocks;
+    int e = logged(log, s, QV_K_LAMBDA, -1, es.lam_bytes, [&] { return launch_lambda(la, bt.prec, s); });
+    if (e) return e;
+    for (size_t L = 0; L < es.rev.size(); L++) {
+        const Level &lv = es.rev[L];
+        LevelArgs a = level_args(bt, es, dp, lv, bt.d_psi.p, bt.d_lam.p);
+        e = logged(log, s, lv.stride ? QV_K_STRIDE_ADJ : QV_K_TILE_ADJ, (int)L, lv.bytes, [&] {
+            return lv.stride ? launch_stride_level(a, bt.prec, 1, s) : launch_level(a, bt.prec, 1, s);
+        });
+        if (e) return e;
+    }
+    GradReduceArgs ga;
+    ga.n_out = (int32_t)bt.n_grad;
+    ga.ref_begin = es.d_gref_begin.as<int64_t>();
+    ga.refs = es.d_grefs.as<PartialRef>();
+    ga.partials = es.d_adj_partials.as<double>();
+    ga.grad = bt.d_grad.as<double>();
+    return logged(log, s, QV_K_GRAD_REDUCE, -1, 0, [&] { return launch_grad_reduce(ga, s); });
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// C interface
+// ---------------------------------------------------------------------------------------------------------
+// Exported functions (C linkage comes from their declarations in qvpu.h).
+
+const char *qv_last_error(void) { return g_err.c_str(); }
+
+const char *qv_version(void) { return "qvpu 0.1 (gfx950)"; }
+
+qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_json, qv_ctx *out)
+{
+    if (!out) return fail(QV_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    std::map<std::string, std::string> opt;
+    std::string perr;
+    if (!parse_options(options_json, opt, perr)) return fail(QV_E_INVALID, "options_json: %s", perr.c_str());
+    auto c = std::make_unique<qv_ctx_s>();
+    for (auto &kv : opt) {
+        const std::string &k = kv.first, &v = kv.second;
+        if (k == "n-virtual-qpus") {
+            int n = atoi(v.c_str());
+            if (n < 1) return fail(QV_E_INVALID, "n-virtual-qpus must be >= 1");
+            c->n_vqpu = n;
+        } else if (k == "engine") {
+            if (v == "tiled") c->engine_stride = 0;
+            else if (v == "stride") c->engine_stride = 1;
+            else return fail(QV_E_INVALID, "engine must be \"tiled\" or \"stride\"");
+        } else if (k == "tile_qubits") {
+            if (v == "auto") c->tile_qubits = 0;
+            else {
+                int t = atoi(v.c_str());
+                if (t < 6 || t > kMaxTileQubits) return fail(QV_E_INVALID, "tile_qubits must be in [6, %d] or \"auto\"", kMaxTileQubits);
+                c->tile_qubits = t;
+            }
+        } else if (k == "graph") {
+            c->graph = (v == "true" || v == "1");
+        } else if (k == "launch_events") {
+            c->launch_events = (v == "true" || v == "1");
+        } else if (k == "launch") {
+            if (v != "levels") return fail(QV_E_UNSUPPORTED, "launch mode \"%s\" is not available", v.c_str());
+        } else if (k == "autotune" || k == "fusion_k" || k == "precision" || k == "deterministic") {
+            /* accepted for compatibility; the current planner ignores them */
+        } else {
+            return fail(QV_E_INVALID, "unknown option \"%s\"", k.c_str());
+        }
+    }
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(QV_E_INVALID, "device %d out of range (%d devices)", device, ndev);
+    c->device = device;
+    HIPCHK(hipSetDevice(device));
+    int e = prepare_kernels();
+    if (e) return fail(QV_E_DEVICE, "kernel setup failed: %s", hipGetErrorString((hipError_t)e));
+    c->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    *out = c.release();
+    return ok();
+}
+
+qv_status qv_ctx_set_stream(qv_ctx ctx, void *hip_stream)
+{
+    if (!ctx) return fail(QV_E_INVALID, "ctx must not be NULL");
+    ctx->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return ok();
+}
+
+qv_status qv_ctx_destroy(qv_ctx ctx)
+{
+    if (!ctx) return fail(QV_E_INVALID, "ctx must not be NULL");
+    (void)hipSetDevice(ctx->device);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return ok();
+}
+
+qv_status qv_validate_batch(int32_t n_circuits, const int32_t *n_qubits, const int64_t *gate_offsets,
+                            const qv_gate *gates, const int32_t *n_params, int32_t params_shared,
+                            const int64_t *term_offsets, const uint64_t *xmask, const uint64_t *zmask,
+                            const double *coeff, int32_t obs_shared, qv_precision precision)
+{
+    qv_status st = validate(n_circuits, n_qubits, gate_offsets, gates, n_params, params_shared, term_offsets, xmask,
+                            zmask, coeff, obs_shared, precision);
+    if (st == QV_OK) return ok();
+    return st;
+}
+
+static int default_tile_qubits(qv_precision p, bool adjoint)
+{
+    const char *env = getenv("QV_TILE_QUBITS");
+    int t = env ? atoi(env) : 0;
+    if (t < 6 || t > kMaxTileQubits) t = (p == QV_C64) ? 13 : 12;
+    if (adjoint) t -= 1;
+    if (p == QV_C128 && t > 13) t = 13;
+    if (adjoint && p == QV_C128 && t > 12) t = 12;
+    if (adjoint && p == QV_C64 && t > 13) t = 13;
+    return t;
+}
+
+qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_t *goff, const qv_gate *gates,
+                          const int32_t *np, int32_t params_shared, const int64_t *toff, const uint64_t *xm,
+                          const uint64_t *zm, const double *cf, int32_t obs_shared, qv_precision prec,
+                          qv_batch *out)
+{
+    if (!ctx) return fail(QV_E_INVALID, "ctx must not be NULL");
+    if (!out) return fail(QV_E_INVALID, "out must not be NULL");
+    *out = nullptr;
+    qv_status st = validate(B, nq, goff, gates, np, params_shared, toff, xm, zm, cf, obs_shared, prec);
+    if (st != QV_OK) return st;
+    HIPCHK(hipSetDevice(ctx->device));
+    auto bt = std::make_unique<qv_batch_s>();
+    bt->ctx = ctx;
+    bt->B = B;
+    bt->prec = prec;
+    bt->amp_bytes = prec == QV_C64 ? 8 : 16;
+    bt->nq.assign(nq, nq + B);
+    bt->goff.assign(goff, goff + B + 1);
+    bt->gates.assign(gates, gates + goff[B]);
+    bt->nparams.assign(np, np + B);
+    bt->params_shared = params_shared ? 1 : 0;
+    bt->n_theta = 0;
+    if (params_shared) bt->n_theta = np[0];
+    else for (int b = 0; b < B; b++) bt->n_theta += np[b];
+    bt->n_grad = bt->n_theta;
+    bt->obs_shared = obs_shared ? 1 : 0;
+    const int nto = obs_shared ? 1 : B;
+    bt->toff.assign(toff, toff + nto + 1);
+    const int64_t T0 = toff[0], T1 = toff[nto];
+    bt->xm.assign(xm ? xm + T0 : nullptr, xm ? xm + T1 : nullptr);
+    bt->zm.assign(zm ? zm + T0 : nullptr, zm ? zm + T1 : nullptr);
+    bt->cf.assign(cf ? cf + T0 : nullptr, cf ? cf + T1 : nullptr);
+    for (auto &v : bt->toff) v -= T0;
+    bt->n_tv = obs_shared ? (int64_t)B * (bt->toff[1] - bt->toff[0]) : bt->toff[B];
+
+    // memory check: states of the batch
+    int64_t amps = 0;
+    for (int b = 0; b < B; b++) amps += (int64_t)1 << nq[b];
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const double need = (double)amps * bt->amp_bytes;
+    if (need > 0.92 * (double)freeb)
+        return fail(QV_E_OOM, "states need %.2f GiB, device has %.2f GiB free", need / 1073741824.0, freeb / 1073741824.0);
+
+    // plans: circuits with the same structure share one
+    // The adjoint sweep holds two tiles (psi and lambda) in LDS, so a plan's tiles are capped at
+    // 2^13 amplitudes for complex64 and 2^12 for complex128 (2 x 64 KiB plus the index table).
+    bt->tile_qubits = ctx->tile_qubits ? ctx->tile_qubits : default_tile_qubits(prec, false);
+    bt->tile_qubits = std::min(bt->tile_qubits, prec == QV_C64 ? 13 : 12);
+    std::unordered_map<std::string, int> sig2plan;
+    bt->plan_of.resize(B);
+    for (int b = 0; b < B; b++) {
+        std::string sig((const char *)&nq[b], sizeof(int32_t));
+        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
+            const qv_gate &g = gates[k];
+            int32_t rec[4] = {g.kind, g.q0, is_two_qubit(g.kind) ? g.q1 : -1, (is_rotation(g.kind) && g.param >= 0) ? 1 : 0};
+            sig.append((const char *)rec, sizeof rec);
+        }
+        auto it = sig2plan.find(sig);
+        if (it != sig2plan.end()) { bt->plan_of[b] = it->second; continue; }
+        const int id = (int)bt->plans.size();
+        sig2plan.emplace(sig, id);
+        bt->plan_of[b] = id;
+        PlanInput pin;
+        pin.n = nq[b];
+        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
+            const qv_gate &g = gates[k];
+            pin.kinds.push_back(g.kind);
+            pin.q0.push_back(g.q0);
+            pin.q1.push_back(is_two_qubit(g.kind) ? g.q1 : -1);
+            pin.trainable.push_back(is_rotation(g.kind) && g.param >= 0);
+        }
+        const int lowc = prec == QV_C64 ? 4 : 3;
+        bt->plans.push_back(ctx->engine_stride ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc));
+    }
+    // device plan arrays
+    auto dp = std::make_unique<DevPlans>();
+    std::vector<DevPass> passes;
+    std::vector<DevOp> ops;
+    for (const Plan &pl : bt->plans) {
+        dp->pass_base.push_back((int)passes.size());
+        lower_plan(pl, passes, ops);
+    }
+    HIPCHK(dp->passes.upload(passes));
+    HIPCHK(dp->ops.upload(ops));
+
+    // main set
+    ExecSet &es = bt->main;
+    es.n_circ = B;
+    es.circs.resize(B);
+    es.plan_of = bt->plan_of;
+    int64_t off = 0, pb = 0;
+    for (int b = 0; b < B; b++) {
+        DevCirc &c = es.circs[b];
+        c.state_off = off;
+        c.gate_off = goff[b];
+        c.param_base = params_shared ? 0 : pb;
+        c.n = nq[b];
+        c.shift_gate = -1;
+        c.shift = 0.0;
+        c.base_circ = b;
+        c.pad = 0;
+        off += (int64_t)1 << nq[b];
+        pb += np[b];
+    }
+    es.state_amps = off;
+    build_levels(es, bt->plans, dp->pass_base, ctx->n_vqpu, bt->amp_bytes);
+    ObsView ov{bt->toff.data(), bt->xm.data(), bt->zm.data(), bt->cf.data(), bt->obs_shared};
+    std::vector<int> obs_of(B);
+    std::vector<int64_t> out_base(B);
+    const int64_t Tsh = obs_shared ? bt->toff[1] - bt->toff[0] : 0;
+    for (int b = 0; b < B; b++) {
+        obs_of[b] = b;
+        out_base[b] = obs_shared ? (int64_t)b * Tsh : bt->toff[b];
+    }
+    build_expectation(es, ov, obs_of, out_base, bt->n_tv, true, bt->amp_bytes);
+    build_lambda(es, ov, obs_of, bt->amp_bytes);
+    build_grad_refs(es, *bt, dp->pass_base);
+    HIPCHK(upload_set(es, true));
+
+    HIPCHK(bt->d_gates.upload(bt->gates));
+    HIPCHK(bt->d_theta.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_theta)));
+    HIPCHK(bt->d_psi.alloc((size_t)off * bt->amp_bytes));
+    HIPCHK(bt->d_energies.alloc(sizeof(double) * B));
+    HIPCHK(bt->d_tv.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_tv)));
+    HIPCHK(bt->d_norms.alloc(sizeof(double) * B));
+    HIPCHK(bt->d_grad.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_grad)));
+    HIPCHK(bt->d_upstream.alloc(sizeof(double) * B));
+    HIPCHK(hipEventCreate(&bt->ev0));
+    HIPCHK(hipEventCreate(&bt->ev1));
+    if (bt->n_theta == 0) bt->theta_set = true;
+    g_devplans[bt.get()] = std::move(dp);
+    *out = bt.release();
+    return ok();
+}
+
+qv_status qv_batch_set_params(qv_batch bt, const double *theta, int32_t on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (bt->n_theta == 0) { bt->theta_set = true; return ok(); }
+    if (!theta) return fail(QV_E_INVALID, "theta must not be NULL");
+    if (!on_device)
+        for (int64_t i = 0; i < bt->n_theta; i++)
+            if (!std::isfinite(theta[i])) return fail(QV_E_INVALID, "theta[%lld] is not finite", (long long)i);
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    hipStream_t s = bt->ctx->stream();
+    HIPCHK(hipMemcpyAsync(bt->d_theta.p, theta, sizeof(double) * (size_t)bt->n_theta,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    if (!on_device) HIPCHK(hipStreamSynchronize(s));
+    bt->theta_set = true;
+    bt->fwd_valid = false;
+    return ok();
+}
+
+// Runs `fn` either directly on the stream or through a cached graph captured on the context's capture stream.
+template <typename F>
+static qv_status run_graph(qv_batch bt, hipGraphExec_t &cache, F fn)
+{
+    hipStream_t s = bt->ctx->stream();
+    if (!bt->ctx->graph) {
+        int e = fn(s, bt->ctx->launch_events ? &bt->log : nullptr);
+        if (e) return fail(QV_E_DEVICE, "launch failed: %s", hipGetErrorString((hipError_t)e));
+        return QV_OK;
+    }
+    if (!cache) {
+        hipStream_t cs = bt->ctx->cap_stream;
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        int e = fn(cs, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e) { if (g) (void)hipGraphDestroy(g); return fail(QV_E_DEVICE, "launch failed during capture: %s", hipGetErrorString((hipError_t)e)); }
+        if (e2 != hipSuccess) return fail(QV_E_DEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e2));
+        hipError_t e3 = hipGraphInstantiate(&cache, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) { cache = nullptr; return fail(QV_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e3)); }
+    }
+    HIPCHK(hipGraphLaunch(cache, s));
+    return QV_OK;
+}
+
+static qv_status forward(qv_batch bt)
+{
+    DevPlans &dp = *g_devplans[bt];
+    qv_status st = run_graph(bt, bt->g_fwd, [&](hipStream_t s, LaunchLog *log) {
+        return enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                               bt->d_norms.as<double>(), s, log);
+    });
+    if (st != QV_OK) return st;
+    bt->fwd_valid = true;
+    bt->last = qv_stats{};
+    bt->last.passes = bt->main.passes_fwd;
+    bt->last.launches = 3 + (int64_t)bt->main.fwd.size();
+    bt->last.algorithmic_bytes = bt->main.algo_bytes_fwd;
+    return QV_OK;
+}
+
+static qv_status copy_out(qv_batch bt, void *dst, const void *src, size_t bytes, int on_device)
+{
+    if (!dst || bytes == 0) return QV_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, bt->ctx->stream()));
+    return QV_OK;
+}
+
+qv_status qv_batch_expectations(qv_batch bt, double *energies, double *term_values, int32_t out_on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(hipEventRecord(bt->ev0, bt->ctx->stream()));
+    qv_status st = forward(bt);
+    if (st != QV_OK) return st;
+    HIPCHK(hipEventRecord(bt->ev1, bt->ctx->stream()));
+    bt->timed = true;
+    if ((st = copy_out(bt, energies, bt->d_energies.p, sizeof(double) * bt->B, out_on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, term_values, bt->d_tv.p, sizeof(double) * (size_t)bt->n_tv, out_on_device)) != QV_OK) return st;
+    if (!out_on_device) HIPCHK(hipStreamSynchronize(bt->ctx->stream()));
+    return ok();
+}
+
+static qv_status ensure_lambda(qv_batch bt)
+{
+    if (bt->d_lam.p) return QV_OK;
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const double need = (double)bt->main.state_amps * bt->amp_bytes;
+    if (need > 0.92 * (double)freeb)
+        return fail(QV_E_OOM, "adjoint vectors need %.2f GiB, device has %.2f GiB free", need / 1073741824.0, freeb / 1073741824.0);
+    HIPCHK(bt->d_lam.alloc((size_t)bt->main.state_amps * bt->amp_bytes));
+    return QV_OK;
+}
+
+// Parameter-shift variants: every trainable gate occurrence (b, k) gives variants 2i (+pi/2), 2i+1 (-pi/2).
+static qv_status ensure_param_shift(qv_batch bt)
+{
+    if (bt->ps_ready) return QV_OK;
+    DevPlans &dp = *g_devplans[bt];
+    struct Occ { int b; int k; int64_t out; };
+    std::vector<Occ> occ;
+    std::vector<int64_t> pbase(bt->B + 1, 0);
+    for (int b = 0; b < bt->B; b++) pbase[b + 1] = pbase[b] + bt->nparams[b];
+    for (int b = 0; b < bt->B; b++)
+        for (int64_t k = bt->goff[b]; k < bt->goff[b + 1]; k++) {
+            const qv_gate &g = bt->gates[k];
+            if (is_rotation(g.kind) && g.param >= 0)
+                occ.push_back({b, (int)(k - bt->goff[b]), bt->params_shared ? g.param : pbase[b] + g.param});
+        }
+    bt->n_occ = (int64_t)occ.size();
+    // CSR by output index
+    std::vector<std::vector<int>> by_out(bt->n_grad);
+    for (size_t i = 0; i < occ.size(); i++) by_out[occ[i].out].push_back((int)i);
+    bt->occ_begin.assign(bt->n_grad + 1, 0);
+    bt->occ_plus.clear(); bt->occ_minus.clear(); bt->occ_circ.clear();
+    for (int64_t g = 0; g < bt->n_grad; g++) {
+        for (int i : by_out[g]) {
+            bt->occ_plus.push_back(2 * i);
+            bt->occ_minus.push_back(2 * i + 1);
+            bt->occ_circ.push_back(occ[i].b);
+        }
+        bt->occ_begin[g + 1] = (int64_t)bt->occ_plus.size();
+    }
+    // chunk variants so that a chunk's states stay within a budget
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const char *envb = getenv("QV_PS_BUDGET_MB");
+    double budget = envb ? atof(envb) * 1048576.0 : std::min(8.0 * 1073741824.0, 0.5 * (double)freeb);
+    const int64_t nvar = 2 * bt->n_occ;
+    bt->ps_chunks.clear();
+    bt->ps_chunk_var0.clear();
+    int64_t v = 0, max_amps = 0;
+    int64_t maxT = 0;
+    for (int b = 0; b < bt->B; b++) {
+        const int64_t T = bt->obs_shared ? bt->toff[1] - bt->toff[0] : bt->toff[b + 1] - bt->toff[b];
+        maxT = std::max(maxT, T);
+    }
+    ObsView ov{bt->toff.data(), bt->xm.data(), bt->zm.data(), bt->cf.data(), bt->obs_shared};
+    int64_t max_chunk_var = 0;
+    while (v < nvar) {
+        auto es = std::make_unique<ExecSet>();
+        int64_t amps = 0;
+        std::vector<int> obs_of;
+        while (v < nvar) {
+            const Occ &o = occ[v / 2];
+            const int64_t a = (int64_t)1 << bt->nq[o.b];
+            if (es->n_circ > 0 && (double)(amps + a) * bt->amp_bytes > budget) break;
+            DevCirc c = bt->main.circs[o.b];
+            c.state_off = amps;
+            c.shift_gate = o.k;
+            c.shift = (v % 2 == 0) ? M_PI / 2.0 : -M_PI / 2.0;
+            c.base_circ = o.b;
+            es->circs.push_back(c);
+            es->plan_of.push_back(bt->plan_of[o.b]);
+            obs_of.push_back(o.b);
+            es->n_circ++;
+            amps += a;
+            v++;
+        }
+        es->state_amps = amps;
+        max_amps = std::max(max_amps, amps);
+        build_levels(*es, bt->plans, dp.pass_base, bt->ctx->n_vqpu, bt->amp_bytes);
+        std::vector<int64_t> out_base(es->n_circ);
+        int64_t ob = 0;
+        for (int c = 0; c < es->n_circ; c++) {
+            out_base[c] = ob;
+            const int b = obs_of[c];
+            ob += bt->obs_shared ? bt->toff[1] - bt->toff[0] : bt->toff[b + 1] - bt->toff[b];
+        }
+        build_expectation(*es, ov, obs_of, out_base, ob, false, bt->amp_bytes);
+        HIPCHK(upload_set(*es, false));
+        bt->ps_chunk_var0.push_back(v - es->n_circ);
+        max_chunk_var = std::max<int64_t>(max_chunk_var, es->n_circ);
+        bt->ps_chunks.push_back(std::move(es));
+    }
+    HIPCHK(bt->d_ps_psi.alloc((size_t)std::max<int64_t>(1, max_amps) * bt->amp_bytes));
+    HIPCHK(bt->d_ps_energies.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, nvar)));
+    HIPCHK(bt->d_ps_tv.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, max_chunk_var * std::max<int64_t>(1, maxT))));
+    HIPCHK(bt->d_occ_begin.upload(bt->occ_begin));
+    HIPCHK(bt->d_occ_plus.upload(bt->occ_plus));
+    HIPCHK(bt->d_occ_minus.upload(bt->occ_minus));
+    HIPCHK(bt->d_occ_circ.upload(bt->occ_circ));
+    bt->ps_ready = true;
+    return QV_OK;
+}
+
+qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *upstream, double *grad,
+                            double *energies, int32_t on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!grad) return fail(QV_E_INVALID, "grad must not be NULL");
+    if (method != QV_ADJOINT && method != QV_PARAM_SHIFT) return fail(QV_E_INVALID, "unknown gradient method %d", (int)method);
+    if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    hipStream_t s = bt->ctx->stream();
+    if (upstream) {
+        if (!on_device)
+            for (int b = 0; b < bt->B; b++)
+                if (!std::isfinite(upstream[b])) return fail(QV_E_INVALID, "upstream[%d] is not finite", b);
+        HIPCHK(hipMemcpyAsync(bt->d_upstream.p, upstream, sizeof(double) * bt->B,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    } else {
+        int e = launch_fill(bt->d_upstream.as<double>(), bt->B, 1.0, s);
+        if (e) return fail(QV_E_DEVICE, "fill failed: %s", hipGetErrorString((hipError_t)e));
+    }
+    DevPlans &dp = *g_devplans[bt];
+    qv_status st;
+    HIPCHK(hipEventRecord(bt->ev0, s));
+    if (method == QV_ADJOINT) {
+        if ((st = ensure_lambda(bt)) != QV_OK) return st;
+        // The reverse sweep starts from the final states of a forward pass with the current parameters;
+        // run one first unless the last call left them in place.
+        int64_t passes = 0, bytes = 0, launches = 0;
+        if (!bt->fwd_valid) {
+            if ((st = forward(bt)) != QV_OK) return st;
+            passes += bt->last.passes;
+            bytes += bt->last.algorithmic_bytes;
+            launches += bt->last.launches;
+        }
+        st = run_graph(bt, bt->g_adj,
+                       [&](hipStream_t cs, LaunchLog *log) { return enqueue_adjoint(*bt, bt->main, dp, cs, log); });
+        if (st != QV_OK) return st;
+        bt->fwd_valid = false;  // the reverse sweep has un-applied the circuit from psi
+        bt->last = qv_stats{};
+        bt->last.passes = passes + bt->main.passes_rev;
+        bt->last.launches = launches + 2 + (int64_t)bt->main.rev.size();
+        bt->last.algorithmic_bytes = bytes + bt->main.algo_bytes_rev;
+    } else {
+        if ((st = ensure_param_shift(bt)) != QV_OK) return st;
+        st = run_graph(bt, bt->g_ps, [&](hipStream_t cs, LaunchLog *log) {
+            int e = enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                                    bt->d_norms.as<double>(), cs, log);
+            if (e) return e;
+            for (size_t i = 0; i < bt->ps_chunks.size(); i++) {
+                ExecSet &es = *bt->ps_chunks[i];
+                e = enqueue_forward(*bt, es, dp, bt->d_ps_psi.p, bt->d_ps_energies.as<double>() + bt->ps_chunk_var0[i],
+                                    bt->d_ps_tv.as<double>(), nullptr, cs, log);
+                if (e) return e;
+            }
+            ShiftCombineArgs sa;
+            sa.n_out = (int32_t)bt->n_grad;
+            sa.occ_begin = bt->d_occ_begin.as<int64_t>();
+            sa.occ_plus = bt->d_occ_plus.as<int32_t>();
+            sa.occ_minus = bt->d_occ_minus.as<int32_t>();
+            sa.occ_circ = bt->d_occ_circ.as<int32_t>();
+            sa.energies = bt->d_ps_energies.as<double>();
+            sa.upstream = bt->d_upstream.as<double>();
+            sa.grad = bt->d_grad.as<double>();
+            return logged(log, cs, QV_K_SHIFT_COMBINE, -1, 0, [&] { return launch_shift_combine(sa, cs); });
+        });
+        if (st != QV_OK) return st;
+        bt->fwd_valid = true;
+        bt->last = qv_stats{};
+        int64_t passes = bt->main.passes_fwd, bytes = bt->main.algo_bytes_fwd, launches = 4 + (int64_t)bt->main.fwd.size();
+        for (auto &c : bt->ps_chunks) {
+            passes += c->passes_fwd;
+            bytes += c->algo_bytes_fwd;
+            launches += 3 + (int64_t)c->fwd.size();
+        }
+        bt->last.passes = passes;
+        bt->last.launches = launches;
+        bt->last.algorithmic_bytes = bytes;
+    }
+    HIPCHK(hipEventRecord(bt->ev1, s));
+    bt->timed = true;
+    if ((st = copy_out(bt, grad, bt->d_grad.p, sizeof(double) * (size_t)bt->n_grad, on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, energies, bt->d_energies.p, sizeof(double) * bt->B, on_device)) != QV_OK) return st;
+    if (!on_device) HIPCHK(hipStreamSynchronize(s));
+    return ok();
+}
+
+qv_status qv_batch_state(qv_batch bt, int32_t circuit, void *out, int32_t out_on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!out) return fail(QV_E_INVALID, "out must not be NULL");
+    if (circuit < 0 || circuit >= bt->B) return fail(QV_E_INVALID, "circuit %d out of range [0, %d)", circuit, bt->B);
+    if (!bt->fwd_valid) return fail(QV_E_STATE, "no forward state: call qv_batch_expectations first");
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    const DevCirc &c = bt->main.circs[circuit];
+    const size_t bytes = ((size_t)1 << c.n) * bt->amp_bytes;
+    HIPCHK(hipMemcpyAsync(out, (char *)bt->d_psi.p + (size_t)c.state_off * bt->amp_bytes, bytes,
+                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, bt->ctx->stream()));
+    if (!out_on_device) HIPCHK(hipStreamSynchronize(bt->ctx->stream()));
+    return ok();
+}
+
+qv_status qv_batch_stats(qv_batch bt, qv_stats *out)
+{
+    if (!bt || !out) return fail(QV_E_INVALID, "batch and out must not be NULL");
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    if (bt->timed) {
+        HIPCHK(hipEventSynchronize(bt->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, bt->ev0, bt->ev1));
+        bt->last.kernel_ms = ms;
+    }
+    if (bt->fwd_valid || bt->d_norms.p) {
+        std::vector<double> nrm(bt->B);
+        HIPCHK(hipMemcpy(nrm.data(), bt->d_norms.p, sizeof(double) * bt->B, hipMemcpyDeviceToHost));
+        double m = 0.0;
+        for (double v : nrm) m = std::max(m, std::fabs(v - 1.0));
+        bt->last.norm_err_max = m;
+    }
+    *out = bt->last;
+    return ok();
+}
+
+qv_status qv_batch_destroy(qv_batch bt)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    (void)hipSetDevice(bt->ctx->device);
+    (void)hipStreamSynchronize(bt->ctx->stream());
+    if (bt->g_fwd) (void)hipGraphExecDestroy(bt->g_fwd);
+    if (bt->g_adj) (void)hipGraphExecDestroy(bt->g_adj);
+    if (bt->g_ps) (void)hipGraphExecDestroy(bt->g_ps);
+    if (bt->ev0) (void)hipEventDestroy(bt->ev0);
+    if (bt->ev1) (void)hipEventDestroy(bt->ev1);
+    g_devplans.erase(bt);
+    delete bt;
+    return ok();
+}
+
+
+
+qv_status qv_batch_launch_log(qv_batch bt, qv_launch_rec *out, int32_t max_records, int32_t *n_records)
+{
+    if (!bt || !n_records) return fail(QV_E_INVALID, "batch and n_records must not be NULL");
+    if (max_records > 0 && !out) return fail(QV_E_INVALID, "out must not be NULL when max_records > 0");
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    const int32_t n = (int32_t)bt->log.recs.size();
+    *n_records = n;
+    if (n == 0) return ok();
+    HIPCHK(hipEventSynchronize(bt->log.ev.back().second));
+    for (int32_t i = 0; i < n && i < max_records; i++) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, bt->log.ev[i].first, bt->log.ev[i].second));
+        out[i] = bt->log.recs[i];
+        out[i].ms = ms;
+    }
+    if (max_records >= n) bt->log.clear();
+    return ok();
+}

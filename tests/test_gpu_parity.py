@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library through its C interface against the CPU oracle on the same seeded inputs.
+
+Tolerances (the accuracy targets of the build):
+  * complex128 path: |x - x_ref| <= 1e-12 for every energy, term value and gradient component;
+  * complex64 path:  |x - x_ref| <= 1e-5 * max(|x_ref|, S), S = sum_t |c_t| for expectations and
+    S = sum_t |c_t| * sum_b |w_b| for gradients (random-string expectations are ~2^{-n/2}, so a purely
+    relative bound is meaningless near zero).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_03466_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def qv():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_03466_amd import qvpu
+    qvpu.load()
+    return qvpu
+
+
+def ctx_for(qv, **opts):
+    import torch
+    js = json.dumps(opts) if opts else None
+    return qv.Context(0, torch.cuda.current_stream().cuda_stream, js)
+
+
+def c64_tol(ref, scale):
+    return 1e-5 * np.maximum(np.abs(ref), scale)
+
+
+def check(x, ref, prec, scale, what):
+    x, ref = np.asarray(x), np.asarray(ref)
+    assert x.shape == ref.shape, (what, x.shape, ref.shape)
+    err = np.abs(x - ref)
+    if prec == 1:
+        bad = err > 1e-12
+    else:
+        bad = err > c64_tol(ref, scale)
+    assert not bad.any(), f"{what}: max err {err.max():.3e} at {int(np.argmax(err))}"
+
+
+def obs_scale(wl):
+    if wl.obs_shared:
+        return float(np.sum(np.abs(wl.coeff)))
+    return max(float(np.sum(np.abs(wl.terms(b)[2]))) for b in range(wl.B))
+
+
+# --------------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"graph": False}])
+def test_c1_expectations(qv, prec, opts):
+    say(f"c1 expectations prec={prec} opts={opts}")
+    wl = W.config1()
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+    e, tv = b.expectations()
+    check(e, e_ref, prec, obs_scale(wl), "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    st = b.stats()
+    assert st["norm_err_max"] < (1e-13 if prec == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}])
+def test_c1_gradients(qv, prec, opts):
+    say(f"c1 gradients prec={prec} opts={opts}")
+    wl = W.config1()
+    g_ref = oracle.grad_param_shift(wl)
+    b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+    g_ad, e_ad = b.gradient(qv.QV_ADJOINT)
+    g_ps, e_ps = b.gradient(qv.QV_PARAM_SHIFT)
+    s = obs_scale(wl)
+    check(g_ad, g_ref, prec, s, "adjoint grad")
+    check(g_ps, g_ref, prec, s, "param-shift grad")
+    e_ref, _, _, _ = oracle.expectations(wl)
+    check(e_ad, e_ref, prec, s, "energy (adjoint call)")
+    check(e_ps, e_ref, prec, s, "energy (param-shift call)")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_c2_full(qv, prec):
+    """16 qubits, 8 layers, 100 terms: every energy/term value; adjoint and the 513-circuit parameter-shift
+    batch against the oracle gradient."""
+    say(f"c2 prec={prec}")
+    wl = W.config2()
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    g_ref = oracle.grad_adjoint(wl)
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    g_ad, _ = b.gradient(qv.QV_ADJOINT)
+    check(g_ad, g_ref, prec, s, "adjoint grad")
+    g_ps, _ = b.gradient(qv.QV_PARAM_SHIFT)
+    check(g_ps, g_ref, prec, s, "param-shift grad")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("tile", [6, 9, None])
+def test_uneven_batch(qv, prec, tile):
+    """Circuits of 2..16 qubits and 0..80 gates in one batch: per-circuit energies, terms, states and
+    adjoint gradients (own parameters per circuit) with upstream weights."""
+    say(f"uneven prec={prec} tile={tile}")
+    wl = W.random_batch(24, 2, 16, 0, 80, 5, seed_index=41)
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    up = np.linspace(-1.0, 1.5, wl.B)
+    g_ref = oracle.grad_adjoint(wl, up)
+    opts = {} if tile is None else {"tile_qubits": tile}
+    b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    for c in [0, 5, 11, 23]:
+        n = int(wl.n_qubits[c])
+        psi_ref = oracle.final_state(n, wl.circuit(c), wl.theta_of(c))
+        psi = b.state(c)
+        err = np.max(np.abs(psi - psi_ref))
+        assert err < (1e-13 if prec == 1 else 1e-5), (c, err)
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+    check(g, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")
+    g2, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
+    check(g2, g_ref, prec, s * np.sum(np.abs(up)), "param-shift grad")
+
+
+def test_waves_and_engines_bitwise(qv):
+    """Results do not depend on how many circuits are in flight (n-virtual-qpus): bitwise equal."""
+    say("waves")
+    wl = W.random_batch(40, 3, 15, 10, 60, 4, seed_index=42)
+    outs = []
+    for nv in [1, 4, 40]:
+        b = qv.Batch(ctx_for(qv, **{"n-virtual-qpus": nv}), wl, 0)
+        e, tv = b.expectations()
+        g, _ = b.gradient(qv.QV_ADJOINT)
+        outs.append((e, tv, g))
+    for o in outs[1:]:
+        for a, r in zip(o, outs[0]):
+            assert np.array_equal(a, r)
+
+
+def test_shuffled_batch_permutes_output(qv):
+    say("shuffle")
+    wl = W.random_batch(20, 3, 14, 5, 40, 3, seed_index=43)
+    perm = np.random.default_rng(1).permutation(wl.B)
+    e0, _ = qv.Batch(ctx_for(qv), wl, 0).expectations()
+    e1, _ = qv.Batch(ctx_for(qv), wl.subset(perm), 0).expectations()
+    assert np.array_equal(e0[perm], e1)
+
+
+def test_graph_replays_with_new_params(qv):
+    """The captured graph is replayed with new parameters and eager work in between; each replay matches
+    the oracle for its parameters."""
+    import torch
+    say("graph replays")
+    wl = W.qcl(n=12, layers=2, samples=6, seed_index=44)
+    b = qv.Batch(ctx_for(qv), wl, 1)
+    rng = np.random.default_rng(3)
+    for r in range(4):
+        th = rng.uniform(0, 2 * np.pi, wl.n_grad())
+        b.set_params(th)
+        x = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        e, _ = b.expectations()
+        e_ref, _, _, _ = oracle.expectations(W.with_theta(wl, th))
+        check(e, e_ref, 1, 1.0, f"replay {r}")
+        assert torch.isfinite(x)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_qcl_autograd_small(qv, prec):
+    """ExpectationFn forward/backward on a 12-qubit circuit-learning batch against the oracle's adjoint
+    gradient and central finite differences of the MSE loss."""
+    import torch
+    from paper_2406_03466_amd.autograd import expectation
+    say(f"qcl autograd prec={prec}")
+    wl = W.qcl(n=12, layers=2, samples=8, seed_index=3)
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    theta = torch.tensor(wl.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    y = torch.tensor(wl.extra["y"], dtype=torch.float64, device="cuda")
+    f = expectation(theta, b)
+    loss = torch.mean((f - y) ** 2)
+    loss.backward()
+    e_ref, _, _, _ = oracle.expectations(wl)
+    up = 2.0 * (e_ref - wl.extra["y"]) / wl.B
+    g_ref = oracle.grad_adjoint(wl, up)
+    g_fd = oracle.grad_fd(wl, 1e-4, up)
+    assert np.max(np.abs(g_ref - g_fd)) < 1e-7 * np.sum(np.abs(up))
+    check(f.detach().cpu().numpy(), e_ref, prec, 1.0, "energies")
+    check(theta.grad.cpu().numpy(), g_ref, prec, float(np.sum(np.abs(up))), "grad")
+
+
+def _golden(name):
+    p = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(p):
+        pytest.skip(f"golden file {name}.json not generated")
+    return json.load(open(p))
+
+
+@pytest.mark.parametrize("layers", [2, 8])
+def test_qcl20_full_size(qv, layers):
+    """20 qubits, 64 samples, complex64: every energy and every gradient component of the MSE loss against
+    the oracle's stored values, in the launch configuration the benchmark times."""
+    say(f"qcl20 L={layers}")
+    gold = _golden(f"qcl20_L{layers}")
+    wl = W.config3(layers)
+    b = qv.Batch(ctx_for(qv), wl, 0)
+    e, _ = b.expectations(want_terms=False)
+    check(e, np.array(gold["energies"]), 0, 1.0, "energies")
+    up = 2.0 * (e - wl.extra["y"]) / wl.B
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
+    check(g, np.array(gold["grad"]), 0, float(np.sum(np.abs(gold["upstream"]))), "grad")
+    assert np.max(np.abs(up - np.array(gold["upstream"]))) < 1e-5
+
+
+def test_random1024_full_size(qv):
+    """1024 random circuits of 8..22 qubits, complex64: every energy and term value."""
+    say("random1024")
+    gold = _golden("random1024")
+    wl = W.config4()
+    b = qv.Batch(ctx_for(qv), wl, 0)
+    e, tv = b.expectations()
+    check(e, np.array(gold["energies"]), 0, obs_scale(wl), "energies")
+    check(tv, np.array(gold["term_values"]), 0, 1.0, "terms")
+
+
+@pytest.mark.parametrize("n", [26, 32])
+def test_large_state_closed_form(qv, n):
+    """One HEA layer on n qubits (32: a 32 GiB complex64 state) with the ZZ chain: the CNOT ladder is a
+    prefix-XOR permutation, so E = sum_{i>=1} cos(theta_RY[i]) and dE/dtheta_RY[i] = -sin(theta_RY[i])
+    (0 for i = 0); checks 64-bit indexing at full size."""
+    say(f"large n={n}")
+    wl = W.large_hea(n, 1, seed_index=5)
+    b = qv.Batch(ctx_for(qv), wl, 0)
+    e, tv = b.expectations()
+    ry = wl.theta[:n]
+    check(tv, np.cos(ry[1:]), 0, 1.0, "ZZ terms")
+    check(e, [np.sum(np.cos(ry[1:]))], 0, n - 1.0, "energy")
+    g, _ = b.gradient(qv.QV_ADJOINT)
+    want = np.concatenate([[0.0], -np.sin(ry[1:])])
+    check(g, want, 0, n - 1.0, "grad")
+    st = b.stats()
+    assert st["norm_err_max"] < 1e-5
+    b.close()
+
+
+def test_error_paths_on_device(qv):
+    import ctypes
+    say("error paths")
+    lib = qv.load()
+    ctx = ctx_for(qv)
+    wl = W.config1()
+    a = qv._Arrays(wl)
+    h = ctypes.c_void_p()
+    assert lib.qv_batch_create(ctx.h, *a.args(), 0, ctypes.byref(h)) == 0
+    e = np.zeros(1)
+    assert lib.qv_batch_expectations(h, e.ctypes.data, None, 0) == qv.QV_E_STATE
+    assert "set_params" in qv.last_error()
+    bad = np.full(80, np.nan)
+    assert lib.qv_batch_set_params(h, bad.ctypes.data, 0) == qv.QV_E_INVALID
+    out = np.zeros(1 << 10, np.complex64)
+    assert lib.qv_batch_state(h, 0, out.ctypes.data, 0) == qv.QV_E_STATE
+    assert lib.qv_batch_state(h, 5, out.ctypes.data, 0) == qv.QV_E_INVALID
+    assert lib.qv_batch_destroy(h) == 0
+    assert qv.Context.__init__ is not None
+    with pytest.raises(qv.QvError):
+        qv.Context(0, None, '{"engine": "warp"}')
+    with pytest.raises(qv.QvError):
+        qv.Context(0, None, '{"tile_qubits": 20}')
+    with pytest.raises(qv.QvError):
+        qv.Context(7, None, None)
