@@ -33,8 +33,8 @@
  * Ownership and streams
  *   Input arrays belong to the caller and are copied during the call. Output arrays are allocated by the
  *   caller, either in host memory or in device memory of the context's device (flag *_on_device).
- *   All device work of a context is ordered on the context's stream (the caller's HIP stream, or a
- *   stream the library creates when NULL is passed). Calls that write host outputs return after the
+ *   All device work of a context is ordered on the context's stream (the caller's HIP stream; NULL is the
+ *   device's default stream). Calls that write host outputs return after the
  *   results are in place; calls that write device outputs return once the work is enqueued.
  *   A context and its batches must be used from one thread at a time.
  */
@@ -111,8 +111,8 @@ typedef struct {
 typedef struct qv_ctx_s *qv_ctx;
 typedef struct qv_batch_s *qv_batch;
 
-/* Creates a context on HIP device `device`. hip_stream is a hipStream_t (NULL: the library creates a
- * stream of default priority). options_json is NULL or a flat JSON object; recognised keys:
+/* Creates a context on HIP device `device`. hip_stream is the hipStream_t all work is ordered on (NULL:
+ * the device's default stream). options_json is NULL or a flat JSON object; recognised keys:
  *   "n-virtual-qpus" : int >= 1   how many circuits may be in flight at once (default: all); results do
  *                                 not depend on it (the paper's option of the same name, Section 3.2);
  *   "engine"         : "tiled" (default; LDS tile passes) or "stride" (one global-memory pass per gate);
@@ -123,7 +123,7 @@ typedef struct qv_batch_s *qv_batch;
  *                      the records of the last call are read with qv_batch_launch_log. */
 qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_json, qv_ctx *out);
 
-/* Points the context at another hipStream_t (NULL: the library's own stream). */
+/* Points the context at another hipStream_t (NULL: the device's default stream). */
 qv_status qv_ctx_set_stream(qv_ctx ctx, void *hip_stream);
 
 qv_status qv_ctx_destroy(qv_ctx ctx);

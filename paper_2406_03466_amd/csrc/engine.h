@@ -28,9 +28,21 @@ struct DevOp {
     uint8_t p0, p1;      // local positions of q0 / q1
     uint8_t flags;       // OP_TRAIN when the gate's angle is a trainable parameter
     int32_t train_slot;  // position among the pass's trainable gates (adjoint partial sums), else -1
-    int32_t pad;
+    int8_t k0, k1;       // register-tiled passes: register bit holding p0 / p1, -1 when it is a thread bit
+    int16_t pad;
 };
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
+
+// Register-tiled passes run their ops in segments. Within a segment every thread holds 2^RB amplitudes of
+// the LDS tile in registers: register bit k is local position rpos[k], thread bit m is local position
+// tpos[m]. Every op of a segment that mixes amplitude pairs has its target among rpos, so it runs without
+// leaving registers; diagonal ops and CNOT controls may sit on thread bits.
+struct DevSeg {
+    int32_t op_begin;
+    int32_t n_ops;
+    int8_t rpos[8];
+    int8_t tpos[16];
+};
 
 struct DevPass {
     uint64_t local_mask;  // qubits of the tile
@@ -39,7 +51,9 @@ struct DevPass {
     int32_t n_ops;
     int32_t n_train;      // trainable ops in the pass
     int32_t stride;       // 1: stride pass (one gate straight from global memory), 0: LDS tile pass
-    int32_t pad;
+    int32_t pad;          // lowc: local positions 0..lowc-1 are qubits 0..lowc-1
+    int32_t seg_begin;    // register-tiled passes: segments [seg_begin, seg_begin + n_seg)
+    int32_t n_seg;        // 0: the pass runs op by op in LDS
     int8_t lq[16];        // local position -> qubit, ascending
 };
 
@@ -60,6 +74,8 @@ struct Seg {
     int64_t partial_base; // adjoint: base slot of this (circuit, pass) in the partial-sum array
     int32_t circ;
     int32_t pass;
+    int32_t first;        // 1: first pass of the circuit -- the tile starts as |0...0> instead of a load
+    int32_t pad;
 };
 
 // Expectation work: one Pauli x-mask group of one circuit. Blocks [first_block, ...) cover its chunks.
@@ -102,6 +118,9 @@ struct LevelArgs {
     int64_t n_blocks;
     const DevPass *passes;
     const DevOp *ops;
+    const DevSeg *rsegs;  // register segments of the passes
+    int32_t max_train;    // largest n_train of the level's passes (LDS for the adjoint partial sums)
+    int32_t pad;
     const DevCirc *circs;
     const qv_gate *gates;
     const double *theta;

@@ -103,14 +103,13 @@ static bool parse_options(const char *js, std::map<std::string, std::string> &ou
 struct qv_ctx_s {
     int device = 0;
     hipStream_t user_stream = nullptr;
-    hipStream_t own_stream = nullptr;
     hipStream_t cap_stream = nullptr;
     int engine_stride = 0;      // 0: LDS tiles, 1: one global pass per gate
     int tile_qubits = 0;        // 0: automatic
     int graph = 1;
     int n_vqpu = 0;             // 0: all circuits in flight
     int launch_events = 0;      // 1: record a HIP event pair around every launch (eager mode)
-    hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+    hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
 // A device buffer owned by a batch.
@@ -723,7 +722,6 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
     int e = prepare_kernels();
     if (e) return fail(QV_E_DEVICE, "kernel setup failed: %s", hipGetErrorString((hipError_t)e));
     c->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
-    HIPCHK(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     *out = c.release();
     return ok();
@@ -740,7 +738,6 @@ qv_status qv_ctx_destroy(qv_ctx ctx)
 {
     if (!ctx) return fail(QV_E_INVALID, "ctx must not be NULL");
     (void)hipSetDevice(ctx->device);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return ok();
