@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ps", action="store_true")
     ap.add_argument("--tile-qubits", type=int, default=0)
+    ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the whole batch is one GPU's share; "
@@ -107,7 +108,7 @@ def main():
     torch.cuda.set_device(dev)
     wl = W.config3(args.layers)
     stream = torch.cuda.current_stream(dev)
-    opts = {"graph": False, "launch_events": True}
+    opts = {"graph": False, "launch_events": True, "engine": args.engine}
     if args.tile_qubits:
         opts["tile_qubits"] = args.tile_qubits
     ctx = qvpu.Context(0, stream.cuda_stream, json.dumps(opts))
@@ -143,7 +144,8 @@ def main():
     dom = max(per, key=lambda k: per[k]["ms"])
     d = per[dom]
     achieved = d["gbs"]
-    kernel_sym = {"tile_adj": "k_tile<float,true>", "tile": "k_tile<float,false>"}.get(dom, dom)
+    kernel_sym = {"tile_adj": "k_tile<float,true>", "tile": "k_tile<float,false>",
+                  "rtile_adj": "k_rtile<float,true,5>", "rtile": "k_rtile<float,false,5>"}.get(dom, dom)
     workload_tag = f"qcl20_L{args.layers}"
     traffic = pmc_traffic(dom, workload_tag)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -151,7 +153,8 @@ def main():
                 "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
                 "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
     # forward-only circuit evals/s (the 64 circuits of one forward pass)
-    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("init", "tile", "expect", "finalize")) / args.steps
+    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("init", "tile", "rtile", "stride", "expect",
+                                                          "finalize")) / args.steps
     circuit_evals_per_s = wl.B / (fwd_ms / 1e3)
 
     extra = {}
@@ -215,7 +218,7 @@ def main():
                                f"RY(arcsin x) encoding + {args.layers} HEA layers ({wl.n_grad()} params), "
                                f"<Z_0>, MSE loss, adjoint gradient, complex64 with FP64 reductions",
                    "qubits": 20, "layers": args.layers, "samples": 64, "params": wl.n_grad(),
-                   "precision": "c64", "tile_qubits": args.tile_qubits or "auto"},
+                   "precision": "c64", "tile_qubits": args.tile_qubits or "auto", "engine": args.engine},
         "roofline": roofline,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1)}

@@ -95,7 +95,9 @@ typedef enum {
     QV_K_FINALIZE = 6,      /* term values and energies from partial sums */
     QV_K_LAMBDA = 7,        /* adjoint seed lambda = w H psi */
     QV_K_GRAD_REDUCE = 8,   /* adjoint gradient from partial sums */
-    QV_K_SHIFT_COMBINE = 9  /* parameter-shift gradient from shifted energies */
+    QV_K_SHIFT_COMBINE = 9, /* parameter-shift gradient from shifted energies */
+    QV_K_RTILE = 10,        /* register-tiled LDS pass, forward */
+    QV_K_RTILE_ADJ = 11     /* register-tiled LDS pass, adjoint reverse sweep */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -115,7 +117,9 @@ typedef struct qv_batch_s *qv_batch;
  * the device's default stream). options_json is NULL or a flat JSON object; recognised keys:
  *   "n-virtual-qpus" : int >= 1   how many circuits may be in flight at once (default: all); results do
  *                                 not depend on it (the paper's option of the same name, Section 3.2);
- *   "engine"         : "tiled" (default; LDS tile passes) or "stride" (one global-memory pass per gate);
+ *   "engine"         : "tiled" (default: LDS tile passes whose gates run on register-resident segments),
+ *                      "lds" (LDS tile passes, one gate at a time in LDS) or "stride" (one global-memory
+ *                      pass per gate);
  *   "tile_qubits"    : int 6..14 or "auto" (default "auto": the autotuner's choice);
  *   "launch"         : "levels" (one launch per pass level, default) or "persistent";
  *   "graph"          : true (default) to capture each call's launches in a hipGraph and replay it;

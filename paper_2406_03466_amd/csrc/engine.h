@@ -18,6 +18,8 @@ constexpr int kBlock = 256;          // threads per workgroup for every kernel
 constexpr int kMaxGroupTerms = 8;    // Pauli terms evaluated together by one expectation item
 constexpr int kExpChunkLog2 = 12;    // amplitude pairs per expectation workgroup (4096)
 constexpr int kStrideGroupsPerBlock = 1024;
+constexpr int kRegBitsC64 = 5;       // register-tiled passes: 32 complex64 amplitudes per thread
+constexpr int kRegBitsC128 = 4;      // 16 complex128 amplitudes per thread
 
 enum OpFlags : uint8_t { OP_TRAIN = 1 };
 
@@ -186,6 +188,7 @@ struct ShiftCombineArgs {
 // Launchers (kernels.hip). All return hipSuccess or the launch error.
 int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_stride_level(const LevelArgs &a, int precision, int adjoint, void *stream);
+int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_init_states(void *psi, const DevCirc *circs, const int64_t *first_block, int32_t n_circ,
                        int64_t n_blocks, int precision, void *stream);
 int launch_expectation(const ExpArgs &a, int precision, void *stream);

@@ -197,6 +197,14 @@ __global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
     Cx<R> *glam = ADJ ? reinterpret_cast<Cx<R> *>(a.lam) + C.state_off : nullptr;
     const uint32_t lmask = (1u << lowc) - 1u;
     for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+        if (!ADJ && sg.first) {
+            // first pass of the circuit: the tile of |0...0> is zero except amplitude 0 of tile 0
+            Cx<R> z;
+            z.re = (R)((base == 0 && e == 0) ? 1 : 0);
+            z.im = (R)0;
+            sp[e] = z;
+            continue;
+        }
         const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
         sp[e] = gpsi[g];
         if (ADJ) sl[e] = glam[g];
@@ -258,6 +266,340 @@ __global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
         const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
         gpsi[g] = sp[e];
         if (ADJ) glam[g] = sl[e];
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Register-tiled pass. The tile sits in LDS (XOR-swizzled so that any quarter wave touches distinct
+// banks); each register segment loads 2^RB amplitudes per thread into registers, runs its ops there and
+// stores them back. A rotation or CNOT target is always a register qubit of its segment, so those ops
+// need no data exchange; diagonal ops and CNOT controls on thread qubits use the thread's own index bits.
+// ------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t swz(uint32_t e)
+{
+    return e ^ (((e >> 4) ^ (e >> 8) ^ (e >> 12)) & 15u);
+}
+
+// Bit j of reg_pattern(k) is bit k of j: the registers whose index has register bit k set.
+__device__ __forceinline__ uint32_t reg_pattern(int k)
+{
+    return k == 0 ? 0xAAAAAAAAu : k == 1 ? 0xCCCCCCCCu : k == 2 ? 0xF0F0F0F0u : k == 3 ? 0xFF00FF00u : 0xFFFF0000u;
+}
+
+// Runs STMT with the compile-time register bit K equal to the runtime value k (0 <= k < RB).
+#define WITH_K(RB_, k, STMT)                                                 \
+    switch (k) {                                                             \
+    case 0: { constexpr int K = 0; STMT; } break;                            \
+    case 1: { constexpr int K = 1; STMT; } break;                            \
+    case 2: { constexpr int K = 2; STMT; } break;                            \
+    case 3: { constexpr int K = 3; STMT; } break;                            \
+    default: { constexpr int K = (RB_) > 4 ? 4 : 0; if ((RB_) > 4) { STMT; } } break; \
+    }
+
+// [[c, -s], [s, c]] on register bit K (RY and its inverse).
+template <int K, int N, typename R>
+__device__ __forceinline__ void r_real(Cx<R> (&v)[N], R c, R s)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (j & (1 << K)) continue;
+        const int j1 = j | (1 << K);
+        const Cx<R> x = v[j], y = v[j1];
+        v[j].re = c * x.re - s * y.re;
+        v[j].im = c * x.im - s * y.im;
+        v[j1].re = s * x.re + c * y.re;
+        v[j1].im = s * x.im + c * y.im;
+    }
+}
+
+template <int K, int N, typename R>
+__device__ __forceinline__ void r_gen(Cx<R> (&v)[N], const M2<R> &m)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (j & (1 << K)) continue;
+        apply2(m, v[j], v[j | (1 << K)]);
+    }
+}
+
+// diag(d0, d1) on register bit K.
+template <int K, int N, typename R>
+__device__ __forceinline__ void r_diag(Cx<R> (&v)[N], R d0r, R d0i, R d1r, R d1i)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const R dr = (j & (1 << K)) ? d1r : d0r, di = (j & (1 << K)) ? d1i : d0i;
+        const Cx<R> x = v[j];
+        v[j].re = dr * x.re - di * x.im;
+        v[j].im = dr * x.im + di * x.re;
+    }
+}
+
+template <int N, typename R>
+__device__ __forceinline__ void t_scale(Cx<R> (&v)[N], R dr, R di)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const Cx<R> x = v[j];
+        v[j].re = dr * x.re - di * x.im;
+        v[j].im = dr * x.im + di * x.re;
+    }
+}
+
+// CNOT with target register bit KT; the control is register j's bit of m (pair j, j | 2^KT).
+template <int KT, int N, typename R>
+__device__ __forceinline__ void r_cnot_mask(Cx<R> (&v)[N], uint32_t m)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (j & (1 << KT)) continue;
+        const int j1 = j | (1 << KT);
+        const bool c = (m >> j) & 1u;
+        const Cx<R> x = v[j], y = v[j1];
+        v[j] = c ? y : x;
+        v[j1] = c ? x : y;
+    }
+}
+
+// CNOT with target register bit KT, control given per thread.
+template <int KT, int N, typename R>
+__device__ __forceinline__ void t_cnot(Cx<R> (&v)[N], bool ctl)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (j & (1 << KT)) continue;
+        const int j1 = j | (1 << KT);
+        const Cx<R> x = v[j], y = v[j1];
+        v[j] = ctl ? y : x;
+        v[j1] = ctl ? x : y;
+    }
+}
+
+// Negates register j where bit j of m is set.
+template <int N, typename R>
+__device__ __forceinline__ void neg_mask(Cx<R> (&v)[N], uint32_t m)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (m >> j & 1u) {
+            v[j].re = -v[j].re;
+            v[j].im = -v[j].im;
+        }
+    }
+}
+
+// Im <l| G |a> over the register pairs of bit K, G the generator of the rotation kind. FP64.
+template <int K, int N, typename R>
+__device__ __forceinline__ double r_inner(int kind, const Cx<R> (&a)[N], const Cx<R> (&l)[N])
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (j & (1 << K)) continue;
+        const int j1 = j | (1 << K);
+        acc += gen_inner<R>(kind, a[j], a[j1], l[j], l[j1]);
+    }
+    return acc;
+}
+
+// Im <l| Z_p |a> when qubit p is a thread bit with value `bit`.
+template <int N, typename R>
+__device__ __forceinline__ double t_inner_z(const Cx<R> (&a)[N], const Cx<R> (&l)[N], int bit)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++)
+        acc += (double)l[j].re * (double)a[j].im - (double)l[j].im * (double)a[j].re;
+    return bit ? -acc : acc;
+}
+
+// One op applied to the registers v (the inverse when INV).
+template <bool INV, int RB, typename R>
+__device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, int kind, double ang, uint32_t Et)
+{
+    constexpr int N = 1 << RB;
+    if (kind == QV_CNOT) {
+        if (op.k0 >= 0) {
+            // control on a register bit: a per-register mask, so every pair swap is a select
+            const uint32_t m = reg_pattern(op.k0);
+            WITH_K(RB, op.k1, r_cnot_mask<K>(v, m));
+        } else {
+            const bool ctl = (Et >> op.p0) & 1u;
+            WITH_K(RB, op.k1, t_cnot<K>(v, ctl));
+        }
+        return;
+    }
+    if (kind == QV_CZ) {
+        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
+        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
+        neg_mask(v, ma & mb);
+        return;
+    }
+    if (kind == QV_RY) {
+        double s, c;
+        sincos(0.5 * ang, &s, &c);
+        const R cr = (R)c, sr = INV ? (R)(-s) : (R)s;
+        WITH_K(RB, op.k0, r_real<K>(v, cr, sr));
+        return;
+    }
+    if (kind == QV_RZ || kind == QV_Z || kind == QV_S || kind == QV_T) {
+        double d0r = 1, d0i = 0, d1r = 1, d1i = 0;
+        if (kind == QV_RZ) {
+            double s, c;
+            sincos(0.5 * ang, &s, &c);
+            d0r = c; d0i = -s; d1r = c; d1i = s;
+        } else if (kind == QV_Z) {
+            d1r = -1;
+        } else if (kind == QV_S) {
+            d1r = 0; d1i = 1;
+        } else {
+            d1r = 0.70710678118654752440; d1i = 0.70710678118654752440;
+        }
+        if (INV) { d0i = -d0i; d1i = -d1i; }
+        if (op.k0 >= 0) {
+            WITH_K(RB, op.k0, r_diag<K>(v, (R)d0r, (R)d0i, (R)d1r, (R)d1i));
+        } else {
+            const bool b = (Et >> op.p0) & 1u;
+            t_scale(v, (R)(b ? d1r : d0r), (R)(b ? d1i : d0i));
+        }
+        return;
+    }
+    M2d md;
+    gate_matrix(kind, ang, md);
+    if (INV) dagger(md);
+    const M2<R> m = narrow<R>(md);
+    WITH_K(RB, op.k0, r_gen<K>(v, m));
+}
+
+template <typename R, bool ADJ, int RB>
+__global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
+{
+    constexpr int N = 1 << RB;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
+    const int64_t tile = blk - sg.first_block;
+    const DevPass P = a.passes[sg.pass];
+    const DevCirc C = a.circs[sg.circ];
+    const int n = C.n, t = P.t, lowc = P.pad;
+    const uint32_t T = 1u << t;
+    const int TL = 1 << (a.lds_t);
+
+    Cx<R> *sp = reinterpret_cast<Cx<R> *>(smem);
+    Cx<R> *sl = sp + (ADJ ? TL : 0);
+    uint64_t *segtab = reinterpret_cast<uint64_t *>(sp + (ADJ ? 2 * TL : TL));
+    const int tab_bits = a.lds_t > 3 ? a.lds_t - 3 : 0;
+    double *red = reinterpret_cast<double *>(segtab + (1 << tab_bits));
+
+    const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    const uint64_t base = deposit((uint64_t)tile, full & ~P.local_mask);
+    const uint64_t himask = P.local_mask & ~((1ull << lowc) - 1ull);
+    const uint32_t nh = 1u << (t - lowc);
+    const uint32_t lmask = (1u << lowc) - 1u;
+    Cx<R> *gpsi = reinterpret_cast<Cx<R> *>(a.psi) + C.state_off;
+    Cx<R> *glam = ADJ ? reinterpret_cast<Cx<R> *>(a.lam) + C.state_off : nullptr;
+
+    if (!ADJ && sg.first) {
+        // first pass of the circuit: the tile of |0...0> is zero except amplitude 0 of tile 0
+        for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+            Cx<R> z;
+            z.re = (R)((base == 0 && e == 0) ? 1 : 0);
+            z.im = (R)0;
+            sp[swz(e)] = z;
+        }
+    } else {
+        for (uint32_t h = threadIdx.x; h < nh; h += kBlock) segtab[h] = deposit(h, himask);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+            const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+            sp[swz(e)] = gpsi[g];
+            if (ADJ) sl[swz(e)] = glam[g];
+        }
+    }
+    __syncthreads();
+
+    const int tbits = t - RB;
+    const uint32_t tmask = (1u << tbits) - 1u;
+    const bool active = threadIdx.x <= tmask;
+    const uint32_t tid = threadIdx.x & tmask;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    for (int s0 = 0; s0 < P.n_seg; s0++) {
+        const int si = ADJ ? P.n_seg - 1 - s0 : s0;
+        const DevSeg S = a.rsegs[P.seg_begin + si];
+        uint32_t Et = 0;
+#pragma unroll
+        for (int m = 0; m < 16; m++)
+            if (m < tbits && (tid >> m & 1u)) Et |= 1u << S.tpos[m];
+        const uint32_t PE = swz(Et);
+        uint32_t rbit[RB];
+#pragma unroll
+        for (int k = 0; k < RB; k++) rbit[k] = 1u << S.rpos[k];
+        Cx<R> av[N], lv[N];
+#pragma unroll
+        for (int j = 0; j < N; j++) {
+            uint32_t D = 0;
+#pragma unroll
+            for (int k = 0; k < RB; k++)
+                if (j >> k & 1) D |= rbit[k];
+            const uint32_t addr = PE ^ swz(D);
+            av[j] = sp[addr];
+            if (ADJ) lv[j] = sl[addr];
+        }
+        for (int k0 = 0; k0 < S.n_ops; k0++) {
+            const int k = ADJ ? S.n_ops - 1 - k0 : k0;
+            const DevOp op = a.ops[S.op_begin + k];
+            int kind;
+            const double ang = op_angle(a, C, op, kind);
+            if (ADJ) {
+                if (op.flags & OP_TRAIN) {
+                    double ip;
+                    if (kind == QV_RZ && op.k0 < 0) {
+                        ip = t_inner_z(av, lv, (int)((Et >> op.p0) & 1u));
+                    } else {
+                        ip = 0.0;
+                        WITH_K(RB, op.k0, ip = r_inner<K>(kind, av, lv));
+                    }
+                    if (!active) ip = 0.0;
+                    for (int o = 32; o > 0; o >>= 1) ip += __shfl_xor(ip, o, 64);
+                    if (lane == 0) red[op.train_slot * (kBlock / 64) + wave] = ip;
+                }
+                rop_apply<true, RB, R>(av, op, kind, ang, Et);
+                rop_apply<true, RB, R>(lv, op, kind, ang, Et);
+            } else {
+                rop_apply<false, RB, R>(av, op, kind, ang, Et);
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < N; j++) {
+                uint32_t D = 0;
+#pragma unroll
+                for (int k = 0; k < RB; k++)
+                    if (j >> k & 1) D |= rbit[k];
+                const uint32_t addr = PE ^ swz(D);
+                sp[addr] = av[j];
+                if (ADJ) sl[addr] = lv[j];
+            }
+        }
+        __syncthreads();
+    }
+
+    if (ADJ) {
+        for (int slot = threadIdx.x; slot < P.n_train; slot += kBlock) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; w++) s += red[slot * (kBlock / 64) + w];
+            a.partials[sg.partial_base + tile * P.n_train + slot] = s;
+        }
+    }
+    if (sg.first && !ADJ) {
+        for (uint32_t h = threadIdx.x; h < nh; h += kBlock) segtab[h] = deposit(h, himask);
+        __syncthreads();
+    }
+    for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+        const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+        gpsi[g] = sp[swz(e)];
+        if (ADJ) glam[g] = sl[swz(e)];
     }
 }
 
@@ -537,7 +879,38 @@ int prepare_kernels()
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<double, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<float, false, kRegBitsC64>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<float, true, kRegBitsC64>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<double, false, kRegBitsC128>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<double, true, kRegBitsC128>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     return e;
+}
+
+int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int amp = precision == QV_C64 ? 8 : 16;
+    const size_t lds = tile_lds_bytes(a.lds_t, amp, adjoint) +
+                       (adjoint ? sizeof(double) * (kBlock / 64) * (size_t)a.max_train : 0);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    dim3 grid((unsigned)a.n_blocks), block(kBlock);
+    if (precision == QV_C64) {
+        if (adjoint) hipLaunchKernelGGL((k_rtile<float, true, kRegBitsC64>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_rtile<float, false, kRegBitsC64>), grid, block, lds, s, a);
+    } else {
+        if (adjoint) hipLaunchKernelGGL((k_rtile<double, true, kRegBitsC128>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_rtile<double, false, kRegBitsC128>), grid, block, lds, s, a);
+    }
+    return hipGetLastError();
 }
 
 int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream)

@@ -3,6 +3,9 @@
 // can move ahead of unscheduled gates it shares no qubit with). The greedy loop below walks the
 // unscheduled gates in program order, growing the local set while it has room; once a gate cannot join,
 // its qubits are blocked for the rest of the pass so that later gates on them keep their order.
+// Register segments split a pass the same way one level down: a segment holds 2^reg_bits amplitudes
+// per thread, and a gate joins it when the qubit it mixes (a rotation's qubit, a CNOT's target) is one of
+// the segment's register qubits.
 #include "planner.h"
 
 #include <algorithm>
@@ -10,6 +13,18 @@
 namespace qv {
 
 static bool two_qubit(int kind) { return kind == QV_CNOT || kind == QV_CZ; }
+
+static bool diagonal(int kind)
+{
+    return kind == QV_Z || kind == QV_S || kind == QV_T || kind == QV_RZ || kind == QV_CZ;
+}
+
+static void number_train_slots(PlanPass &pp)
+{
+    int slot = 0;
+    for (PlanOp &op : pp.ops) op.train_slot = op.train_slot >= 0 ? slot++ : -1;
+    pp.n_train = slot;
+}
 
 static void finish_pass(PlanPass &pp, int n)
 {
@@ -19,12 +34,78 @@ static void finish_pass(PlanPass &pp, int n)
     pp.t = (int)pp.lq.size();
     pp.lowc = 0;
     while (pp.lowc < pp.t && pp.lq[pp.lowc] == pp.lowc) pp.lowc++;
-    int slot = 0;
-    for (PlanOp &op : pp.ops) op.train_slot = op.train_slot >= 0 ? slot++ : -1;
-    pp.n_train = slot;
+    number_train_slots(pp);
 }
 
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc)
+void segment_pass(PlanPass &pp, int reg_bits)
+{
+    pp.segs.clear();
+    if (reg_bits <= 0 || pp.t < reg_bits || pp.stride) return;
+    int pos[64];
+    for (int i = 0; i < 64; i++) pos[i] = -1;
+    for (size_t i = 0; i < pp.lq.size(); i++) pos[pp.lq[i]] = (int)i;
+    const int G = (int)pp.ops.size();
+    std::vector<char> done(G, 0);
+    std::vector<PlanOp> order;
+    order.reserve(G);
+    int remaining = G, first = 0;
+    while (remaining > 0) {
+        PlanSeg sg;
+        sg.op_begin = (int)order.size();
+        uint32_t R = 0, blocked = 0;
+        int nr = 0;
+        while (first < G && done[first]) first++;
+        for (int g = first; g < G; g++) {
+            if (done[g]) continue;
+            const PlanOp &op = pp.ops[g];
+            const int a = pos[op.q0], b = two_qubit(op.kind) ? pos[op.q1] : -1;
+            const uint32_t qs = (1u << a) | (b >= 0 ? (1u << b) : 0u);
+            if (qs & blocked) { blocked |= qs; continue; }
+            uint32_t need = 0;
+            if (op.kind == QV_CNOT) need = 1u << b;
+            else if (!diagonal(op.kind)) need = 1u << a;
+            need &= ~R;
+            const int add = __builtin_popcount(need);
+            if (nr + add <= reg_bits) {
+                R |= need;
+                nr += add;
+                done[g] = 1;
+                remaining--;
+                order.push_back(op);
+            } else {
+                blocked |= qs;
+            }
+        }
+        sg.n_ops = (int)order.size() - sg.op_begin;
+        // register qubits: the ones the segment needs, then the lowest free positions
+        for (int p = 0; p < pp.t; p++)
+            if (R >> p & 1u) sg.rpos.push_back(p);
+        for (int p = 0; p < pp.t && (int)sg.rpos.size() < reg_bits; p++)
+            if (!(R >> p & 1u)) { sg.rpos.push_back(p); R |= 1u << p; }
+        // thread bits: the four lowest lanes on positions with distinct (position mod 4), so a quarter
+        // wave's LDS accesses fall in distinct banks under the tile's XOR swizzle; the rest ascending
+        std::vector<int> rest;
+        for (int p = 0; p < pp.t; p++)
+            if (!(R >> p & 1u)) rest.push_back(p);
+        uint32_t used_mod = 0;
+        for (int m = 0; m < 4 && !rest.empty(); m++) {
+            size_t pick = 0;
+            bool found = false;
+            for (size_t i = 0; i < rest.size(); i++)
+                if (!(used_mod >> (rest[i] & 3) & 1u)) { pick = i; found = true; break; }
+            if (!found) break;
+            used_mod |= 1u << (rest[pick] & 3);
+            sg.tpos.push_back(rest[pick]);
+            rest.erase(rest.begin() + (long)pick);
+        }
+        for (int p : rest) sg.tpos.push_back(p);
+        pp.segs.push_back(sg);
+    }
+    pp.ops = order;
+    number_train_slots(pp);
+}
+
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits)
 {
     Plan pl;
     const int n = in.n;
@@ -39,22 +120,16 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc)
         op.train_slot = in.trainable[g] ? 0 : -1;
         return op;
     };
-    if (n <= tile_qubits) {
-        PlanPass pp;
-        pp.local_mask = full;
-        for (int g = 0; g < G; g++) pp.ops.push_back(mk_op(g));
-        finish_pass(pp, n);
-        pl.passes.push_back(pp);
-        return pl;
-    }
     lowc = std::min(lowc, n);
     std::vector<char> done(G, 0);
     int remaining = G;
     int first = 0;
+    const bool whole = n <= tile_qubits;
     while (remaining > 0) {
         PlanPass pp;
-        uint64_t L = (1ull << lowc) - 1ull;
-        int cnt = lowc;
+        uint64_t L = whole ? full : (1ull << lowc) - 1ull;
+        int cnt = whole ? n : lowc;
+        int ntrain = 0;
         uint64_t blocked = 0;
         while (first < G && done[first]) first++;
         for (int g = first; g < G; g++) {
@@ -63,11 +138,13 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc)
             if (qs & blocked) { blocked |= qs; continue; }
             const uint64_t need = qs & ~L;
             const int add = __builtin_popcountll(need);
-            if (cnt + add <= tile_qubits) {
+            const bool train_full = in.trainable[g] && ntrain >= kMaxTrainPerPass;
+            if (cnt + add <= tile_qubits && !train_full) {
                 L |= need;
                 cnt += add;
                 done[g] = 1;
                 remaining--;
+                ntrain += in.trainable[g] ? 1 : 0;
                 pp.ops.push_back(mk_op(g));
             } else {
                 blocked |= qs;
@@ -78,6 +155,7 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc)
             if (!(L >> q & 1ull)) { L |= 1ull << q; cnt++; }
         pp.local_mask = L;
         finish_pass(pp, n);
+        segment_pass(pp, reg_bits);
         pl.passes.push_back(pp);
     }
     return pl;
@@ -104,7 +182,7 @@ Plan plan_stride(const PlanInput &in)
     return pl;
 }
 
-void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops)
+void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops, std::vector<DevSeg> &segs)
 {
     for (const PlanPass &pp : pl.passes) {
         DevPass d{};
@@ -115,11 +193,18 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
         d.n_train = pp.n_train;
         d.stride = pp.stride;
         d.pad = pp.lowc;
+        d.seg_begin = (int32_t)segs.size();
+        d.n_seg = (int32_t)pp.segs.size();
         for (int i = 0; i < 16; i++) d.lq[i] = i < (int)pp.lq.size() ? (int8_t)pp.lq[i] : (int8_t)-1;
         int pos[64];
         for (int i = 0; i < 64; i++) pos[i] = -1;
         for (size_t i = 0; i < pp.lq.size(); i++) pos[pp.lq[i]] = (int)i;
-        for (const PlanOp &op : pp.ops) {
+        // register index of each local position, per segment
+        std::vector<int> seg_of(pp.ops.size(), -1);
+        for (size_t s = 0; s < pp.segs.size(); s++)
+            for (int k = 0; k < pp.segs[s].n_ops; k++) seg_of[pp.segs[s].op_begin + k] = (int)s;
+        for (size_t i = 0; i < pp.ops.size(); i++) {
+            const PlanOp &op = pp.ops[i];
             DevOp o{};
             o.gate = op.gate;
             o.kind = (uint8_t)op.kind;
@@ -132,8 +217,25 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
             }
             o.flags = op.train_slot >= 0 ? OP_TRAIN : 0;
             o.train_slot = op.train_slot;
+            o.k0 = -1;
+            o.k1 = -1;
+            if (seg_of[i] >= 0) {
+                const PlanSeg &sg = pp.segs[seg_of[i]];
+                for (size_t k = 0; k < sg.rpos.size(); k++) {
+                    if (sg.rpos[k] == o.p0) o.k0 = (int8_t)k;
+                    if (op.q1 >= 0 && sg.rpos[k] == o.p1) o.k1 = (int8_t)k;
+                }
+            }
             o.pad = 0;
             ops.push_back(o);
+        }
+        for (const PlanSeg &sg : pp.segs) {
+            DevSeg ds{};
+            ds.op_begin = d.op_begin + sg.op_begin;
+            ds.n_ops = sg.n_ops;
+            for (int k = 0; k < 8; k++) ds.rpos[k] = k < (int)sg.rpos.size() ? (int8_t)sg.rpos[k] : (int8_t)-1;
+            for (int m = 0; m < 16; m++) ds.tpos[m] = m < (int)sg.tpos.size() ? (int8_t)sg.tpos[m] : (int8_t)-1;
+            segs.push_back(ds);
         }
         passes.push_back(d);
     }

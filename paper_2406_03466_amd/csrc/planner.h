@@ -21,6 +21,14 @@ struct PlanOp {
     int train_slot;  // position among the pass's trainable gates, -1 if fixed
 };
 
+// A register segment of a pass (see DevSeg in engine.h): positions are local.
+struct PlanSeg {
+    std::vector<int> rpos;  // register bit -> local position
+    std::vector<int> tpos;  // thread bit -> local position
+    int op_begin = 0;       // first op of the segment in the pass's (reordered) op list
+    int n_ops = 0;
+};
+
 struct PlanPass {
     uint64_t local_mask = 0;
     int t = 0;
@@ -28,20 +36,30 @@ struct PlanPass {
     int stride = 0;   // 1: a single gate applied straight from global memory
     int n_train = 0;
     std::vector<int> lq;      // local position -> qubit (ascending)
-    std::vector<PlanOp> ops;  // in program order
+    std::vector<PlanOp> ops;  // in program order (register-tiled passes: in segment order)
+    std::vector<PlanSeg> segs;  // empty: the pass runs op by op in LDS
 };
 
 struct Plan {
     std::vector<PlanPass> passes;
 };
 
+// Most trainable gates one pass may hold (their adjoint partial sums live in LDS).
+constexpr int kMaxTrainPerPass = 512;
+
 // LDS tile plan with tiles of at most `tile_qubits` qubits, the lowest `lowc` qubits always local.
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc);
+// reg_bits > 0 splits every pass of at least reg_bits qubits into register segments of 2^reg_bits
+// amplitudes per thread.
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0);
+
+// Splits one pass into register segments (reorders its ops; dependencies are kept).
+void segment_pass(PlanPass &pp, int reg_bits);
 
 // One stride pass per gate.
 Plan plan_stride(const PlanInput &in);
 
 // Appends a plan's passes and ops in device form.
-void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops);
+void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops,
+                std::vector<DevSeg> &segs);
 
 }  // namespace qv

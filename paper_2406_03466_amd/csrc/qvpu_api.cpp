@@ -104,7 +104,7 @@ struct qv_ctx_s {
     int device = 0;
     hipStream_t user_stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    int engine_stride = 0;      // 0: LDS tiles, 1: one global pass per gate
+    int engine = 0;             // 0: register tiles, 1: op-by-op LDS tiles, 2: one global pass per gate
     int tile_qubits = 0;        // 0: automatic
     int graph = 1;
     int n_vqpu = 0;             // 0: all circuits in flight
@@ -137,14 +137,23 @@ struct DBuf {
     T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+enum LevelKind { LK_RTILE = 0, LK_TILE = 1, LK_STRIDE = 2 };
+
 struct Level {
     int64_t seg_off;
     int32_t n_segs;
     int64_t n_blocks;
     int32_t lds_t;
-    int32_t stride;
+    int32_t kind;     // LevelKind
     int64_t bytes;    // algorithmic state bytes moved by the launch (read + write)
+    int32_t max_train;
 };
+
+static int pass_kind(const PlanPass &pp)
+{
+    if (pp.stride) return LK_STRIDE;
+    return pp.segs.empty() ? LK_TILE : LK_RTILE;
+}
 
 // Per-launch HIP event log (context option "launch_events"; eager launches only, no graph).
 struct LaunchLog {
@@ -365,42 +374,55 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
         es.passes_fwd += (int64_t)pl.passes.size();
         es.passes_rev += (int64_t)pl.passes.size();
     }
+    // One launch per (depth, kernel kind): passes of the same depth that need different kernels (register
+    // tiles, op-by-op LDS tiles for tiny tiles, stride passes) go to separate launches of that depth.
     for (int w0 = 0; w0 < N; w0 += wave) {
         const int w1 = std::min(N, w0 + wave);
         int maxp = 0;
         for (int c = w0; c < w1; c++) maxp = std::max(maxp, (int)plans[es.plan_of[c]].passes.size());
         for (int dir = 0; dir < 2; dir++) {
             for (int L = 0; L < maxp; L++) {
-                Level lv{(int64_t)es.segs.size(), 0, 0, 0, -1, 0};
-                for (int c = w0; c < w1; c++) {
-                    const Plan &pl = plans[es.plan_of[c]];
-                    const int np = (int)pl.passes.size();
-                    if (L >= np) continue;
-                    const int p = dir == 0 ? L : np - 1 - L;
-                    Seg s;
-                    s.first_block = lv.n_blocks;
-                    s.partial_base = pbase[c][p];
-                    s.circ = c;
-                    s.pass = pass_base[es.plan_of[c]] + p;
-                    es.segs.push_back(s);
-                    lv.n_segs++;
-                    lv.n_blocks += tiles_of(es.circs[c], pl, p);
-                    lv.lds_t = std::max(lv.lds_t, pl.passes[p].t);
-                    lv.bytes += (dir == 0 ? 2 : 4) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
-                    const int st = pl.passes[p].stride;
-                    lv.stride = st;  // a level never mixes engines: the engine is chosen per batch
+                for (int kind = 0; kind < 3; kind++) {
+                    Level lv{(int64_t)es.segs.size(), 0, 0, 0, kind, 0, 0};
+                    for (int c = w0; c < w1; c++) {
+                        const Plan &pl = plans[es.plan_of[c]];
+                        const int np = (int)pl.passes.size();
+                        if (L >= np) continue;
+                        const int p = dir == 0 ? L : np - 1 - L;
+                        const PlanPass &pp = pl.passes[p];
+                        if (pass_kind(pp) != kind) continue;
+                        Seg s;
+                        s.first_block = lv.n_blocks;
+                        s.partial_base = pbase[c][p];
+                        s.circ = c;
+                        s.pass = pass_base[es.plan_of[c]] + p;
+                        s.first = (dir == 0 && p == 0 && !pp.stride) ? 1 : 0;
+                        s.pad = 0;
+                        es.segs.push_back(s);
+                        lv.n_segs++;
+                        lv.n_blocks += tiles_of(es.circs[c], pl, p);
+                        lv.lds_t = std::max(lv.lds_t, pp.t);
+                        lv.max_train = std::max(lv.max_train, pp.n_train);
+                        lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : 4) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
+                    }
+                    if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
                 }
-                if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
             }
         }
     }
-    // init blocks
+    // |0...0> is written by k_init only for circuits whose first pass does not generate it
     es.init_first_block.assign(N + 1, 0);
-    for (int c = 0; c < N; c++)
-        es.init_first_block[c + 1] = es.init_first_block[c] + ((((int64_t)1 << es.circs[c].n) + 4095) / 4096);
-    es.init_blocks = es.init_first_block[N];
     es.init_bytes = 0;
-    for (int c = 0; c < N; c++) es.init_bytes += ((int64_t)1 << es.circs[c].n) * amp_bytes;
+    for (int c = 0; c < N; c++) {
+        const Plan &pl = plans[es.plan_of[c]];
+        const bool needs = pl.passes.empty() || pl.passes[0].stride;
+        const int64_t amps = (int64_t)1 << es.circs[c].n;
+        es.init_first_block[c + 1] = es.init_first_block[c] + (needs ? (amps + 4095) / 4096 : 0);
+        if (needs) es.init_bytes += amps * amp_bytes;
+    }
+    es.init_blocks = es.init_first_block[N];
+    es.algo_bytes_fwd = es.init_bytes;
+    for (const Level &lv : es.fwd) es.algo_bytes_fwd += lv.bytes;
 }
 
 struct ObsView {
@@ -573,7 +595,7 @@ static hipError_t upload_set(ExecSet &es, bool adjoint_parts)
 // Launch sequences
 // ---------------------------------------------------------------------------------------------------------
 struct DevPlans {
-    DBuf passes, ops;
+    DBuf passes, ops, rsegs;
     std::vector<int> pass_base;
 };
 
@@ -595,7 +617,24 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
     a.psi = psi;
     a.lam = lam;
     a.partials = es.d_adj_partials.as<double>();
+    a.rsegs = dp.rsegs.as<DevSeg>();
+    a.max_train = lv.max_train;
+    a.pad = 0;
     return a;
+}
+
+static int launch_kind(const Level &lv, const LevelArgs &a, int prec, int adjoint, hipStream_t s)
+{
+    if (lv.kind == LK_STRIDE) return launch_stride_level(a, prec, adjoint, s);
+    if (lv.kind == LK_RTILE) return launch_rlevel(a, prec, adjoint, s);
+    return launch_level(a, prec, adjoint, s);
+}
+
+static int log_id(const Level &lv, int adjoint)
+{
+    if (lv.kind == LK_STRIDE) return adjoint ? QV_K_STRIDE_ADJ : QV_K_STRIDE;
+    if (lv.kind == LK_RTILE) return adjoint ? QV_K_RTILE_ADJ : QV_K_RTILE;
+    return adjoint ? QV_K_TILE_ADJ : QV_K_TILE;
 }
 
 static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, void *psi, double *energies,
@@ -609,9 +648,7 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     for (size_t L = 0; L < es.fwd.size(); L++) {
         const Level &lv = es.fwd[L];
         LevelArgs a = level_args(bt, es, dp, lv, psi, nullptr);
-        e = logged(log, s, lv.stride ? QV_K_STRIDE : QV_K_TILE, (int)L, lv.bytes, [&] {
-            return lv.stride ? launch_stride_level(a, bt.prec, 0, s) : launch_level(a, bt.prec, 0, s);
-        });
+        e = logged(log, s, log_id(lv, 0), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 0, s); });
         if (e) return e;
     }
     ExpArgs ea;
@@ -654,9 +691,7 @@ static int enqueue_adjoint(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     for (size_t L = 0; L < es.rev.size(); L++) {
         const Level &lv = es.rev[L];
         LevelArgs a = level_args(bt, es, dp, lv, bt.d_psi.p, bt.d_lam.p);
-        e = logged(log, s, lv.stride ? QV_K_STRIDE_ADJ : QV_K_TILE_ADJ, (int)L, lv.bytes, [&] {
-            return lv.stride ? launch_stride_level(a, bt.prec, 1, s) : launch_level(a, bt.prec, 1, s);
-        });
+        e = logged(log, s, log_id(lv, 1), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 1, s); });
         if (e) return e;
     }
     GradReduceArgs ga;
@@ -692,9 +727,10 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             if (n < 1) return fail(QV_E_INVALID, "n-virtual-qpus must be >= 1");
             c->n_vqpu = n;
         } else if (k == "engine") {
-            if (v == "tiled") c->engine_stride = 0;
-            else if (v == "stride") c->engine_stride = 1;
-            else return fail(QV_E_INVALID, "engine must be \"tiled\" or \"stride\"");
+            if (v == "tiled") c->engine = 0;
+            else if (v == "lds") c->engine = 1;
+            else if (v == "stride") c->engine = 2;
+            else return fail(QV_E_INVALID, "engine must be \"tiled\", \"lds\" or \"stride\"");
         } else if (k == "tile_qubits") {
             if (v == "auto") c->tile_qubits = 0;
             else {
@@ -839,18 +875,21 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
             pin.trainable.push_back(is_rotation(g.kind) && g.param >= 0);
         }
         const int lowc = prec == QV_C64 ? 4 : 3;
-        bt->plans.push_back(ctx->engine_stride ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc));
+        const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
+        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb));
     }
     // device plan arrays
     auto dp = std::make_unique<DevPlans>();
     std::vector<DevPass> passes;
     std::vector<DevOp> ops;
+    std::vector<DevSeg> rsegs;
     for (const Plan &pl : bt->plans) {
         dp->pass_base.push_back((int)passes.size());
-        lower_plan(pl, passes, ops);
+        lower_plan(pl, passes, ops, rsegs);
     }
     HIPCHK(dp->passes.upload(passes));
     HIPCHK(dp->ops.upload(ops));
+    HIPCHK(dp->rsegs.upload(rsegs));
 
     // main set
     ExecSet &es = bt->main;

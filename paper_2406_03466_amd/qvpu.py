@@ -42,7 +42,7 @@ class qv_launch_rec(ctypes.Structure):
 
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
-                "grad_reduce", "shift_combine"]
+                "grad_reduce", "shift_combine", "rtile", "rtile_adj"]
 
 _lib = None
 

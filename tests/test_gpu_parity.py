@@ -65,7 +65,8 @@ def obs_scale(wl):
 # --------------------------------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"graph": False}])
+@pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"engine": "lds"},
+                                  {"engine": "lds", "tile_qubits": 7}, {"graph": False}])
 def test_c1_expectations(qv, prec, opts):
     say(f"c1 expectations prec={prec} opts={opts}")
     wl = W.config1()
@@ -79,7 +80,8 @@ def test_c1_expectations(qv, prec, opts):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}])
+@pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"engine": "lds"},
+                                  {"engine": "lds", "tile_qubits": 7}])
 def test_c1_gradients(qv, prec, opts):
     say(f"c1 gradients prec={prec} opts={opts}")
     wl = W.config1()
@@ -115,16 +117,16 @@ def test_c2_full(qv, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("tile", [6, 9, None])
-def test_uneven_batch(qv, prec, tile):
+@pytest.mark.parametrize("tile,engine", [(6, "tiled"), (9, "tiled"), (None, "tiled"), (8, "lds"), (None, "lds")])
+def test_uneven_batch(qv, prec, tile, engine):
     """Circuits of 2..16 qubits and 0..80 gates in one batch: per-circuit energies, terms, states and
     adjoint gradients (own parameters per circuit) with upstream weights."""
-    say(f"uneven prec={prec} tile={tile}")
+    say(f"uneven prec={prec} tile={tile} engine={engine}")
     wl = W.random_batch(24, 2, 16, 0, 80, 5, seed_index=41)
     e_ref, tv_ref, _, _ = oracle.expectations(wl)
     up = np.linspace(-1.0, 1.5, wl.B)
     g_ref = oracle.grad_adjoint(wl, up)
-    opts = {} if tile is None else {"tile_qubits": tile}
+    opts = {"engine": engine} if tile is None else {"tile_qubits": tile, "engine": engine}
     b = qv.Batch(ctx_for(qv, **opts), wl, prec)
     e, tv = b.expectations()
     s = obs_scale(wl)
