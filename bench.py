@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--no-ps", action="store_true")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
+    ap.add_argument("--contig", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the whole batch is one GPU's share; "
@@ -111,6 +112,8 @@ def main():
     opts = {"graph": False, "launch_events": True, "engine": args.engine}
     if args.tile_qubits:
         opts["tile_qubits"] = args.tile_qubits
+    if args.contig:
+        opts["contig_qubits"] = args.contig
     ctx = qvpu.Context(0, stream.cuda_stream, json.dumps(opts))
     batch = qvpu.Batch(ctx, wl, qvpu.QV_C64)
     theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev, requires_grad=True)

@@ -97,7 +97,8 @@ typedef enum {
     QV_K_GRAD_REDUCE = 8,   /* adjoint gradient from partial sums */
     QV_K_SHIFT_COMBINE = 9, /* parameter-shift gradient from shifted energies */
     QV_K_RTILE = 10,        /* register-tiled LDS pass, forward */
-    QV_K_RTILE_ADJ = 11     /* register-tiled LDS pass, adjoint reverse sweep */
+    QV_K_RTILE_ADJ = 11,    /* register-tiled LDS pass, adjoint reverse sweep */
+    QV_K_MATRICES = 12      /* 2x2 matrices of every gate at the current parameters */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -123,6 +124,8 @@ typedef struct qv_batch_s *qv_batch;
  *   "tile_qubits"    : int 6..14 or "auto" (default "auto": the autotuner's choice);
  *   "launch"         : "levels" (one launch per pass level, default) or "persistent";
  *   "graph"          : true (default) to capture each call's launches in a hipGraph and replay it;
+ *   "contig_qubits"  : 1..6: qubits 0..k-1 are in every tile, so tiles move in runs of 2^k amplitudes
+ *                      (default 4 for complex64, 3 for complex128: 128-byte runs);
  *   "launch_events"  : true to time every launch with a HIP event pair (only with "graph": false);
  *                      the records of the last call are read with qv_batch_launch_log. */
 qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_json, qv_ctx *out);
@@ -197,6 +200,26 @@ qv_status qv_batch_destroy(qv_batch batch);
 
 /* Message of the last failure on the calling thread ("" if none); valid until the next call. */
 const char *qv_last_error(void);
+
+/* One pass of a circuit's execution plan (see qv_plan_circuit). */
+typedef struct {
+    uint64_t local_mask;  /* qubits held in the pass's tile */
+    int32_t qubits;       /* tile size: popcount(local_mask) */
+    int32_t n_ops;        /* gates the pass applies */
+    int32_t n_trainable;  /* of them trainable */
+    int32_t n_segments;   /* register segments (0: gates run one at a time in LDS or from HBM) */
+    int32_t first_gate;   /* circuit index of the pass's first gate in execution order */
+    int32_t contiguous_low; /* qubits 0..contiguous_low-1 are all local (length of contiguous runs) */
+} qv_pass_info;
+
+/* Plans one circuit without a device, as qv_batch_create would for a batch with the given engine
+ * (0 "tiled", 1 "lds", 2 "stride") and tile size (0: the default): each pass is one read and one write
+ * of the state. Writes the pass count to *n_passes and the first max_passes passes to out; when order
+ * is not NULL it receives the n_gates gate indices in execution order (passes in turn, each pass's
+ * gates in the order the kernel applies them). Host only; for inspecting and testing the planner. */
+qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gates, int32_t tile_qubits,
+                          qv_precision precision, int32_t engine, int32_t max_passes, qv_pass_info *out,
+                          int32_t *n_passes, int32_t *order);
 
 /* Library version string. */
 const char *qv_version(void);

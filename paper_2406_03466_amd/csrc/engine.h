@@ -68,6 +68,7 @@ struct DevCirc {
     double shift;         // the move (+pi/2 or -pi/2)
     int32_t base_circ;    // the batch circuit this entry evaluates (variants point at their base)
     int32_t pad;
+    int64_t op_base;      // first op of the circuit's plan; matrix of op o is mats[gate_off + o - op_base]
 };
 
 // One (circuit, pass) of a level launch; blocks [first_block, next segment's first_block) run it.
@@ -122,13 +123,25 @@ struct LevelArgs {
     const DevOp *ops;
     const DevSeg *rsegs;  // register segments of the passes
     int32_t max_train;    // largest n_train of the level's passes (LDS for the adjoint partial sums)
-    int32_t pad;
+    int32_t tab_bits;     // largest t - lowc of the level's passes: the LDS run-offset table has 2^tab_bits entries
     const DevCirc *circs;
     const qv_gate *gates;
     const double *theta;
+    const void *mats;     // per circuit and plan op: its 2x2 matrix (8 reals, R precision), built from theta
     void *psi;
     void *lam;
     double *partials;
+};
+
+// Gate matrices of a batch: for every gate record, its 2x2 complex matrix at the current parameters.
+struct MatArgs {
+    const qv_gate *gates;
+    const int32_t *gate_circ;   // circuit of each gate record
+    const DevOp *ops;           // plans: entry gate_off + j of the table is the circuit's op op_base + j
+    const DevCirc *circs;
+    const double *theta;
+    void *mats;
+    int64_t n_gates;
 };
 
 struct ExpArgs {
@@ -197,6 +210,7 @@ int launch_lambda(const LambdaArgs &a, int precision, void *stream);
 int launch_grad_reduce(const GradReduceArgs &a, void *stream);
 int launch_shift_combine(const ShiftCombineArgs &a, void *stream);
 int launch_fill(double *p, int64_t n, double v, void *stream);
+int launch_matrices(const MatArgs &a, int precision, void *stream);
 int prepare_kernels();  // raises the dynamic-LDS limits; call once per device
 
 }  // namespace qv

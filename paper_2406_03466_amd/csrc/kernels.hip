@@ -118,6 +118,30 @@ __device__ __forceinline__ double gen_inner(int kind, Cx<R> a0, Cx<R> a1, Cx<R> 
     return (l0r * a0i - l0i * a0r) - (l1r * a1i - l1i * a1r);
 }
 
+// DPP move of a double: both 32-bit halves go through the same lane permutation. Lanes of rows outside
+// row_mask receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS); the total ends up in lane 63.
+// quad_perm [1,0,3,2] and [2,3,0,1] sum each quad, row_half_mirror each 8 lanes, row_mirror each row of
+// 16; row_bcast15 adds row 0 into row 1 and row 2 into row 3; row_bcast31 adds lane 31 into rows 2 and 3.
+__device__ __forceinline__ double wave_sum_to_63(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);
+    v += dpp_f64<0x4E, 0xF>(v);
+    v += dpp_f64<0x141, 0xF>(v);
+    v += dpp_f64<0x140, 0xF>(v);
+    v += dpp_f64<0x142, 0xA>(v);
+    v += dpp_f64<0x143, 0xC>(v);
+    return v;
+}
+
 // Sum over the workgroup (kBlock threads); the result is valid in thread 0. red holds kBlock/64 doubles.
 __device__ inline double block_sum(double v, double *red)
 {
@@ -153,13 +177,43 @@ __device__ __forceinline__ int find_prefix(const int64_t *pre, int n, int64_t bl
     return lo;
 }
 
-__device__ __forceinline__ double op_angle(const LevelArgs &a, const DevCirc &C, const DevOp &op, int &kind)
+// Matrix of op for circuit C: from the batch's matrix table, or built on the spot for the one gate whose
+// angle a parameter-shift variant moves.
+// The table is laid out in plan order (entry gate_off + o - op_base for the plan's op o), so an op's matrix
+// can be fetched without first reading the op record.
+template <typename R>
+__device__ __forceinline__ M2<R> op_matrix(const LevelArgs &a, const DevCirc &C, const DevOp &op, int64_t oi)
 {
-    const qv_gate g = a.gates[C.gate_off + op.gate];
-    kind = g.kind;
-    double ang = g.param >= 0 ? a.theta[C.param_base + g.param] : g.angle;
-    if (op.gate == C.shift_gate) ang += C.shift;
-    return ang;
+    if (op.gate == C.shift_gate) {
+        const qv_gate g = a.gates[C.gate_off + op.gate];
+        const double ang = (g.param >= 0 ? a.theta[C.param_base + g.param] : g.angle) + C.shift;
+        M2d md;
+        gate_matrix(g.kind, ang, md);
+        return narrow<R>(md);
+    }
+    return reinterpret_cast<const M2<R> *>(a.mats)[C.gate_off + (oi - C.op_base)];
+}
+
+template <typename R>
+__device__ __forceinline__ M2<R> dagger_r(const M2<R> &m)
+{
+    M2<R> o;
+    o.re[0] = m.re[0]; o.im[0] = -m.im[0];
+    o.re[1] = m.re[2]; o.im[1] = -m.im[2];
+    o.re[2] = m.re[1]; o.im[2] = -m.im[1];
+    o.re[3] = m.re[3]; o.im[3] = -m.im[3];
+    return o;
+}
+
+// Im <lambda| G |psi> on one amplitude pair in the state's own precision (the caller accumulates in FP64).
+template <typename R>
+__device__ __forceinline__ R gen_inner_r(int kind, Cx<R> a0, Cx<R> a1, Cx<R> l0, Cx<R> l1)
+{
+    if (kind == QV_RX)
+        return (l0.re * a1.im - l0.im * a1.re) + (l1.re * a0.im - l1.im * a0.re);
+    if (kind == QV_RY)
+        return -(l0.re * a1.re + l0.im * a1.im) + (l1.re * a0.re + l1.im * a0.im);
+    return (l0.re * a0.im - l0.im * a0.re) - (l1.re * a1.im - l1.im * a1.re);
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -183,8 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
     Cx<R> *sp = reinterpret_cast<Cx<R> *>(smem);
     Cx<R> *sl = sp + (ADJ ? TL : 0);
     uint64_t *segtab = reinterpret_cast<uint64_t *>(sp + (ADJ ? 2 * TL : TL));
-    const int tab_bits = a.lds_t > 3 ? a.lds_t - 3 : 0;
-    double *red = reinterpret_cast<double *>(segtab + (1 << tab_bits));
+    double *red = reinterpret_cast<double *>(segtab + (1 << a.tab_bits));
 
     const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     const uint64_t base = deposit((uint64_t)tile, full & ~P.local_mask);
@@ -214,8 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
     for (int k0 = 0; k0 < P.n_ops; k0++) {
         const int k = ADJ ? P.n_ops - 1 - k0 : k0;
         const DevOp op = a.ops[P.op_begin + k];
-        int kind;
-        const double ang = op_angle(a, C, op, kind);
+        const int kind = op.kind;
         if (kind == QV_CNOT || kind == QV_CZ) {
             const uint32_t bc = 1u << op.p0, bt = 1u << op.p1;
             const int plo = op.p0 < op.p1 ? op.p0 : op.p1, phi = op.p0 < op.p1 ? op.p1 : op.p0;
@@ -243,10 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
                 const double s = block_sum(acc, red);
                 if (threadIdx.x == 0) a.partials[sg.partial_base + tile * P.n_train + op.train_slot] = s;
             }
-            M2d md;
-            gate_matrix(kind, ang, md);
-            if (ADJ) dagger(md);
-            const M2<R> m = narrow<R>(md);
+            M2<R> m = op_matrix<R>(a, C, op, P.op_begin + k);
+            if (ADJ) m = dagger_r(m);
             for (uint32_t i = threadIdx.x; i < (T >> 1); i += kBlock) {
                 const uint32_t i0 = insert0(i, p), i1 = i0 | bit;
                 Cx<R> x = sp[i0], y = sp[i1];
@@ -397,7 +447,7 @@ __device__ __forceinline__ double r_inner(int kind, const Cx<R> (&a)[N], const C
     for (int j = 0; j < N; j++) {
         if (j & (1 << K)) continue;
         const int j1 = j | (1 << K);
-        acc += gen_inner<R>(kind, a[j], a[j1], l[j], l[j1]);
+        acc += (double)gen_inner_r<R>(kind, a[j], a[j1], l[j], l[j1]);
     }
     return acc;
 }
@@ -409,13 +459,14 @@ __device__ __forceinline__ double t_inner_z(const Cx<R> (&a)[N], const Cx<R> (&l
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < N; j++)
-        acc += (double)l[j].re * (double)a[j].im - (double)l[j].im * (double)a[j].re;
+        acc += (double)(l[j].re * a[j].im - l[j].im * a[j].re);
     return bit ? -acc : acc;
 }
 
 // One op applied to the registers v (the inverse when INV).
 template <bool INV, int RB, typename R>
-__device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, int kind, double ang, uint32_t Et)
+__device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, int kind, const M2<R> &mat,
+                                          uint32_t Et)
 {
     constexpr int N = 1 << RB;
     if (kind == QV_CNOT) {
@@ -436,38 +487,23 @@ __device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, 
         return;
     }
     if (kind == QV_RY) {
-        double s, c;
-        sincos(0.5 * ang, &s, &c);
-        const R cr = (R)c, sr = INV ? (R)(-s) : (R)s;
+        // [[c, -s], [s, c]]; the inverse is the transpose
+        const R cr = mat.re[0], sr = INV ? -mat.re[2] : mat.re[2];
         WITH_K(RB, op.k0, r_real<K>(v, cr, sr));
         return;
     }
     if (kind == QV_RZ || kind == QV_Z || kind == QV_S || kind == QV_T) {
-        double d0r = 1, d0i = 0, d1r = 1, d1i = 0;
-        if (kind == QV_RZ) {
-            double s, c;
-            sincos(0.5 * ang, &s, &c);
-            d0r = c; d0i = -s; d1r = c; d1i = s;
-        } else if (kind == QV_Z) {
-            d1r = -1;
-        } else if (kind == QV_S) {
-            d1r = 0; d1i = 1;
-        } else {
-            d1r = 0.70710678118654752440; d1i = 0.70710678118654752440;
-        }
-        if (INV) { d0i = -d0i; d1i = -d1i; }
+        const R d0r = mat.re[0], d1r = mat.re[3];
+        const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
         if (op.k0 >= 0) {
-            WITH_K(RB, op.k0, r_diag<K>(v, (R)d0r, (R)d0i, (R)d1r, (R)d1i));
+            WITH_K(RB, op.k0, r_diag<K>(v, d0r, d0i, d1r, d1i));
         } else {
             const bool b = (Et >> op.p0) & 1u;
-            t_scale(v, (R)(b ? d1r : d0r), (R)(b ? d1i : d0i));
+            t_scale(v, b ? d1r : d0r, b ? d1i : d0i);
         }
         return;
     }
-    M2d md;
-    gate_matrix(kind, ang, md);
-    if (INV) dagger(md);
-    const M2<R> m = narrow<R>(md);
+    const M2<R> m = INV ? dagger_r(mat) : mat;
     WITH_K(RB, op.k0, r_gen<K>(v, m));
 }
 
@@ -488,8 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
     Cx<R> *sp = reinterpret_cast<Cx<R> *>(smem);
     Cx<R> *sl = sp + (ADJ ? TL : 0);
     uint64_t *segtab = reinterpret_cast<uint64_t *>(sp + (ADJ ? 2 * TL : TL));
-    const int tab_bits = a.lds_t > 3 ? a.lds_t - 3 : 0;
-    double *red = reinterpret_cast<double *>(segtab + (1 << tab_bits));
+    double *red = reinterpret_cast<double *>(segtab + (1 << a.tab_bits));
 
     const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     const uint64_t base = deposit((uint64_t)tile, full & ~P.local_mask);
@@ -546,11 +581,22 @@ __global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
             av[j] = sp[addr];
             if (ADJ) lv[j] = sl[addr];
         }
+        // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
+        const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.gate_off - C.op_base);
+        int64_t oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
+        DevOp nop = a.ops[oi];
+        M2<R> nmat = mtab[oi];
         for (int k0 = 0; k0 < S.n_ops; k0++) {
-            const int k = ADJ ? S.n_ops - 1 - k0 : k0;
-            const DevOp op = a.ops[S.op_begin + k];
-            int kind;
-            const double ang = op_angle(a, C, op, kind);
+            const DevOp op = nop;
+            M2<R> mat = nmat;
+            const int64_t cur = oi;
+            if (k0 + 1 < S.n_ops) {
+                oi += ADJ ? -1 : 1;
+                nop = a.ops[oi];
+                nmat = mtab[oi];
+            }
+            const int kind = op.kind;
+            if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
             if (ADJ) {
                 if (op.flags & OP_TRAIN) {
                     double ip;
@@ -561,13 +607,13 @@ __global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
                         WITH_K(RB, op.k0, ip = r_inner<K>(kind, av, lv));
                     }
                     if (!active) ip = 0.0;
-                    for (int o = 32; o > 0; o >>= 1) ip += __shfl_xor(ip, o, 64);
-                    if (lane == 0) red[op.train_slot * (kBlock / 64) + wave] = ip;
+                    ip = wave_sum_to_63(ip);
+                    if (lane == 63) red[op.train_slot * (kBlock / 64) + wave] = ip;
                 }
-                rop_apply<true, RB, R>(av, op, kind, ang, Et);
-                rop_apply<true, RB, R>(lv, op, kind, ang, Et);
+                rop_apply<true, RB, R>(av, op, kind, mat, Et);
+                rop_apply<true, RB, R>(lv, op, kind, mat, Et);
             } else {
-                rop_apply<false, RB, R>(av, op, kind, ang, Et);
+                rop_apply<false, RB, R>(av, op, kind, mat, Et);
             }
         }
         if (active) {
@@ -618,8 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
     const DevCirc C = a.circs[sg.circ];
     const int n = C.n;
     const DevOp op = a.ops[P.op_begin];
-    int kind;
-    const double ang = op_angle(a, C, op, kind);
+    const int kind = op.kind;
     Cx<R> *gpsi = reinterpret_cast<Cx<R> *>(a.psi) + C.state_off;
     Cx<R> *glam = ADJ ? reinterpret_cast<Cx<R> *>(a.lam) + C.state_off : nullptr;
     const uint64_t g0 = (uint64_t)chunk * kStrideGroupsPerBlock;
@@ -647,10 +692,8 @@ __global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
     const uint64_t ngroups = 1ull << (n - 1);
     const int p = op.p0;
     const uint64_t bit = 1ull << p;
-    M2d md;
-    gate_matrix(kind, ang, md);
-    if (ADJ) dagger(md);
-    const M2<R> m = narrow<R>(md);
+    M2<R> m = op_matrix<R>(a, C, op, P.op_begin);
+    if (ADJ) m = dagger_r(m);
     double acc = 0.0;
     for (uint32_t e = threadIdx.x; e < kStrideGroupsPerBlock; e += kBlock) {
         const uint64_t gi = g0 + e;
@@ -670,6 +713,26 @@ __global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
         const double s = block_sum(acc, red);
         if (threadIdx.x == 0) a.partials[sg.partial_base + chunk * P.n_train + op.train_slot] = s;
     }
+}
+
+// Matrix table: the 2x2 matrix of every one-qubit gate record at the current parameters (FP64 angles and
+// trigonometry, rounded to the state precision).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_matrices(MatArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n_gates) return;
+    const DevCirc C = a.circs[a.gate_circ[i]];
+    const DevOp op = a.ops[C.op_base + (i - C.gate_off)];
+    const qv_gate g = a.gates[C.gate_off + op.gate];
+    M2d md;
+    if (g.kind == QV_CNOT || g.kind == QV_CZ) {
+        gate_matrix(-1, 0.0, md);
+    } else {
+        const double ang = g.param >= 0 ? a.theta[C.param_base + g.param] : g.angle;
+        gate_matrix(g.kind, ang, md);
+    }
+    reinterpret_cast<M2<R> *>(a.mats)[i] = narrow<R>(md);
 }
 
 // psi_b = |0...0> for every circuit; blocks cover 4096 amplitudes each.
@@ -857,9 +920,10 @@ __global__ void k_fill(double *p, int64_t n, double v)
 // ------------------------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------------------------
-static size_t tile_lds_bytes(int lds_t, int amp_bytes, int adjoint)
+// LDS of a tile launch: the tile (twice for the adjoint), the table of 2^tab_bits run offsets, and a
+// small reduction area.
+static size_t tile_lds_bytes(int lds_t, int tab_bits, int amp_bytes, int adjoint)
 {
-    const int tab_bits = lds_t > 3 ? lds_t - 3 : 0;
     return (size_t)(adjoint ? 2 : 1) * ((size_t)1 << lds_t) * amp_bytes + ((size_t)8 << tab_bits) +
            sizeof(double) * (kBlock / 64);
 }
@@ -899,7 +963,7 @@ int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
     if (a.n_blocks <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int amp = precision == QV_C64 ? 8 : 16;
-    const size_t lds = tile_lds_bytes(a.lds_t, amp, adjoint) +
+    const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint) +
                        (adjoint ? sizeof(double) * (kBlock / 64) * (size_t)a.max_train : 0);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.n_blocks), block(kBlock);
@@ -918,7 +982,7 @@ int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream)
     if (a.n_blocks <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int amp = precision == QV_C64 ? 8 : 16;
-    const size_t lds = tile_lds_bytes(a.lds_t, amp, adjoint);
+    const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.n_blocks), block(kBlock);
     if (precision == QV_C64) {
@@ -1003,6 +1067,16 @@ int launch_shift_combine(const ShiftCombineArgs &a, void *stream)
     if (a.n_out <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_shift_combine, dim3((unsigned)((a.n_out + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_matrices(const MatArgs &a, int precision, void *stream)
+{
+    if (a.n_gates <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)((a.n_gates + kBlock - 1) / kBlock));
+    if (precision == QV_C64) hipLaunchKernelGGL((k_matrices<float>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_matrices<double>), grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -122,37 +122,72 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits)
     };
     lowc = std::min(lowc, n);
     std::vector<char> done(G, 0);
+    std::vector<uint64_t> qmask(G);
+    for (int g = 0; g < G; g++)
+        qmask[g] = (1ull << in.q0[g]) | (two_qubit(in.kinds[g]) ? (1ull << in.q1[g]) : 0ull);
     int remaining = G;
     int first = 0;
     const bool whole = n <= tile_qubits;
-    while (remaining > 0) {
-        PlanPass pp;
-        uint64_t L = whole ? full : (1ull << lowc) - 1ull;
-        int cnt = whole ? n : lowc;
-        int ntrain = 0;
+    // Gates a pass with local set L can take: in program order, each unscheduled gate whose qubits are
+    // local and not blocked by an earlier gate left behind.
+    auto schedulable = [&](uint64_t L, std::vector<int> *out) {
         uint64_t blocked = 0;
-        while (first < G && done[first]) first++;
+        int cnt = 0, ntrain = 0;
         for (int g = first; g < G; g++) {
             if (done[g]) continue;
-            const uint64_t qs = (1ull << in.q0[g]) | (two_qubit(in.kinds[g]) ? (1ull << in.q1[g]) : 0ull);
+            const uint64_t qs = qmask[g];
             if (qs & blocked) { blocked |= qs; continue; }
-            const uint64_t need = qs & ~L;
-            const int add = __builtin_popcountll(need);
-            const bool train_full = in.trainable[g] && ntrain >= kMaxTrainPerPass;
-            if (cnt + add <= tile_qubits && !train_full) {
-                L |= need;
-                cnt += add;
-                done[g] = 1;
-                remaining--;
-                ntrain += in.trainable[g] ? 1 : 0;
-                pp.ops.push_back(mk_op(g));
-            } else {
-                blocked |= qs;
+            if ((qs & ~L) || (in.trainable[g] && ntrain >= kMaxTrainPerPass)) { blocked |= qs; continue; }
+            cnt++;
+            ntrain += in.trainable[g] ? 1 : 0;
+            if (out) out->push_back(g);
+        }
+        return cnt;
+    };
+    while (remaining > 0) {
+        PlanPass pp;
+        while (first < G && done[first]) first++;
+        // 1. grow the local set greedily in program order
+        uint64_t L = whole ? full : (1ull << lowc) - 1ull;
+        int cnt = whole ? n : lowc;
+        {
+            uint64_t blocked = 0;
+            for (int g = first; g < G && cnt < tile_qubits; g++) {
+                if (done[g]) continue;
+                const uint64_t qs = qmask[g];
+                if (qs & blocked) { blocked |= qs; continue; }
+                const uint64_t need = qs & ~L;
+                const int add = __builtin_popcountll(need);
+                if (cnt + add <= tile_qubits) { L |= need; cnt += add; }
+                else blocked |= qs;
+            }
+            for (int q = 0; q < n && cnt < tile_qubits; q++)
+                if (!(L >> q & 1ull)) { L |= 1ull << q; cnt++; }
+        }
+        // 2. local search: swap one free qubit in and one out while that lets the pass take more gates
+        if (!whole) {
+            int best = schedulable(L, nullptr);
+            for (int round = 0; round < 64; round++) {
+                bool improved = false;
+                for (int qi = lowc; qi < n && !improved; qi++) {
+                    if (L >> qi & 1ull) continue;
+                    for (int qo = lowc; qo < n; qo++) {
+                        if (!(L >> qo & 1ull)) continue;
+                        const uint64_t L2 = (L | (1ull << qi)) & ~(1ull << qo);
+                        const int c2 = schedulable(L2, nullptr);
+                        if (c2 > best) { best = c2; L = L2; improved = true; break; }
+                    }
+                }
+                if (!improved) break;
             }
         }
-        // pad the tile with the lowest unused qubits (fewer, larger tiles; longer contiguous runs)
-        for (int q = 0; q < n && cnt < tile_qubits; q++)
-            if (!(L >> q & 1ull)) { L |= 1ull << q; cnt++; }
+        std::vector<int> take;
+        schedulable(L, &take);
+        for (int g : take) {
+            done[g] = 1;
+            remaining--;
+            pp.ops.push_back(mk_op(g));
+        }
         pp.local_mask = L;
         finish_pass(pp, n);
         segment_pass(pp, reg_bits);

@@ -109,6 +109,7 @@ struct qv_ctx_s {
     int graph = 1;
     int n_vqpu = 0;             // 0: all circuits in flight
     int launch_events = 0;      // 1: record a HIP event pair around every launch (eager mode)
+    int contig = 0;             // qubits 0..contig-1 always local (0: 4 for complex64, 3 for complex128)
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
@@ -147,6 +148,7 @@ struct Level {
     int32_t kind;     // LevelKind
     int64_t bytes;    // algorithmic state bytes moved by the launch (read + write)
     int32_t max_train;
+    int32_t tab_bits; // largest (tile qubits - contiguous low qubits) of the level's passes
 };
 
 static int pass_kind(const PlanPass &pp)
@@ -262,6 +264,7 @@ struct qv_batch_s {
     bool ps_ready = false;
 
     DBuf d_gates, d_theta, d_psi, d_lam, d_energies, d_tv, d_norms, d_grad, d_upstream;
+    DBuf d_gate_circ, d_mats;   // circuit of each gate record; 2x2 matrix of each gate record
     DBuf d_ps_psi, d_ps_energies, d_ps_tv, d_occ_begin, d_occ_plus, d_occ_minus, d_occ_circ;
 
     bool theta_set = false;
@@ -383,7 +386,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
         for (int dir = 0; dir < 2; dir++) {
             for (int L = 0; L < maxp; L++) {
                 for (int kind = 0; kind < 3; kind++) {
-                    Level lv{(int64_t)es.segs.size(), 0, 0, 0, kind, 0, 0};
+                    Level lv{(int64_t)es.segs.size(), 0, 0, 0, kind, 0, 0, 0};
                     for (int c = w0; c < w1; c++) {
                         const Plan &pl = plans[es.plan_of[c]];
                         const int np = (int)pl.passes.size();
@@ -403,6 +406,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         lv.n_blocks += tiles_of(es.circs[c], pl, p);
                         lv.lds_t = std::max(lv.lds_t, pp.t);
                         lv.max_train = std::max(lv.max_train, pp.n_train);
+                        lv.tab_bits = std::max(lv.tab_bits, pp.t - pp.lowc);
                         lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : 4) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
                     }
                     if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
@@ -614,12 +618,13 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
     a.circs = es.d_circs.as<DevCirc>();
     a.gates = bt.d_gates.as<qv_gate>();
     a.theta = bt.d_theta.as<double>();
+    a.mats = bt.d_mats.p;
     a.psi = psi;
     a.lam = lam;
     a.partials = es.d_adj_partials.as<double>();
     a.rsegs = dp.rsegs.as<DevSeg>();
     a.max_train = lv.max_train;
-    a.pad = 0;
+    a.tab_bits = lv.tab_bits;
     return a;
 }
 
@@ -635,6 +640,19 @@ static int log_id(const Level &lv, int adjoint)
     if (lv.kind == LK_STRIDE) return adjoint ? QV_K_STRIDE_ADJ : QV_K_STRIDE;
     if (lv.kind == LK_RTILE) return adjoint ? QV_K_RTILE_ADJ : QV_K_RTILE;
     return adjoint ? QV_K_TILE_ADJ : QV_K_TILE;
+}
+
+static int enqueue_matrices(const qv_batch_s &bt, hipStream_t s, LaunchLog *log)
+{
+    MatArgs ma;
+    ma.gates = bt.d_gates.as<qv_gate>();
+    ma.gate_circ = bt.d_gate_circ.as<int32_t>();
+    ma.ops = g_devplans.at(&bt)->ops.as<DevOp>();
+    ma.circs = bt.main.d_circs.as<DevCirc>();
+    ma.theta = bt.d_theta.as<double>();
+    ma.mats = bt.d_mats.p;
+    ma.n_gates = (int64_t)bt.gates.size();
+    return logged(log, s, QV_K_MATRICES, -1, 0, [&] { return launch_matrices(ma, bt.prec, s); });
 }
 
 static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, void *psi, double *energies,
@@ -740,6 +758,10 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             }
         } else if (k == "graph") {
             c->graph = (v == "true" || v == "1");
+        } else if (k == "contig_qubits") {
+            int cq = atoi(v.c_str());
+            if (cq < 1 || cq > 6) return fail(QV_E_INVALID, "contig_qubits must be in [1, 6]");
+            c->contig = cq;
         } else if (k == "launch_events") {
             c->launch_events = (v == "true" || v == "1");
         } else if (k == "launch") {
@@ -874,7 +896,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
             pin.q1.push_back(is_two_qubit(g.kind) ? g.q1 : -1);
             pin.trainable.push_back(is_rotation(g.kind) && g.param >= 0);
         }
-        const int lowc = prec == QV_C64 ? 4 : 3;
+        const int lowc = ctx->contig ? ctx->contig : (prec == QV_C64 ? 4 : 3);
         const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
         bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb));
     }
@@ -883,8 +905,10 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     std::vector<DevPass> passes;
     std::vector<DevOp> ops;
     std::vector<DevSeg> rsegs;
+    std::vector<int64_t> plan_op_base;
     for (const Plan &pl : bt->plans) {
         dp->pass_base.push_back((int)passes.size());
+        plan_op_base.push_back((int64_t)ops.size());
         lower_plan(pl, passes, ops, rsegs);
     }
     HIPCHK(dp->passes.upload(passes));
@@ -907,6 +931,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
         c.shift = 0.0;
         c.base_circ = b;
         c.pad = 0;
+        c.op_base = plan_op_base[bt->plan_of[b]];
         off += (int64_t)1 << nq[b];
         pb += np[b];
     }
@@ -926,6 +951,13 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     HIPCHK(upload_set(es, true));
 
     HIPCHK(bt->d_gates.upload(bt->gates));
+    {
+        std::vector<int32_t> gc(bt->gates.size());
+        for (int b = 0; b < B; b++)
+            for (int64_t k = goff[b]; k < goff[b + 1]; k++) gc[k] = b;
+        HIPCHK(bt->d_gate_circ.upload(gc));
+        HIPCHK(bt->d_mats.alloc((size_t)std::max<int64_t>(1, (int64_t)bt->gates.size()) * 8 * (bt->amp_bytes / 2)));
+    }
     HIPCHK(bt->d_theta.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_theta)));
     HIPCHK(bt->d_psi.alloc((size_t)off * bt->amp_bytes));
     HIPCHK(bt->d_energies.alloc(sizeof(double) * B));
@@ -989,6 +1021,8 @@ static qv_status forward(qv_batch bt)
 {
     DevPlans &dp = *g_devplans[bt];
     qv_status st = run_graph(bt, bt->g_fwd, [&](hipStream_t s, LaunchLog *log) {
+        const int e = enqueue_matrices(*bt, s, log);
+        if (e) return e;
         return enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
                                bt->d_norms.as<double>(), s, log);
     });
@@ -1172,7 +1206,9 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
     } else {
         if ((st = ensure_param_shift(bt)) != QV_OK) return st;
         st = run_graph(bt, bt->g_ps, [&](hipStream_t cs, LaunchLog *log) {
-            int e = enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+            int e = enqueue_matrices(*bt, cs, log);
+            if (e) return e;
+            e = enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
                                     bt->d_norms.as<double>(), cs, log);
             if (e) return e;
             for (size_t i = 0; i < bt->ps_chunks.size(); i++) {
@@ -1282,5 +1318,54 @@ qv_status qv_batch_launch_log(qv_batch bt, qv_launch_rec *out, int32_t max_recor
         out[i].ms = ms;
     }
     if (max_records >= n) bt->log.clear();
+    return ok();
+}
+
+qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gates, int32_t tile_qubits,
+                          qv_precision precision, int32_t engine, int32_t max_passes, qv_pass_info *out,
+                          int32_t *n_passes, int32_t *order)
+{
+    if (!n_passes) return fail(QV_E_INVALID, "n_passes must not be NULL");
+    if (max_passes > 0 && !out) return fail(QV_E_INVALID, "out must not be NULL when max_passes > 0");
+    if (engine < 0 || engine > 2) return fail(QV_E_INVALID, "engine must be 0 (tiled), 1 (lds) or 2 (stride)");
+    const int64_t goff[2] = {0, n_gates};
+    const int32_t nq[1] = {n_qubits};
+    int32_t np = 0;
+    for (int64_t k = 0; k < n_gates; k++)
+        if (gates && gates[k].param >= np) np = gates[k].param + 1;
+    const int64_t toff[2] = {0, 0};
+    qv_status st = validate(1, nq, goff, gates, &np, 1, toff, nullptr, nullptr, nullptr, 1, precision);
+    if (st != QV_OK) return st;
+    int t = tile_qubits > 0 ? tile_qubits : default_tile_qubits(precision, false);
+    if (t < 6 || t > kMaxTileQubits) return fail(QV_E_INVALID, "tile_qubits must be in [6, %d]", kMaxTileQubits);
+    t = std::min(t, precision == QV_C64 ? 13 : 12);
+    PlanInput pin;
+    pin.n = n_qubits;
+    for (int64_t k = 0; k < n_gates; k++) {
+        pin.kinds.push_back(gates[k].kind);
+        pin.q0.push_back(gates[k].q0);
+        pin.q1.push_back(is_two_qubit(gates[k].kind) ? gates[k].q1 : -1);
+        pin.trainable.push_back(is_rotation(gates[k].kind) && gates[k].param >= 0);
+    }
+    const int lowc = precision == QV_C64 ? 4 : 3;
+    const int rb = engine == 0 ? (precision == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
+    const Plan pl = engine == 2 ? plan_stride(pin) : plan_tiled(pin, t, lowc, rb);
+    *n_passes = (int32_t)pl.passes.size();
+    for (int32_t i = 0; i < *n_passes && i < max_passes; i++) {
+        const PlanPass &pp = pl.passes[i];
+        qv_pass_info &o = out[i];
+        o.local_mask = pp.local_mask;
+        o.qubits = pp.t;
+        o.n_ops = (int32_t)pp.ops.size();
+        o.n_trainable = pp.n_train;
+        o.n_segments = (int32_t)pp.segs.size();
+        o.first_gate = pp.ops.empty() ? -1 : pp.ops.front().gate;
+        o.contiguous_low = pp.lowc;
+    }
+    if (order) {
+        int64_t k = 0;
+        for (const PlanPass &pp : pl.passes)
+            for (const PlanOp &op : pp.ops) order[k++] = op.gate;
+    }
     return ok();
 }

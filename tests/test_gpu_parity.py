@@ -288,3 +288,21 @@ def test_error_paths_on_device(qv):
         qv.Context(0, None, '{"tile_qubits": 20}')
     with pytest.raises(qv.QvError):
         qv.Context(7, None, None)
+
+
+@pytest.mark.parametrize("prec,contig", [(0, 1), (0, 2), (0, 3), (1, 2)])
+def test_contig_qubits(qv, prec, contig):
+    """Tiles whose contiguous low runs are short (contig_qubits 1..3) need a longer run-offset table in
+    LDS; energies, terms and adjoint gradients stay at parity."""
+    say(f"contig prec={prec} contig={contig}")
+    wl = W.random_batch(10, 12, 16, 20, 90, 4, seed_index=45)
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    up = np.linspace(0.5, -1.0, wl.B)
+    g_ref = oracle.grad_adjoint(wl, up)
+    b = qv.Batch(ctx_for(qv, contig_qubits=contig, tile_qubits=10), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+    check(g, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")

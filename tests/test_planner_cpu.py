@@ -1,0 +1,85 @@
+"""CPU checks of the pass planner (host logic of the library, no device): every gate is scheduled once,
+gates that share a qubit keep their program order, every pass's gates are local to its tile, and running
+the circuit in the planned order gives the same state as program order (oracle, complex128)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_03466_amd import qvpu
+from paper_2406_03466_amd import workloads as W
+
+
+def _check_plan(n, gates, passes, order):
+    G = len(gates)
+    assert sorted(order.tolist()) == list(range(G))
+    assert sum(p["n_ops"] for p in passes) == G
+    # per-qubit program order is preserved
+    last = {}
+    for g in order:
+        r = gates[g]
+        qs = [int(r["q0"])] + ([int(r["q1"])] if int(r["kind"]) in (W.CNOT, W.CZ) else [])
+        for q in qs:
+            assert last.get(q, -1) < g, f"gate {g} on qubit {q} runs after a later gate"
+            last[q] = g
+    # every pass's gates act on its tile's qubits only
+    k = 0
+    for p in passes:
+        for g in order[k:k + p["n_ops"]]:
+            r = gates[g]
+            m = (1 << int(r["q0"])) | ((1 << int(r["q1"])) if int(r["kind"]) in (W.CNOT, W.CZ) else 0)
+            assert m & ~p["local_mask"] == 0
+        k += p["n_ops"]
+        assert bin(p["local_mask"]).count("1") == p["qubits"]
+
+
+@pytest.mark.parametrize("engine", [0, 1, 2])
+@pytest.mark.parametrize("tile", [6, 8, 13])
+def test_random_circuits_planned_order(engine, tile):
+    rng = np.random.default_rng(tile * 10 + engine)
+    wl = W.random_batch(12, 2, 16, 0, 120, 1, seed_index=60 + tile)
+    for b in range(wl.B):
+        n = int(wl.n_qubits[b])
+        gates = wl.circuit(b)
+        passes, order = qvpu.plan_circuit(n, gates, tile, qvpu.QV_C64, engine, with_order=True)
+        _check_plan(n, gates, passes, order)
+        if n <= 12 and len(gates):
+            th = wl.theta_of(b)
+            a = oracle.final_state(n, gates, th)
+            bst = oracle.final_state(n, gates[order], th)
+            np.testing.assert_allclose(a, bst, atol=1e-13)
+    del rng
+
+
+def test_hea_pass_counts_and_tiles():
+    """20-qubit circuit learning, 8 layers: the planner packs the 492 gates into a handful of tile passes,
+    every register-tiled pass holds 13 qubits with qubits 0..3 contiguous."""
+    wl = W.config3(8)
+    passes, order = qvpu.plan_circuit(20, wl.circuit(0), 13, qvpu.QV_C64, 0, with_order=True)
+    _check_plan(20, wl.circuit(0), passes, order)
+    assert len(passes) <= 8
+    for p in passes:
+        assert p["qubits"] == 13 and p["contiguous_low"] >= 4 and p["n_segments"] >= 1
+    stride = qvpu.plan_circuit(20, wl.circuit(0), 13, qvpu.QV_C64, 2)
+    assert len(stride) == 492
+
+
+def test_small_circuits_are_one_pass():
+    wl = W.config1()
+    passes = qvpu.plan_circuit(10, wl.circuit(0), 13, qvpu.QV_C128, 0)
+    assert len(passes) == 1 and passes[0]["qubits"] == 10 and passes[0]["n_ops"] == 116
+
+
+def test_trainable_cap_per_pass():
+    """A pass holds at most 512 trainable gates (their adjoint partial sums live in LDS)."""
+    g = [W.gate(W.RY, i % 6, -1, i) for i in range(1300)]
+    arr = np.array(g, W.GATE_DTYPE)
+    passes = qvpu.plan_circuit(6, arr, 13, qvpu.QV_C64, 0)
+    assert [p["n_trainable"] for p in passes] == [512, 512, 276]
+
+
+def test_plan_rejects_bad_input():
+    arr = np.array([W.gate(W.CNOT, 0, 0)], W.GATE_DTYPE)
+    with pytest.raises(qvpu.QvError):
+        qvpu.plan_circuit(4, arr, 13, qvpu.QV_C64, 0)
+    with pytest.raises(qvpu.QvError):
+        qvpu.plan_circuit(4, np.array([W.gate(W.H, 0)], W.GATE_DTYPE), 3, qvpu.QV_C64, 0)
