@@ -94,6 +94,10 @@ def main():
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
+    ap.add_argument("--launch", default="levels", choices=["levels", "persistent"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    ap.add_argument("--levels", action="store_true", help="print per-launch times of one step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the whole batch is one GPU's share; "
@@ -101,6 +105,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8}), flush=True)
+        return
     from paper_2406_03466_amd import qvpu
     from paper_2406_03466_amd import workloads as W
     from paper_2406_03466_amd.autograd import expectation
@@ -109,11 +121,13 @@ def main():
     torch.cuda.set_device(dev)
     wl = W.config3(args.layers)
     stream = torch.cuda.current_stream(dev)
-    opts = {"graph": False, "launch_events": True, "engine": args.engine}
+    opts = {"graph": False, "launch_events": True, "engine": args.engine, "launch": args.launch}
     if args.tile_qubits:
         opts["tile_qubits"] = args.tile_qubits
     if args.contig:
         opts["contig_qubits"] = args.contig
+    if not args.tile_qubits and not args.contig:
+        opts["autotune"] = "search"
     ctx = qvpu.Context(0, stream.cuda_stream, json.dumps(opts))
     batch = qvpu.Batch(ctx, wl, qvpu.QV_C64)
     theta = torch.tensor(wl.theta, dtype=torch.float64, device=dev, requires_grad=True)
@@ -140,6 +154,11 @@ def main():
     t_end.record(stream)
     torch.cuda.synchronize()
     recs = batch.launch_log()
+    tuned = batch.stats()
+    if args.levels:
+        per_step = len(recs) // max(1, args.steps)
+        for r in recs[:per_step]:
+            print(f"# {r['kernel']:12s} level {r['level']:3d} {r['ms']:9.4f} ms {r['bytes'] / 1e9:8.3f} GB", flush=True)
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
     grads_per_s = 1000.0 / ms_step
@@ -148,7 +167,9 @@ def main():
     d = per[dom]
     achieved = d["gbs"]
     kernel_sym = {"tile_adj": "k_tile<float,true>", "tile": "k_tile<float,false>",
-                  "rtile_adj": "k_rtile<float,true,5>", "rtile": "k_rtile<float,false,5>"}.get(dom, dom)
+                  "rtile_adj": "k_rtile_adj<float,4,512>", "rtile": "k_rtile_fwd<float,4,512>",
+                  "rtile_adj_persist": "k_rtile_adj_persist<float,4,512>",
+                  "rtile_persist": "k_rtile_fwd_persist<float,4,512>"}.get(dom, dom)
     workload_tag = f"qcl20_L{args.layers}"
     traffic = pmc_traffic(dom, workload_tag)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -156,8 +177,8 @@ def main():
                 "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
                 "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
     # forward-only circuit evals/s (the 64 circuits of one forward pass)
-    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("init", "tile", "rtile", "stride", "expect",
-                                                          "finalize")) / args.steps
+    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("matrices", "init", "tile", "rtile", "rtile_persist",
+                                                          "stride", "expect", "finalize")) / args.steps
     circuit_evals_per_s = wl.B / (fwd_ms / 1e3)
 
     extra = {}
@@ -221,7 +242,9 @@ def main():
                                f"RY(arcsin x) encoding + {args.layers} HEA layers ({wl.n_grad()} params), "
                                f"<Z_0>, MSE loss, adjoint gradient, complex64 with FP64 reductions",
                    "qubits": 20, "layers": args.layers, "samples": 64, "params": wl.n_grad(),
-                   "precision": "c64", "tile_qubits": args.tile_qubits or "auto", "engine": args.engine},
+                   "precision": "c64", "engine": args.engine, "tile_qubits": tuned["tile_qubits"],
+                   "contig_qubits": tuned["contig_qubits"], "passes": tuned["passes_per_circuit_max"],
+                   "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch},
         "roofline": roofline,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1)}

@@ -82,6 +82,10 @@ typedef struct {
     int64_t algorithmic_bytes; /* state bytes read + written by the last call's passes and reductions */
     double kernel_ms;          /* device time of the last call, from HIP events on the context stream */
     double norm_err_max;       /* max |<psi|psi> - 1| over the batch after the last forward call */
+    int32_t tile_qubits;       /* tile size of the batch's plans (after autotuning) */
+    int32_t contig_qubits;     /* qubits 0..contig_qubits-1 are in every tile */
+    int32_t passes_per_circuit_max; /* longest plan */
+    int32_t pad;
 } qv_stats;
 
 /* Kernels named in launch records. */
@@ -98,7 +102,9 @@ typedef enum {
     QV_K_SHIFT_COMBINE = 9, /* parameter-shift gradient from shifted energies */
     QV_K_RTILE = 10,        /* register-tiled LDS pass, forward */
     QV_K_RTILE_ADJ = 11,    /* register-tiled LDS pass, adjoint reverse sweep */
-    QV_K_MATRICES = 12      /* 2x2 matrices of every gate at the current parameters */
+    QV_K_MATRICES = 12,     /* 2x2 matrices of every gate at the current parameters */
+    QV_K_RTILE_PERSIST = 13,     /* all forward register-tiled passes in one persistent launch */
+    QV_K_RTILE_ADJ_PERSIST = 14  /* all adjoint register-tiled passes in one persistent launch */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -122,7 +128,14 @@ typedef struct qv_batch_s *qv_batch;
  *                      "lds" (LDS tile passes, one gate at a time in LDS) or "stride" (one global-memory
  *                      pass per gate);
  *   "tile_qubits"    : int 6..14 or "auto" (default "auto": the autotuner's choice);
- *   "launch"         : "levels" (one launch per pass level, default) or "persistent";
+ *   "launch"         : "levels" (one launch per pass level, default) or "persistent" (all levels of a
+ *                      sweep in one launch: resident workgroups take tiles from a queue in level order and
+ *                      wait, with a bounded spin, until their circuit's earlier passes are complete);
+ *   "autotune"       : "off", "cached" (default: reuse a choice stored by an earlier search) or
+ *                      "search" (on the first forward call, time one forward pass for each candidate tile
+ *                      size and contiguous-run length and keep the fastest; stored in the text file named
+ *                      by QV_TUNE_CACHE, default $HOME/.cache/qvpu_tune.txt). "tile_qubits" or
+ *                      "contig_qubits" given explicitly disable it;
  *   "graph"          : true (default) to capture each call's launches in a hipGraph and replay it;
  *   "contig_qubits"  : 1..6: qubits 0..k-1 are in every tile, so tiles move in runs of 2^k amplitudes
  *                      (default 4 for complex64, 3 for complex128: 128-byte runs);

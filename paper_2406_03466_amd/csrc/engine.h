@@ -18,8 +18,9 @@ constexpr int kBlock = 256;          // threads per workgroup for every kernel
 constexpr int kMaxGroupTerms = 8;    // Pauli terms evaluated together by one expectation item
 constexpr int kExpChunkLog2 = 12;    // amplitude pairs per expectation workgroup (4096)
 constexpr int kStrideGroupsPerBlock = 1024;
-constexpr int kRegBitsC64 = 5;       // register-tiled passes: 32 complex64 amplitudes per thread
-constexpr int kRegBitsC128 = 4;      // 16 complex128 amplitudes per thread
+constexpr int kRtileThreads = 512;  // register-tiled passes: workgroup size
+constexpr int kRegBitsC64 = 4;       // 16 complex64 amplitudes per thread (2^13-amplitude tiles)
+constexpr int kRegBitsC128 = 3;      // 8 complex128 amplitudes per thread (2^12-amplitude tiles)
 
 enum OpFlags : uint8_t { OP_TRAIN = 1 };
 
@@ -79,6 +80,7 @@ struct Seg {
     int32_t pass;
     int32_t first;        // 1: first pass of the circuit -- the tile starts as |0...0> instead of a load
     int32_t pad;
+    int64_t wait;         // persistent launch: tiles of this circuit that must be finished first
 };
 
 // Expectation work: one Pauli x-mask group of one circuit. Blocks [first_block, ...) cover its chunks.
@@ -131,6 +133,27 @@ struct LevelArgs {
     void *psi;
     void *lam;
     double *partials;
+};
+
+// One persistent launch runs every level of a direction: workgroups claim items (level blocks in level
+// order) from a queue; an item waits until its circuit's earlier passes are complete.
+struct PersistLevel {
+    int64_t first_item;   // items [first_item, next level's first_item) are this level's blocks
+    int64_t seg_off;
+    int32_t n_segs;
+    int32_t pad;
+};
+
+struct PersistArgs {
+    LevelArgs base;              // segs/n_segs are taken per level; lds_t, tab_bits, max_train are maxima
+    const PersistLevel *levels;
+    int32_t n_levels;
+    int32_t pad;
+    int64_t n_items;
+    unsigned long long *head;    // queue head, zero before the launch
+    unsigned long long *done;    // finished tiles per circuit, zero before the launch
+    int32_t *error;              // set to 1 if a wait hits its spin limit
+    int64_t spin_limit;          // sleep iterations before a wait gives up
 };
 
 // Gate matrices of a batch: for every gate record, its 2x2 complex matrix at the current parameters.
@@ -202,6 +225,9 @@ struct ShiftCombineArgs {
 int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_stride_level(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream);
+int launch_persistent(const PersistArgs &a, int precision, int adjoint, void *stream);
+int persistent_blocks(int precision, int adjoint, int lds_t, int tab_bits, int max_train, int *blocks);
+int launch_zero_u64(unsigned long long *p, int64_t n, void *stream);
 int launch_init_states(void *psi, const DevCirc *circs, const int64_t *first_block, int32_t n_circ,
                        int64_t n_blocks, int precision, void *stream);
 int launch_expectation(const ExpArgs &a, int precision, void *stream);

@@ -507,13 +507,11 @@ __device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, 
     WITH_K(RB, op.k0, r_gen<K>(v, m));
 }
 
-template <typename R, bool ADJ, int RB>
-__global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
+template <typename R, bool ADJ, int RB, int NT>
+__device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, const Seg &sg)
 {
     constexpr int N = 1 << RB;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t blk = (int64_t)blockIdx.x;
-    const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
     const int64_t tile = blk - sg.first_block;
     const DevPass P = a.passes[sg.pass];
     const DevCirc C = a.circs[sg.circ];
@@ -536,16 +534,16 @@ __global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
 
     if (!ADJ && sg.first) {
         // first pass of the circuit: the tile of |0...0> is zero except amplitude 0 of tile 0
-        for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+        for (uint32_t e = threadIdx.x; e < T; e += NT) {
             Cx<R> z;
             z.re = (R)((base == 0 && e == 0) ? 1 : 0);
             z.im = (R)0;
             sp[swz(e)] = z;
         }
     } else {
-        for (uint32_t h = threadIdx.x; h < nh; h += kBlock) segtab[h] = deposit(h, himask);
+        for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+        for (uint32_t e = threadIdx.x; e < T; e += NT) {
             const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
             sp[swz(e)] = gpsi[g];
             if (ADJ) sl[swz(e)] = glam[g];
@@ -608,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
                     }
                     if (!active) ip = 0.0;
                     ip = wave_sum_to_63(ip);
-                    if (lane == 63) red[op.train_slot * (kBlock / 64) + wave] = ip;
+                    if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
                 }
                 rop_apply<true, RB, R>(av, op, kind, mat, Et);
                 rop_apply<true, RB, R>(lv, op, kind, mat, Et);
@@ -632,21 +630,99 @@ __global__ __launch_bounds__(kBlock) void k_rtile(LevelArgs a)
     }
 
     if (ADJ) {
-        for (int slot = threadIdx.x; slot < P.n_train; slot += kBlock) {
+        for (int slot = threadIdx.x; slot < P.n_train; slot += NT) {
             double s = 0.0;
-            for (int w = 0; w < kBlock / 64; w++) s += red[slot * (kBlock / 64) + w];
+            for (int w = 0; w < NT / 64; w++) s += red[slot * (NT / 64) + w];
             a.partials[sg.partial_base + tile * P.n_train + slot] = s;
         }
     }
     if (sg.first && !ADJ) {
-        for (uint32_t h = threadIdx.x; h < nh; h += kBlock) segtab[h] = deposit(h, himask);
+        for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
         __syncthreads();
     }
-    for (uint32_t e = threadIdx.x; e < T; e += kBlock) {
+    for (uint32_t e = threadIdx.x; e < T; e += NT) {
         const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
         gpsi[g] = sp[swz(e)];
         if (ADJ) glam[g] = sl[swz(e)];
     }
+}
+
+// Forward passes ask for two workgroups per CU (at most 128 VGPRs); the adjoint keeps psi and lambda in
+// registers and runs one workgroup per CU.
+template <typename R, int RB, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rtile_fwd(LevelArgs a)
+{
+    const int64_t blk = (int64_t)blockIdx.x;
+    rtile_body<R, false, RB, NT>(a, blk, a.segs[find_block(a.segs, a.n_segs, blk)]);
+}
+
+template <typename R, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_rtile_adj(LevelArgs a)
+{
+    const int64_t blk = (int64_t)blockIdx.x;
+    rtile_body<R, true, RB, NT>(a, blk, a.segs[find_block(a.segs, a.n_segs, blk)]);
+}
+
+// Persistent form: workgroups stay resident and claim items from a queue. Items are the blocks of all
+// levels in level order, so every item an item waits for was claimed earlier by a running workgroup and
+// every wait ends. A finished tile is published with a device-scope release fence before its circuit's
+// counter is incremented; a waiting workgroup acquires after it has seen the count. Waits are bounded:
+// past spin_limit sleeps the workgroup records an error and goes on (the host reports it).
+template <typename R, bool ADJ, int RB, int NT>
+__device__ __forceinline__ void persistent_body(const PersistArgs &pa)
+{
+    __shared__ long long item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = (long long)atomicAdd(pa.head, 1ull);
+        __syncthreads();
+        const int64_t item = item_s;
+        __syncthreads();
+        if (item >= pa.n_items) break;
+        int lo = 0, hi = pa.n_levels - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pa.levels[mid].first_item <= item) lo = mid; else hi = mid - 1;
+        }
+        const PersistLevel lv = pa.levels[lo];
+        LevelArgs a = pa.base;
+        a.segs = pa.base.segs + lv.seg_off;
+        a.n_segs = lv.n_segs;
+        const int64_t blk = item - lv.first_item;
+        const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
+        if (threadIdx.x == 0 && sg.wait > 0) {
+            int64_t spins = 0;
+            while ((int64_t)__hip_atomic_load(pa.done + sg.circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < sg.wait) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > pa.spin_limit) { atomicOr(pa.error, 1); break; }
+            }
+            __threadfence();
+        }
+        __syncthreads();
+        rtile_body<R, ADJ, RB, NT>(a, blk, sg);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            atomicAdd(pa.done + sg.circ, 1ull);
+        }
+    }
+}
+
+template <typename R, int RB, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rtile_fwd_persist(PersistArgs pa)
+{
+    persistent_body<R, false, RB, NT>(pa);
+}
+
+template <typename R, int RB, int NT>
+__global__ __launch_bounds__(NT) void k_rtile_adj_persist(PersistArgs pa)
+{
+    persistent_body<R, true, RB, NT>(pa);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -944,18 +1020,86 @@ int prepare_kernels()
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<double, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<float, false, kRegBitsC64>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd<float, kRegBitsC64, kRtileThreads>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<float, true, kRegBitsC64>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj<float, kRegBitsC64, kRtileThreads>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<double, false, kRegBitsC128>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd<double, kRegBitsC128, kRtileThreads>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile<double, true, kRegBitsC128>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj<double, kRegBitsC128, kRtileThreads>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     return e;
+}
+
+static size_t rtile_lds_bytes(int precision, int adjoint, int lds_t, int tab_bits, int max_train)
+{
+    const int amp = precision == QV_C64 ? 8 : 16;
+    return tile_lds_bytes(lds_t, tab_bits, amp, adjoint) +
+           (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)max_train : 0);
+}
+
+int persistent_blocks(int precision, int adjoint, int lds_t, int tab_bits, int max_train, int *blocks)
+{
+    const size_t lds = rtile_lds_bytes(precision, adjoint, lds_t, tab_bits, max_train) + 64;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const void *k = precision == QV_C64
+                        ? (adjoint ? reinterpret_cast<const void *>(&k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>)
+                                   : reinterpret_cast<const void *>(&k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>))
+                        : (adjoint ? reinterpret_cast<const void *>(&k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>)
+                                   : reinterpret_cast<const void *>(&k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>));
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kRtileThreads, lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    *blocks = (per_cu < 1 ? 1 : per_cu) * cus;
+    return hipSuccess;
+}
+
+int launch_persistent(const PersistArgs &a, int precision, int adjoint, void *stream)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t lds = rtile_lds_bytes(precision, adjoint, a.base.lds_t, a.base.tab_bits, a.base.max_train);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    int blocks = 0;
+    hipError_t e = (hipError_t)persistent_blocks(precision, adjoint, a.base.lds_t, a.base.tab_bits, a.base.max_train,
+                                                 &blocks);
+    if (e != hipSuccess) return e;
+    if ((int64_t)blocks > a.n_items) blocks = (int)a.n_items;
+    const dim3 grid((unsigned)blocks), block(kRtileThreads);
+    if (precision == QV_C64) {
+        if (adjoint) hipLaunchKernelGGL((k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
+    } else {
+        if (adjoint) hipLaunchKernelGGL((k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+int launch_zero_u64(unsigned long long *p, int64_t n, void *stream)
+{
+    if (n <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
@@ -964,15 +1108,15 @@ int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int amp = precision == QV_C64 ? 8 : 16;
     const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint) +
-                       (adjoint ? sizeof(double) * (kBlock / 64) * (size_t)a.max_train : 0);
+                       (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)a.max_train : 0);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    dim3 grid((unsigned)a.n_blocks), block(kBlock);
+    dim3 grid((unsigned)a.n_blocks), block(kRtileThreads);
     if (precision == QV_C64) {
-        if (adjoint) hipLaunchKernelGGL((k_rtile<float, true, kRegBitsC64>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_rtile<float, false, kRegBitsC64>), grid, block, lds, s, a);
+        if (adjoint) hipLaunchKernelGGL((k_rtile_adj<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_rtile_fwd<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
     } else {
-        if (adjoint) hipLaunchKernelGGL((k_rtile<double, true, kRegBitsC128>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_rtile<double, false, kRegBitsC128>), grid, block, lds, s, a);
+        if (adjoint) hipLaunchKernelGGL((k_rtile_adj<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_rtile_fwd<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }

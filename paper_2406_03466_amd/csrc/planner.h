@@ -45,7 +45,7 @@ struct Plan {
 };
 
 // Most trainable gates one pass may hold (their adjoint partial sums live in LDS).
-constexpr int kMaxTrainPerPass = 512;
+constexpr int kMaxTrainPerPass = 256;
 
 // LDS tile plan with tiles of at most `tile_qubits` qubits, the lowest `lowc` qubits always local.
 // reg_bits > 0 splits every pass of at least reg_bits qubits into register segments of 2^reg_bits

@@ -43,6 +43,12 @@ static qv_status ok()
     return QV_OK;
 }
 
+#define HIPRET(expr)                                    \
+    do {                                                \
+        hipError_t e_ = (hipError_t)(expr);             \
+        if (e_ != hipSuccess) return e_;                \
+    } while (0)
+
 #define HIPCHK(expr)                                                                                   \
     do {                                                                                               \
         hipError_t e_ = (hipError_t)(expr);                                                            \
@@ -110,6 +116,8 @@ struct qv_ctx_s {
     int n_vqpu = 0;             // 0: all circuits in flight
     int launch_events = 0;      // 1: record a HIP event pair around every launch (eager mode)
     int contig = 0;             // qubits 0..contig-1 always local (0: 4 for complex64, 3 for complex128)
+    int autotune = 1;           // 0 off, 1 cached (use a stored choice), 2 search (time candidates once)
+    int persistent = 0;         // 1: one persistent work-queue launch per direction instead of one per level
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
@@ -117,6 +125,19 @@ struct qv_ctx_s {
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DBuf &operator=(DBuf &&o) noexcept
+    {
+        if (this != &o) {
+            if (p) (void)hipFree(p);
+            p = o.p; bytes = o.bytes;
+            o.p = nullptr; o.bytes = 0;
+        }
+        return *this;
+    }
     ~DBuf() { if (p) (void)hipFree(p); }
     hipError_t alloc(size_t b)
     {
@@ -231,6 +252,18 @@ struct ExecSet {
     DBuf d_circs, d_segs, d_init_fb, d_groups, d_terms, d_tv_begin, d_term_refs, d_norm_refs, d_coeff;
     DBuf d_lam_fb, d_obs_begin, d_obs, d_gref_begin, d_grefs;
     DBuf d_exp_partials, d_adj_partials;
+    // persistent launches (one per direction), built when every level of the direction is register-tiled
+    std::vector<PersistLevel> p_fwd, p_rev;
+    int64_t p_fwd_items = 0, p_rev_items = 0;
+    int p_fwd_ok = 0, p_rev_ok = 0;
+    int32_t p_lds_t[2] = {0, 0}, p_tab_bits[2] = {0, 0}, p_max_train[2] = {0, 0};
+    DBuf d_p_fwd, d_p_rev, d_p_head, d_p_done, d_p_error;
+};
+
+// Device form of a batch's plans (shared by all its circuits and parameter-shift variants).
+struct DevPlans {
+    DBuf passes, ops, rsegs;
+    std::vector<int> pass_base;
 };
 
 struct qv_batch_s {
@@ -253,6 +286,9 @@ struct qv_batch_s {
     std::vector<Plan> plans;
     std::vector<int> plan_of;          // per circuit
     int tile_qubits = 0;
+    int contig = 0;
+    std::unique_ptr<DevPlans> dp;
+    int tuned = 0;                     // 1 once the autotuner (or its cache) has chosen the configuration
 
     ExecSet main;
     // parameter-shift chunks
@@ -401,6 +437,12 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         s.pass = pass_base[es.plan_of[c]] + p;
                         s.first = (dir == 0 && p == 0 && !pp.stride) ? 1 : 0;
                         s.pad = 0;
+                        s.wait = 0;
+                        if (dir == 0) {
+                            for (int q = 0; q < p; q++) s.wait += tiles_of(es.circs[c], pl, q);
+                        } else {
+                            for (int q = p + 1; q < np; q++) s.wait += tiles_of(es.circs[c], pl, q);
+                        }
                         es.segs.push_back(s);
                         lv.n_segs++;
                         lv.n_blocks += tiles_of(es.circs[c], pl, p);
@@ -425,6 +467,29 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
         if (needs) es.init_bytes += amps * amp_bytes;
     }
     es.init_blocks = es.init_first_block[N];
+    for (int dir = 0; dir < 2; dir++) {
+        const std::vector<Level> &lvs = dir == 0 ? es.fwd : es.rev;
+        std::vector<PersistLevel> &pl = dir == 0 ? es.p_fwd : es.p_rev;
+        int64_t items = 0;
+        int ok = 1;
+        pl.clear();
+        es.p_lds_t[dir] = es.p_tab_bits[dir] = es.p_max_train[dir] = 0;
+        for (const Level &lv : lvs) {
+            if (lv.kind != LK_RTILE) ok = 0;
+            PersistLevel p;
+            p.first_item = items;
+            p.seg_off = lv.seg_off;
+            p.n_segs = lv.n_segs;
+            p.pad = 0;
+            pl.push_back(p);
+            items += lv.n_blocks;
+            es.p_lds_t[dir] = std::max(es.p_lds_t[dir], lv.lds_t);
+            es.p_tab_bits[dir] = std::max(es.p_tab_bits[dir], lv.tab_bits);
+            es.p_max_train[dir] = std::max(es.p_max_train[dir], lv.max_train);
+        }
+        (dir == 0 ? es.p_fwd_items : es.p_rev_items) = items;
+        (dir == 0 ? es.p_fwd_ok : es.p_rev_ok) = ok && !lvs.empty();
+    }
     es.algo_bytes_fwd = es.init_bytes;
     for (const Level &lv : es.fwd) es.algo_bytes_fwd += lv.bytes;
 }
@@ -584,6 +649,12 @@ static hipError_t upload_set(ExecSet &es, bool adjoint_parts)
     if ((e = es.d_norm_refs.upload(es.norm_refs)) != hipSuccess) return e;
     if ((e = es.d_coeff.upload(es.out_coeff)) != hipSuccess) return e;
     if ((e = es.d_exp_partials.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, es.exp_partials))) != hipSuccess) return e;
+    if ((e = es.d_p_fwd.upload(es.p_fwd)) != hipSuccess) return e;
+    if ((e = es.d_p_rev.upload(es.p_rev)) != hipSuccess) return e;
+    if ((e = es.d_p_head.alloc(sizeof(unsigned long long))) != hipSuccess) return e;
+    if ((e = es.d_p_done.alloc(sizeof(unsigned long long) * (size_t)std::max(1, es.n_circ))) != hipSuccess) return e;
+    if ((e = es.d_p_error.alloc(sizeof(int32_t))) != hipSuccess) return e;
+    if ((e = hipMemset(es.d_p_error.p, 0, sizeof(int32_t))) != hipSuccess) return e;
     if (adjoint_parts) {
         if ((e = es.d_lam_fb.upload(es.lam_first_block)) != hipSuccess) return e;
         if ((e = es.d_obs_begin.upload(es.obs_begin)) != hipSuccess) return e;
@@ -598,12 +669,7 @@ static hipError_t upload_set(ExecSet &es, bool adjoint_parts)
 // ---------------------------------------------------------------------------------------------------------
 // Launch sequences
 // ---------------------------------------------------------------------------------------------------------
-struct DevPlans {
-    DBuf passes, ops, rsegs;
-    std::vector<int> pass_base;
-};
 
-static std::unordered_map<const qv_batch_s *, std::unique_ptr<DevPlans>> g_devplans;
 
 static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPlans &dp, const Level &lv,
                             void *psi, void *lam)
@@ -647,12 +713,40 @@ static int enqueue_matrices(const qv_batch_s &bt, hipStream_t s, LaunchLog *log)
     MatArgs ma;
     ma.gates = bt.d_gates.as<qv_gate>();
     ma.gate_circ = bt.d_gate_circ.as<int32_t>();
-    ma.ops = g_devplans.at(&bt)->ops.as<DevOp>();
+    ma.ops = bt.dp->ops.as<DevOp>();
     ma.circs = bt.main.d_circs.as<DevCirc>();
     ma.theta = bt.d_theta.as<double>();
     ma.mats = bt.d_mats.p;
     ma.n_gates = (int64_t)bt.gates.size();
     return logged(log, s, QV_K_MATRICES, -1, 0, [&] { return launch_matrices(ma, bt.prec, s); });
+}
+
+// One persistent launch for all levels of a direction (see k_rtile_*_persist).
+static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, int dir, void *psi, void *lam,
+                              hipStream_t s, LaunchLog *log)
+{
+    const std::vector<Level> &lvs = dir == 0 ? es.fwd : es.rev;
+    int e = launch_zero_u64(es.d_p_head.as<unsigned long long>(), 1, s);
+    if (!e) e = launch_zero_u64(es.d_p_done.as<unsigned long long>(), es.n_circ, s);
+    if (e) return e;
+    PersistArgs pa;
+    pa.base = level_args(bt, es, dp, lvs[0], psi, lam);
+    pa.base.segs = es.d_segs.as<Seg>();
+    pa.base.lds_t = es.p_lds_t[dir];
+    pa.base.tab_bits = es.p_tab_bits[dir];
+    pa.base.max_train = es.p_max_train[dir];
+    pa.levels = (dir == 0 ? es.d_p_fwd : es.d_p_rev).as<PersistLevel>();
+    pa.n_levels = (int32_t)lvs.size();
+    pa.pad = 0;
+    pa.n_items = dir == 0 ? es.p_fwd_items : es.p_rev_items;
+    pa.head = es.d_p_head.as<unsigned long long>();
+    pa.done = es.d_p_done.as<unsigned long long>();
+    pa.error = es.d_p_error.as<int32_t>();
+    pa.spin_limit = (int64_t)1 << 25;
+    int64_t bytes = 0;
+    for (const Level &lv : lvs) bytes += lv.bytes;
+    return logged(log, s, dir == 0 ? QV_K_RTILE_PERSIST : QV_K_RTILE_ADJ_PERSIST, -1, bytes,
+                  [&] { return launch_persistent(pa, bt.prec, dir, s); });
 }
 
 static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, void *psi, double *energies,
@@ -663,11 +757,16 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
                                   es.init_blocks, bt.prec, s);
     });
     if (e) return e;
-    for (size_t L = 0; L < es.fwd.size(); L++) {
-        const Level &lv = es.fwd[L];
-        LevelArgs a = level_args(bt, es, dp, lv, psi, nullptr);
-        e = logged(log, s, log_id(lv, 0), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 0, s); });
+    if (bt.ctx->persistent && es.p_fwd_ok) {
+        e = enqueue_persistent(bt, es, dp, 0, psi, nullptr, s, log);
         if (e) return e;
+    } else {
+        for (size_t L = 0; L < es.fwd.size(); L++) {
+            const Level &lv = es.fwd[L];
+            LevelArgs a = level_args(bt, es, dp, lv, psi, nullptr);
+            e = logged(log, s, log_id(lv, 0), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 0, s); });
+            if (e) return e;
+        }
     }
     ExpArgs ea;
     ea.groups = es.d_groups.as<DevGroup>();
@@ -706,11 +805,16 @@ static int enqueue_adjoint(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     la.n_blocks = es.lam_blocks;
     int e = logged(log, s, QV_K_LAMBDA, -1, es.lam_bytes, [&] { return launch_lambda(la, bt.prec, s); });
     if (e) return e;
-    for (size_t L = 0; L < es.rev.size(); L++) {
-        const Level &lv = es.rev[L];
-        LevelArgs a = level_args(bt, es, dp, lv, bt.d_psi.p, bt.d_lam.p);
-        e = logged(log, s, log_id(lv, 1), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 1, s); });
+    if (bt.ctx->persistent && es.p_rev_ok) {
+        e = enqueue_persistent(bt, es, dp, 1, bt.d_psi.p, bt.d_lam.p, s, log);
         if (e) return e;
+    } else {
+        for (size_t L = 0; L < es.rev.size(); L++) {
+            const Level &lv = es.rev[L];
+            LevelArgs a = level_args(bt, es, dp, lv, bt.d_psi.p, bt.d_lam.p);
+            e = logged(log, s, log_id(lv, 1), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 1, s); });
+            if (e) return e;
+        }
     }
     GradReduceArgs ga;
     ga.n_out = (int32_t)bt.n_grad;
@@ -765,8 +869,15 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
         } else if (k == "launch_events") {
             c->launch_events = (v == "true" || v == "1");
         } else if (k == "launch") {
-            if (v != "levels") return fail(QV_E_UNSUPPORTED, "launch mode \"%s\" is not available", v.c_str());
-        } else if (k == "autotune" || k == "fusion_k" || k == "precision" || k == "deterministic") {
+            if (v == "levels") c->persistent = 0;
+            else if (v == "persistent") c->persistent = 1;
+            else return fail(QV_E_INVALID, "launch must be \"levels\" or \"persistent\"");
+        } else if (k == "autotune") {
+            if (v == "off") c->autotune = 0;
+            else if (v == "cached") c->autotune = 1;
+            else if (v == "search") c->autotune = 2;
+            else return fail(QV_E_INVALID, "autotune must be \"off\", \"cached\" or \"search\"");
+        } else if (k == "fusion_k" || k == "precision" || k == "deterministic") {
             /* accepted for compatibility; the current planner ignores them */
         } else {
             return fail(QV_E_INVALID, "unknown option \"%s\"", k.c_str());
@@ -824,6 +935,121 @@ static int default_tile_qubits(qv_precision p, bool adjoint)
     return t;
 }
 
+static void drop_graphs(qv_batch_s *bt)
+{
+    if (bt->g_fwd) (void)hipGraphExecDestroy(bt->g_fwd);
+    if (bt->g_adj) (void)hipGraphExecDestroy(bt->g_adj);
+    if (bt->g_ps) (void)hipGraphExecDestroy(bt->g_ps);
+    bt->g_fwd = bt->g_adj = bt->g_ps = nullptr;
+    bt->ps_chunks.clear();
+    bt->ps_chunk_var0.clear();
+    bt->ps_ready = false;
+    bt->fwd_valid = false;
+}
+
+// (Re)builds the plans, their device form and the batch's launch structure for a tile size and a
+// contiguous-run length. Cached graphs and parameter-shift chunks are dropped; state buffers are kept.
+static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
+{
+    qv_ctx ctx = bt->ctx;
+    const int B = bt->B;
+    const qv_precision prec = bt->prec;
+    const int32_t *nq = bt->nq.data();
+    const int64_t *goff = bt->goff.data();
+    const qv_gate *gates = bt->gates.data();
+    const int32_t *np = bt->nparams.data();
+    const int params_shared = bt->params_shared;
+    const int obs_shared = bt->obs_shared;
+    drop_graphs(bt);
+    bt->plans.clear();
+    bt->main = ExecSet{};
+    // plans: circuits with the same structure share one
+    // The adjoint sweep holds two tiles (psi and lambda) in LDS, so a plan's tiles are capped at
+    // 2^13 amplitudes for complex64 and 2^12 for complex128 (2 x 64 KiB plus the index table).
+    bt->tile_qubits = tile_qubits ? tile_qubits : default_tile_qubits(prec, false);
+    bt->tile_qubits = std::min(bt->tile_qubits, prec == QV_C64 ? 13 : 12);
+    bt->contig = contig ? contig : (prec == QV_C64 ? 4 : 3);
+    std::unordered_map<std::string, int> sig2plan;
+    bt->plan_of.resize(B);
+    for (int b = 0; b < B; b++) {
+        std::string sig((const char *)&nq[b], sizeof(int32_t));
+        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
+            const qv_gate &g = gates[k];
+            int32_t rec[4] = {g.kind, g.q0, is_two_qubit(g.kind) ? g.q1 : -1, (is_rotation(g.kind) && g.param >= 0) ? 1 : 0};
+            sig.append((const char *)rec, sizeof rec);
+        }
+        auto it = sig2plan.find(sig);
+        if (it != sig2plan.end()) { bt->plan_of[b] = it->second; continue; }
+        const int id = (int)bt->plans.size();
+        sig2plan.emplace(sig, id);
+        bt->plan_of[b] = id;
+        PlanInput pin;
+        pin.n = nq[b];
+        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
+            const qv_gate &g = gates[k];
+            pin.kinds.push_back(g.kind);
+            pin.q0.push_back(g.q0);
+            pin.q1.push_back(is_two_qubit(g.kind) ? g.q1 : -1);
+            pin.trainable.push_back(is_rotation(g.kind) && g.param >= 0);
+        }
+        const int lowc = bt->contig;
+        const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
+        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb));
+    }
+    // device plan arrays
+    auto dp = std::make_unique<DevPlans>();
+    std::vector<DevPass> passes;
+    std::vector<DevOp> ops;
+    std::vector<DevSeg> rsegs;
+    std::vector<int64_t> plan_op_base;
+    for (const Plan &pl : bt->plans) {
+        dp->pass_base.push_back((int)passes.size());
+        plan_op_base.push_back((int64_t)ops.size());
+        lower_plan(pl, passes, ops, rsegs);
+    }
+    HIPRET(dp->passes.upload(passes));
+    HIPRET(dp->ops.upload(ops));
+    HIPRET(dp->rsegs.upload(rsegs));
+
+    // main set
+    ExecSet &es = bt->main;
+    es.n_circ = B;
+    es.circs.resize(B);
+    es.plan_of = bt->plan_of;
+    int64_t off = 0, pb = 0;
+    for (int b = 0; b < B; b++) {
+        DevCirc &c = es.circs[b];
+        c.state_off = off;
+        c.gate_off = goff[b];
+        c.param_base = params_shared ? 0 : pb;
+        c.n = nq[b];
+        c.shift_gate = -1;
+        c.shift = 0.0;
+        c.base_circ = b;
+        c.pad = 0;
+        c.op_base = plan_op_base[bt->plan_of[b]];
+        off += (int64_t)1 << nq[b];
+        pb += np[b];
+    }
+    es.state_amps = off;
+    build_levels(es, bt->plans, dp->pass_base, ctx->n_vqpu, bt->amp_bytes);
+    ObsView ov{bt->toff.data(), bt->xm.data(), bt->zm.data(), bt->cf.data(), bt->obs_shared};
+    std::vector<int> obs_of(B);
+    std::vector<int64_t> out_base(B);
+    const int64_t Tsh = obs_shared ? bt->toff[1] - bt->toff[0] : 0;
+    for (int b = 0; b < B; b++) {
+        obs_of[b] = b;
+        out_base[b] = obs_shared ? (int64_t)b * Tsh : bt->toff[b];
+    }
+    build_expectation(es, ov, obs_of, out_base, bt->n_tv, true, bt->amp_bytes);
+    build_lambda(es, ov, obs_of, bt->amp_bytes);
+    build_grad_refs(es, *bt, dp->pass_base);
+    HIPRET(upload_set(es, true));
+
+    bt->dp = std::move(dp);
+    return hipSuccess;
+}
+
 qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_t *goff, const qv_gate *gates,
                           const int32_t *np, int32_t params_shared, const int64_t *toff, const uint64_t *xm,
                           const uint64_t *zm, const double *cf, int32_t obs_shared, qv_precision prec,
@@ -868,87 +1094,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     if (need > 0.92 * (double)freeb)
         return fail(QV_E_OOM, "states need %.2f GiB, device has %.2f GiB free", need / 1073741824.0, freeb / 1073741824.0);
 
-    // plans: circuits with the same structure share one
-    // The adjoint sweep holds two tiles (psi and lambda) in LDS, so a plan's tiles are capped at
-    // 2^13 amplitudes for complex64 and 2^12 for complex128 (2 x 64 KiB plus the index table).
-    bt->tile_qubits = ctx->tile_qubits ? ctx->tile_qubits : default_tile_qubits(prec, false);
-    bt->tile_qubits = std::min(bt->tile_qubits, prec == QV_C64 ? 13 : 12);
-    std::unordered_map<std::string, int> sig2plan;
-    bt->plan_of.resize(B);
-    for (int b = 0; b < B; b++) {
-        std::string sig((const char *)&nq[b], sizeof(int32_t));
-        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
-            const qv_gate &g = gates[k];
-            int32_t rec[4] = {g.kind, g.q0, is_two_qubit(g.kind) ? g.q1 : -1, (is_rotation(g.kind) && g.param >= 0) ? 1 : 0};
-            sig.append((const char *)rec, sizeof rec);
-        }
-        auto it = sig2plan.find(sig);
-        if (it != sig2plan.end()) { bt->plan_of[b] = it->second; continue; }
-        const int id = (int)bt->plans.size();
-        sig2plan.emplace(sig, id);
-        bt->plan_of[b] = id;
-        PlanInput pin;
-        pin.n = nq[b];
-        for (int64_t k = goff[b]; k < goff[b + 1]; k++) {
-            const qv_gate &g = gates[k];
-            pin.kinds.push_back(g.kind);
-            pin.q0.push_back(g.q0);
-            pin.q1.push_back(is_two_qubit(g.kind) ? g.q1 : -1);
-            pin.trainable.push_back(is_rotation(g.kind) && g.param >= 0);
-        }
-        const int lowc = ctx->contig ? ctx->contig : (prec == QV_C64 ? 4 : 3);
-        const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
-        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb));
-    }
-    // device plan arrays
-    auto dp = std::make_unique<DevPlans>();
-    std::vector<DevPass> passes;
-    std::vector<DevOp> ops;
-    std::vector<DevSeg> rsegs;
-    std::vector<int64_t> plan_op_base;
-    for (const Plan &pl : bt->plans) {
-        dp->pass_base.push_back((int)passes.size());
-        plan_op_base.push_back((int64_t)ops.size());
-        lower_plan(pl, passes, ops, rsegs);
-    }
-    HIPCHK(dp->passes.upload(passes));
-    HIPCHK(dp->ops.upload(ops));
-    HIPCHK(dp->rsegs.upload(rsegs));
-
-    // main set
-    ExecSet &es = bt->main;
-    es.n_circ = B;
-    es.circs.resize(B);
-    es.plan_of = bt->plan_of;
-    int64_t off = 0, pb = 0;
-    for (int b = 0; b < B; b++) {
-        DevCirc &c = es.circs[b];
-        c.state_off = off;
-        c.gate_off = goff[b];
-        c.param_base = params_shared ? 0 : pb;
-        c.n = nq[b];
-        c.shift_gate = -1;
-        c.shift = 0.0;
-        c.base_circ = b;
-        c.pad = 0;
-        c.op_base = plan_op_base[bt->plan_of[b]];
-        off += (int64_t)1 << nq[b];
-        pb += np[b];
-    }
-    es.state_amps = off;
-    build_levels(es, bt->plans, dp->pass_base, ctx->n_vqpu, bt->amp_bytes);
-    ObsView ov{bt->toff.data(), bt->xm.data(), bt->zm.data(), bt->cf.data(), bt->obs_shared};
-    std::vector<int> obs_of(B);
-    std::vector<int64_t> out_base(B);
-    const int64_t Tsh = obs_shared ? bt->toff[1] - bt->toff[0] : 0;
-    for (int b = 0; b < B; b++) {
-        obs_of[b] = b;
-        out_base[b] = obs_shared ? (int64_t)b * Tsh : bt->toff[b];
-    }
-    build_expectation(es, ov, obs_of, out_base, bt->n_tv, true, bt->amp_bytes);
-    build_lambda(es, ov, obs_of, bt->amp_bytes);
-    build_grad_refs(es, *bt, dp->pass_base);
-    HIPCHK(upload_set(es, true));
+    HIPCHK(configure(bt.get(), ctx->tile_qubits, ctx->contig));
 
     HIPCHK(bt->d_gates.upload(bt->gates));
     {
@@ -959,7 +1105,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
         HIPCHK(bt->d_mats.alloc((size_t)std::max<int64_t>(1, (int64_t)bt->gates.size()) * 8 * (bt->amp_bytes / 2)));
     }
     HIPCHK(bt->d_theta.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_theta)));
-    HIPCHK(bt->d_psi.alloc((size_t)off * bt->amp_bytes));
+    HIPCHK(bt->d_psi.alloc((size_t)bt->main.state_amps * bt->amp_bytes));
     HIPCHK(bt->d_energies.alloc(sizeof(double) * B));
     HIPCHK(bt->d_tv.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_tv)));
     HIPCHK(bt->d_norms.alloc(sizeof(double) * B));
@@ -968,7 +1114,6 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     HIPCHK(hipEventCreate(&bt->ev0));
     HIPCHK(hipEventCreate(&bt->ev1));
     if (bt->n_theta == 0) bt->theta_set = true;
-    g_devplans[bt.get()] = std::move(dp);
     *out = bt.release();
     return ok();
 }
@@ -1017,9 +1162,123 @@ static qv_status run_graph(qv_batch bt, hipGraphExec_t &cache, F fn)
     return QV_OK;
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// Autotuner: picks the tile size and the contiguous-run length of a batch by timing one forward pass per
+// candidate on the device, and remembers the choice in a small text cache keyed by device architecture,
+// precision, engine and the batch's shape (circuits, largest register, distinct structures, largest gate
+// count). Explicit "tile_qubits" / "contig_qubits" options always win.
+// ---------------------------------------------------------------------------------------------------------
+static std::string tune_path()
+{
+    const char *p = getenv("QV_TUNE_CACHE");
+    if (p && *p) return p;
+    const char *h = getenv("HOME");
+    return std::string(h && *h ? h : "/tmp") + "/.cache/qvpu_tune.txt";
+}
+
+static std::string tune_key(const qv_batch_s *bt)
+{
+    int nmax = 0;
+    int64_t gmax = 0;
+    for (int b = 0; b < bt->B; b++) {
+        nmax = std::max(nmax, bt->nq[b]);
+        gmax = std::max<int64_t>(gmax, bt->goff[b + 1] - bt->goff[b]);
+    }
+    hipDeviceProp_t prop;
+    std::string arch = "gfx";
+    if (hipGetDeviceProperties(&prop, bt->ctx->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/%s/%s/B%d/n%d/s%d/g%lld", arch.c_str(), bt->prec == QV_C64 ? "c64" : "c128",
+             bt->ctx->engine == 0 ? "tiled" : "lds", bt->B, nmax, (int)bt->plans.size(), (long long)gmax);
+    return buf;
+}
+
+static bool tune_lookup(const std::string &key, int &T, int &contig)
+{
+    FILE *f = fopen(tune_path().c_str(), "r");
+    if (!f) return false;
+    char k[256];
+    int t = 0, c = 0;
+    double ms = 0;
+    bool found = false;
+    while (fscanf(f, "%255s %d %d %lf", k, &t, &c, &ms) == 4)
+        if (key == k) { T = t; contig = c; found = true; }
+    fclose(f);
+    return found;
+}
+
+static void tune_store(const std::string &key, int T, int contig, double ms)
+{
+    const std::string path = tune_path();
+    FILE *f = fopen(path.c_str(), "a");
+    if (!f) return;  // the cache is an optimisation only
+    fprintf(f, "%s %d %d %.6f\n", key.c_str(), T, contig, ms);
+    fclose(f);
+}
+
+static qv_status time_forward(qv_batch bt, double &ms)
+{
+    hipStream_t s = bt->ctx->stream();
+    DevPlans &dp = *bt->dp;
+    for (int rep = 0; rep < 2; rep++) {
+        if (rep == 1) HIPCHK(hipEventRecord(bt->ev0, s));
+        int e = enqueue_matrices(*bt, s, nullptr);
+        if (!e) e = enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                                    bt->d_norms.as<double>(), s, nullptr);
+        if (e) return fail(QV_E_DEVICE, "autotune launch failed: %s", hipGetErrorString((hipError_t)e));
+    }
+    HIPCHK(hipEventRecord(bt->ev1, s));
+    HIPCHK(hipEventSynchronize(bt->ev1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, bt->ev0, bt->ev1));
+    ms = f;
+    return QV_OK;
+}
+
+static qv_status autotune(qv_batch bt)
+{
+    bt->tuned = 1;
+    qv_ctx ctx = bt->ctx;
+    if (ctx->autotune == 0 || ctx->engine == 2 || ctx->tile_qubits || ctx->contig) return QV_OK;
+    int nmax = 0;
+    for (int b = 0; b < bt->B; b++) nmax = std::max(nmax, bt->nq[b]);
+    const int tmax = bt->prec == QV_C64 ? 13 : 12;
+    if (nmax <= tmax) return QV_OK;  // every circuit is one whole-state pass: nothing to choose
+    const std::string key = tune_key(bt);
+    int T = 0, contig = 0;
+    if (tune_lookup(key, T, contig)) {
+        if (T != bt->tile_qubits || contig != bt->contig) HIPCHK(configure(bt, T, contig));
+        return QV_OK;
+    }
+    if (ctx->autotune != 2) return QV_OK;
+    const int c_hi = bt->prec == QV_C64 ? 4 : 3;
+    double best = 1e300;
+    int bT = bt->tile_qubits, bc = bt->contig;
+    for (int t = tmax; t >= tmax - 2; t--) {
+        for (int c = c_hi; c >= c_hi - 1; c--) {
+            HIPCHK(configure(bt, t, c));
+            double ms = 0.0;
+            qv_status st = time_forward(bt, ms);
+            if (st != QV_OK) return st;
+            if (ms < best) { best = ms; bT = t; bc = c; }
+        }
+    }
+    HIPCHK(configure(bt, bT, bc));
+    tune_store(key, bT, bc, best);
+    return QV_OK;
+}
+
 static qv_status forward(qv_batch bt)
 {
-    DevPlans &dp = *g_devplans[bt];
+    if (!bt->tuned) {
+        qv_status st = autotune(bt);
+        if (st != QV_OK) return st;
+    }
+    DevPlans &dp = *bt->dp;
     qv_status st = run_graph(bt, bt->g_fwd, [&](hipStream_t s, LaunchLog *log) {
         const int e = enqueue_matrices(*bt, s, log);
         if (e) return e;
@@ -1032,6 +1291,23 @@ static qv_status forward(qv_batch bt)
     bt->last.passes = bt->main.passes_fwd;
     bt->last.launches = 3 + (int64_t)bt->main.fwd.size();
     bt->last.algorithmic_bytes = bt->main.algo_bytes_fwd;
+    return QV_OK;
+}
+
+// A persistent launch whose wait hit its spin limit leaves a flag behind; report it once.
+static qv_status check_persist_error(qv_batch bt)
+{
+    std::vector<ExecSet *> sets{&bt->main};
+    for (auto &c : bt->ps_chunks) sets.push_back(c.get());
+    for (ExecSet *es : sets) {
+        if (!es->d_p_error.p) continue;
+        int32_t flag = 0;
+        HIPCHK(hipMemcpy(&flag, es->d_p_error.p, sizeof flag, hipMemcpyDeviceToHost));
+        if (flag) {
+            HIPCHK(hipMemset(es->d_p_error.p, 0, sizeof(int32_t)));
+            return fail(QV_E_DEVICE, "a persistent launch gave up waiting for a dependency; its results are invalid");
+        }
+    }
     return QV_OK;
 }
 
@@ -1054,7 +1330,10 @@ qv_status qv_batch_expectations(qv_batch bt, double *energies, double *term_valu
     bt->timed = true;
     if ((st = copy_out(bt, energies, bt->d_energies.p, sizeof(double) * bt->B, out_on_device)) != QV_OK) return st;
     if ((st = copy_out(bt, term_values, bt->d_tv.p, sizeof(double) * (size_t)bt->n_tv, out_on_device)) != QV_OK) return st;
-    if (!out_on_device) HIPCHK(hipStreamSynchronize(bt->ctx->stream()));
+    if (!out_on_device) {
+        HIPCHK(hipStreamSynchronize(bt->ctx->stream()));
+        if ((st = check_persist_error(bt)) != QV_OK) return st;
+    }
     return ok();
 }
 
@@ -1074,7 +1353,7 @@ static qv_status ensure_lambda(qv_batch bt)
 static qv_status ensure_param_shift(qv_batch bt)
 {
     if (bt->ps_ready) return QV_OK;
-    DevPlans &dp = *g_devplans[bt];
+    DevPlans &dp = *bt->dp;
     struct Occ { int b; int k; int64_t out; };
     std::vector<Occ> occ;
     std::vector<int64_t> pbase(bt->B + 1, 0);
@@ -1181,7 +1460,7 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
         int e = launch_fill(bt->d_upstream.as<double>(), bt->B, 1.0, s);
         if (e) return fail(QV_E_DEVICE, "fill failed: %s", hipGetErrorString((hipError_t)e));
     }
-    DevPlans &dp = *g_devplans[bt];
+    DevPlans &dp = *bt->dp;
     qv_status st;
     HIPCHK(hipEventRecord(bt->ev0, s));
     if (method == QV_ADJOINT) {
@@ -1245,7 +1524,10 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
     bt->timed = true;
     if ((st = copy_out(bt, grad, bt->d_grad.p, sizeof(double) * (size_t)bt->n_grad, on_device)) != QV_OK) return st;
     if ((st = copy_out(bt, energies, bt->d_energies.p, sizeof(double) * bt->B, on_device)) != QV_OK) return st;
-    if (!on_device) HIPCHK(hipStreamSynchronize(s));
+    if (!on_device) {
+        HIPCHK(hipStreamSynchronize(s));
+        if ((st = check_persist_error(bt)) != QV_OK) return st;
+    }
     return ok();
 }
 
@@ -1281,7 +1563,15 @@ qv_status qv_batch_stats(qv_batch bt, qv_stats *out)
         for (double v : nrm) m = std::max(m, std::fabs(v - 1.0));
         bt->last.norm_err_max = m;
     }
+    qv_status pst = check_persist_error(bt);
+    if (pst != QV_OK) return pst;
     *out = bt->last;
+    out->tile_qubits = bt->tile_qubits;
+    out->contig_qubits = bt->contig;
+    int pmax = 0;
+    for (const Plan &pl : bt->plans) pmax = std::max(pmax, (int)pl.passes.size());
+    out->passes_per_circuit_max = pmax;
+    out->pad = 0;
     return ok();
 }
 
@@ -1290,12 +1580,9 @@ qv_status qv_batch_destroy(qv_batch bt)
     if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
     (void)hipSetDevice(bt->ctx->device);
     (void)hipStreamSynchronize(bt->ctx->stream());
-    if (bt->g_fwd) (void)hipGraphExecDestroy(bt->g_fwd);
-    if (bt->g_adj) (void)hipGraphExecDestroy(bt->g_adj);
-    if (bt->g_ps) (void)hipGraphExecDestroy(bt->g_ps);
+    drop_graphs(bt);
     if (bt->ev0) (void)hipEventDestroy(bt->ev0);
     if (bt->ev1) (void)hipEventDestroy(bt->ev1);
-    g_devplans.erase(bt);
     delete bt;
     return ok();
 }

@@ -33,7 +33,8 @@ class QvError(RuntimeError):
 
 class qv_stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int64), ("launches", ctypes.c_int64), ("algorithmic_bytes", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double), ("norm_err_max", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double), ("norm_err_max", ctypes.c_double), ("tile_qubits", ctypes.c_int32),
+                ("contig_qubits", ctypes.c_int32), ("passes_per_circuit_max", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class qv_launch_rec(ctypes.Structure):
@@ -42,7 +43,8 @@ class qv_launch_rec(ctypes.Structure):
 
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
-                "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices"]
+                "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices", "rtile_persist",
+                "rtile_adj_persist"]
 
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),

@@ -81,7 +81,8 @@ def test_c1_expectations(qv, prec, opts):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"engine": "lds"},
-                                  {"engine": "lds", "tile_qubits": 7}])
+                                  {"engine": "lds", "tile_qubits": 7}, {"launch": "persistent"},
+                                  {"launch": "persistent", "tile_qubits": 6}])
 def test_c1_gradients(qv, prec, opts):
     say(f"c1 gradients prec={prec} opts={opts}")
     wl = W.config1()
@@ -117,7 +118,8 @@ def test_c2_full(qv, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("tile,engine", [(6, "tiled"), (9, "tiled"), (None, "tiled"), (8, "lds"), (None, "lds")])
+@pytest.mark.parametrize("tile,engine", [(6, "tiled"), (9, "tiled"), (None, "tiled"), (8, "lds"), (None, "lds"),
+                                         (9, "persistent"), (None, "persistent")])
 def test_uneven_batch(qv, prec, tile, engine):
     """Circuits of 2..16 qubits and 0..80 gates in one batch: per-circuit energies, terms, states and
     adjoint gradients (own parameters per circuit) with upstream weights."""
@@ -126,7 +128,9 @@ def test_uneven_batch(qv, prec, tile, engine):
     e_ref, tv_ref, _, _ = oracle.expectations(wl)
     up = np.linspace(-1.0, 1.5, wl.B)
     g_ref = oracle.grad_adjoint(wl, up)
-    opts = {"engine": engine} if tile is None else {"tile_qubits": tile, "engine": engine}
+    opts = {"launch": "persistent"} if engine == "persistent" else {"engine": engine}
+    if tile is not None:
+        opts["tile_qubits"] = tile
     b = qv.Batch(ctx_for(qv, **opts), wl, prec)
     e, tv = b.expectations()
     s = obs_scale(wl)
@@ -306,3 +310,43 @@ def test_contig_qubits(qv, prec, contig):
     check(tv, tv_ref, prec, 1.0, "terms")
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
     check(g, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")
+
+
+def test_autotune_search_and_cache(qv, tmp_path, monkeypatch):
+    """The autotuner times its candidates on the device, keeps the fastest, stores it, and a second batch
+    of the same shape reuses the stored choice; results stay at parity either way."""
+    monkeypatch.setenv("QV_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    say("autotune")
+    wl = W.qcl(n=16, layers=2, samples=6, seed_index=46)
+    e_ref, _, _, _ = oracle.expectations(wl)
+    b = qv.Batch(ctx_for(qv, autotune="search"), wl, 0)
+    e, _ = b.expectations()
+    check(e, e_ref, 0, 1.0, "energies (search)")
+    st = b.stats()
+    assert 11 <= st["tile_qubits"] <= 13 and 3 <= st["contig_qubits"] <= 4
+    lines = (tmp_path / "tune.txt").read_text().split("\n")
+    assert len([x for x in lines if x.strip()]) == 1
+    b2 = qv.Batch(ctx_for(qv, autotune="cached"), wl, 0)
+    e2, _ = b2.expectations()
+    assert np.array_equal(e, e2)
+    st2 = b2.stats()
+    assert (st2["tile_qubits"], st2["contig_qubits"]) == (st["tile_qubits"], st["contig_qubits"])
+
+
+@pytest.mark.parametrize("layers", [2, 8])
+def test_persistent_matches_levels_bitwise(qv, layers):
+    """One persistent launch per sweep (work queue with per-circuit waits) gives bit-identical energies and
+    gradients to one launch per level, at full size (20 qubits, 64 samples)."""
+    say(f"persistent vs levels L={layers}")
+    wl = W.config3(layers)
+    up = np.linspace(-0.02, 0.03, wl.B)
+    out = []
+    for launch in ["levels", "persistent"]:
+        b = qv.Batch(ctx_for(qv, launch=launch, tile_qubits=13), wl, 0)
+        e, _ = b.expectations(want_terms=False)
+        g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+        b.stats()
+        out.append((e, g))
+        b.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])

@@ -70,11 +70,11 @@ def test_small_circuits_are_one_pass():
 
 
 def test_trainable_cap_per_pass():
-    """A pass holds at most 512 trainable gates (their adjoint partial sums live in LDS)."""
+    """A pass holds at most 256 trainable gates (their adjoint partial sums live in LDS)."""
     g = [W.gate(W.RY, i % 6, -1, i) for i in range(1300)]
     arr = np.array(g, W.GATE_DTYPE)
     passes = qvpu.plan_circuit(6, arr, 13, qvpu.QV_C64, 0)
-    assert [p["n_trainable"] for p in passes] == [512, 512, 276]
+    assert [p["n_trainable"] for p in passes] == [256] * 5 + [20]
 
 
 def test_plan_rejects_bad_input():
