@@ -742,7 +742,7 @@ static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans 
     pa.head = es.d_p_head.as<unsigned long long>();
     pa.done = es.d_p_done.as<unsigned long long>();
     pa.error = es.d_p_error.as<int32_t>();
-    pa.spin_limit = (int64_t)1 << 25;
+    pa.spin_limit = (int64_t)1 << 21;  // ~0.1 s of 128-clock sleeps
     int64_t bytes = 0;
     for (const Level &lv : lvs) bytes += lv.bytes;
     return logged(log, s, dir == 0 ? QV_K_RTILE_PERSIST : QV_K_RTILE_ADJ_PERSIST, -1, bytes,
