@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
     ap.add_argument("--launch", default="levels", choices=["levels", "persistent"])
+    ap.add_argument("--fusion", default="off", help='fused 4-qubit MFMA blocks: "off", "on" or a minimum run length')
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--levels", action="store_true", help="print per-launch times of one step")
@@ -121,7 +122,8 @@ def main():
     torch.cuda.set_device(dev)
     wl = W.config3(args.layers)
     stream = torch.cuda.current_stream(dev)
-    opts = {"graph": False, "launch_events": True, "engine": args.engine, "launch": args.launch}
+    opts = {"graph": False, "launch_events": True, "engine": args.engine, "launch": args.launch,
+            "fusion": args.fusion}
     if args.tile_qubits:
         opts["tile_qubits"] = args.tile_qubits
     if args.contig:
@@ -244,7 +246,8 @@ def main():
                    "qubits": 20, "layers": args.layers, "samples": 64, "params": wl.n_grad(),
                    "precision": "c64", "engine": args.engine, "tile_qubits": tuned["tile_qubits"],
                    "contig_qubits": tuned["contig_qubits"], "passes": tuned["passes_per_circuit_max"],
-                   "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch},
+                   "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch,
+                   "fusion": args.fusion},
         "roofline": roofline,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1)}

@@ -104,7 +104,8 @@ typedef enum {
     QV_K_RTILE_ADJ = 11,    /* register-tiled LDS pass, adjoint reverse sweep */
     QV_K_MATRICES = 12,     /* 2x2 matrices of every gate at the current parameters */
     QV_K_RTILE_PERSIST = 13,     /* all forward register-tiled passes in one persistent launch */
-    QV_K_RTILE_ADJ_PERSIST = 14  /* all adjoint register-tiled passes in one persistent launch */
+    QV_K_RTILE_ADJ_PERSIST = 14, /* all adjoint register-tiled passes in one persistent launch */
+    QV_K_FUSE = 15               /* fused 4-qubit block matrices (products of their gates) */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -131,6 +132,9 @@ typedef struct qv_batch_s *qv_batch;
  *   "launch"         : "levels" (one launch per pass level, default) or "persistent" (all levels of a
  *                      sweep in one launch: resident workgroups take tiles from a queue in level order and
  *                      wait, with a bounded spin, until their circuit's earlier passes are complete);
+ *   "fusion"         : "off" (default), "on" (runs of >= 6 gates) or a minimum run length: within a
+ *                      register segment, consecutive gates acting only on its 4 register qubits are
+ *                      multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);
  *   "autotune"       : "off", "cached" (default: reuse a choice stored by an earlier search) or
  *                      "search" (on the first forward call, time one forward pass for each candidate tile
  *                      size and contiguous-run length and keep the fastest; stored in the text file named
@@ -223,16 +227,19 @@ typedef struct {
     int32_t n_segments;   /* register segments (0: gates run one at a time in LDS or from HBM) */
     int32_t first_gate;   /* circuit index of the pass's first gate in execution order */
     int32_t contiguous_low; /* qubits 0..contiguous_low-1 are all local (length of contiguous runs) */
+    int32_t n_fused;      /* fused blocks among the pass's gates */
+    int32_t pad;
 } qv_pass_info;
 
 /* Plans one circuit without a device, as qv_batch_create would for a batch with the given engine
- * (0 "tiled", 1 "lds", 2 "stride") and tile size (0: the default): each pass is one read and one write
+ * (0 "tiled", 1 "lds", 2 "stride"), tile size (0: the default) and fusion minimum run length (0: no
+ * fused blocks; only the "tiled" engine fuses): each pass is one read and one write
  * of the state. Writes the pass count to *n_passes and the first max_passes passes to out; when order
  * is not NULL it receives the n_gates gate indices in execution order (passes in turn, each pass's
  * gates in the order the kernel applies them). Host only; for inspecting and testing the planner. */
 qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gates, int32_t tile_qubits,
-                          qv_precision precision, int32_t engine, int32_t max_passes, qv_pass_info *out,
-                          int32_t *n_passes, int32_t *order);
+                          qv_precision precision, int32_t engine, int32_t fuse_min, int32_t max_passes,
+                          qv_pass_info *out, int32_t *n_passes, int32_t *order);
 
 /* Library version string. */
 const char *qv_version(void);

@@ -69,8 +69,14 @@ struct DevCirc {
     double shift;         // the move (+pi/2 or -pi/2)
     int32_t base_circ;    // the batch circuit this entry evaluates (variants point at their base)
     int32_t pad;
-    int64_t op_base;      // first op of the circuit's plan; matrix of op o is mats[gate_off + o - op_base]
+    int64_t op_base;      // first op of the circuit's plan; matrix of op o is mats[mat_off + o - op_base]
+    int64_t mat_off;      // this circuit's range of the per-op matrix table
+    int64_t fused_off;    // this circuit's first fused block in the fused-matrix table
+    int64_t fused_ops;    // offset of its plan's fused-block marker list
 };
+
+constexpr int kFusedKind = 100;      // op kind of a fused-block marker (its gates follow it)
+constexpr int kFusedFloats = 1024;   // one fused 4-qubit block: the 32x32 real form of a 16x16 complex matrix
 
 // One (circuit, pass) of a level launch; blocks [first_block, next segment's first_block) run it.
 struct Seg {
@@ -130,6 +136,7 @@ struct LevelArgs {
     const qv_gate *gates;
     const double *theta;
     const void *mats;     // per circuit and plan op: its 2x2 matrix (8 reals, R precision), built from theta
+    const float *fmats;   // fused blocks: kFusedFloats per block, in the order the MFMA A operand reads them
     void *psi;
     void *lam;
     double *partials;
@@ -159,7 +166,7 @@ struct PersistArgs {
 // Gate matrices of a batch: for every gate record, its 2x2 complex matrix at the current parameters.
 struct MatArgs {
     const qv_gate *gates;
-    const int32_t *gate_circ;   // circuit of each gate record
+    const int32_t *gate_circ;   // circuit of each matrix-table entry
     const DevOp *ops;           // plans: entry gate_off + j of the table is the circuit's op op_base + j
     const DevCirc *circs;
     const double *theta;
@@ -237,6 +244,21 @@ int launch_grad_reduce(const GradReduceArgs &a, void *stream);
 int launch_shift_combine(const ShiftCombineArgs &a, void *stream);
 int launch_fill(double *p, int64_t n, double v, void *stream);
 int launch_matrices(const MatArgs &a, int precision, void *stream);
+
+// Fused 4-qubit blocks: for every circuit and block, the product of the block's gates (16x16 complex),
+// written as the 32x32 real matrix [[Re, -Im], [Im, Re]] interleaved per amplitude, in MFMA A order.
+struct FuseArgs {
+    const DevOp *ops;
+    const DevCirc *circs;
+    const int64_t *first_block;  // [n_circ + 1]: blocks of circuit c are [first_block[c], first_block[c+1])
+    int32_t n_circ;
+    int32_t pad;
+    const int64_t *fused_ops;    // global op index of each plan's markers
+    const void *mats;            // 2x2 matrices (complex64)
+    float *fmats;
+    int64_t n_blocks;
+};
+int launch_fuse(const FuseArgs &a, void *stream);
 int prepare_kernels();  // raises the dynamic-LDS limits; call once per device
 
 }  // namespace qv

@@ -179,8 +179,8 @@ __device__ __forceinline__ int find_prefix(const int64_t *pre, int n, int64_t bl
 
 // Matrix of op for circuit C: from the batch's matrix table, or built on the spot for the one gate whose
 // angle a parameter-shift variant moves.
-// The table is laid out in plan order (entry gate_off + o - op_base for the plan's op o), so an op's matrix
-// can be fetched without first reading the op record.
+// The table is laid out in plan order (entry mat_off + o - op_base for the plan's op o, fused-block markers
+// included), so an op's matrix can be fetched without first reading the op record.
 template <typename R>
 __device__ __forceinline__ M2<R> op_matrix(const LevelArgs &a, const DevCirc &C, const DevOp &op, int64_t oi)
 {
@@ -191,7 +191,7 @@ __device__ __forceinline__ M2<R> op_matrix(const LevelArgs &a, const DevCirc &C,
         gate_matrix(g.kind, ang, md);
         return narrow<R>(md);
     }
-    return reinterpret_cast<const M2<R> *>(a.mats)[C.gate_off + (oi - C.op_base)];
+    return reinterpret_cast<const M2<R> *>(a.mats)[C.mat_off + (oi - C.op_base)];
 }
 
 template <typename R>
@@ -507,6 +507,42 @@ __device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, 
     WITH_K(RB, op.k0, r_gen<K>(v, m));
 }
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// A fused 4-qubit block on the 16 register amplitudes of every lane, as one wave-wide real GEMM on MFMA:
+// Y (32 x 64) = A (32 x 32) X (32 x 64), where column l of X is lane l's amplitudes as 32 reals
+// (re, im interleaved) and A is the block's [[Re, -Im], [Im, Re]] form. v_mfma_f32_32x32x2_f32 takes B
+// row k from lane half k, so permlane32 swaps pair rows 2s and 2s+1 across the lane halves: one swap
+// yields the B operand of both 32-column halves. Its result holds, per lane half, rows 8i+4h+r of a
+// column; swapping the two halves' accumulators gives every lane its own column back.
+__device__ __forceinline__ void fused_mfma(Cx<float> (&v)[16], const float *__restrict__ A, int lane)
+{
+    float x[32];
+#pragma unroll
+    for (int j = 0; j < 16; j++) { x[2 * j] = v[j].re; x[2 * j + 1] = v[j].im; }
+    v16f acc0, acc1;
+#pragma unroll
+    for (int q = 0; q < 16; q++) { acc0[q] = 0.f; acc1[q] = 0.f; }
+#pragma unroll
+    for (int s = 0; s < 16; s++) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[2 * s]), __float_as_uint(x[2 * s + 1]),
+                                                         false, false);
+        const float a = A[s * 64 + lane];
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, __uint_as_float(sw[0]), acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, __uint_as_float(sw[1]), acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc0[q]), __float_as_uint(acc1[q]), false,
+                                                         false);
+        const int rlo = 8 * (q / 4) + (q % 4);
+        x[rlo] = __uint_as_float(sw[0]);
+        x[rlo + 4] = __uint_as_float(sw[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++) { v[j].re = x[2 * j]; v[j].im = x[2 * j + 1]; }
+}
+
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, const Seg &sg)
 {
@@ -580,7 +616,7 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             if (ADJ) lv[j] = sl[addr];
         }
         // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
-        const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.gate_off - C.op_base);
+        const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.mat_off - C.op_base);
         int64_t oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
         DevOp nop = a.ops[oi];
         M2<R> nmat = mtab[oi];
@@ -594,6 +630,27 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                 nmat = mtab[oi];
             }
             const int kind = op.kind;
+            if (kind == kFusedKind) {
+                // A fused block: forward applies its product on MFMA and skips its gates; the adjoint (which
+                // needs the state at every trainable gate) and complex128 run the gates one by one.
+                if constexpr (!ADJ && RB == 4 && sizeof(R) == 4) {
+                    const int m = op.pad;
+                    bool shifted = false;
+                    if (C.shift_gate >= 0)
+                        for (int j = 1; j <= m; j++) shifted |= a.ops[cur + j].gate == C.shift_gate;
+                    if (!shifted) {
+                        const int f = op.p0 | (op.p1 << 8);
+                        fused_mfma(av, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
+                        k0 += m;
+                        if (k0 + 1 < S.n_ops) {
+                            oi = cur + m + 1;
+                            nop = a.ops[oi];
+                            nmat = mtab[oi];
+                        }
+                    }
+                }
+                continue;
+            }
             if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
             if (ADJ) {
                 if (op.flags & OP_TRAIN) {
@@ -799,9 +856,14 @@ __global__ __launch_bounds__(kBlock) void k_matrices(MatArgs a)
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n_gates) return;
     const DevCirc C = a.circs[a.gate_circ[i]];
-    const DevOp op = a.ops[C.op_base + (i - C.gate_off)];
-    const qv_gate g = a.gates[C.gate_off + op.gate];
+    const DevOp op = a.ops[C.op_base + (i - C.mat_off)];
     M2d md;
+    if (op.kind == kFusedKind) {
+        gate_matrix(-1, 0.0, md);
+        reinterpret_cast<M2<R> *>(a.mats)[i] = narrow<R>(md);
+        return;
+    }
+    const qv_gate g = a.gates[C.gate_off + op.gate];
     if (g.kind == QV_CNOT || g.kind == QV_CZ) {
         gate_matrix(-1, 0.0, md);
     } else {
@@ -809,6 +871,60 @@ __global__ __launch_bounds__(kBlock) void k_matrices(MatArgs a)
         gate_matrix(g.kind, ang, md);
     }
     reinterpret_cast<M2<R> *>(a.mats)[i] = narrow<R>(md);
+}
+
+// Fused-block matrices: one workgroup per (circuit, block) multiplies the block's gates into a 16x16
+// complex matrix in LDS (thread (r, c) owns entry r, c; each gate acts on the rows of its register bits),
+// then writes the 32x32 real form in the order fused_mfma reads it: entry s*64 + l is A[l % 32][2s + l / 32].
+__global__ __launch_bounds__(256) void k_fuse(FuseArgs a)
+{
+    __shared__ float ur[256], ui[256];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const int64_t f = blk - a.first_block[c];
+    const int64_t mk = a.fused_ops[C.fused_ops + f];
+    const DevOp marker = a.ops[mk];
+    const int m = marker.pad;
+    const int r = threadIdx.x >> 4, col = threadIdx.x & 15;
+    ur[threadIdx.x] = r == col ? 1.f : 0.f;
+    ui[threadIdx.x] = 0.f;
+    __syncthreads();
+    const M2<float> *mt = reinterpret_cast<const M2<float> *>(a.mats) + (C.mat_off - C.op_base);
+    for (int j = 1; j <= m; j++) {
+        const DevOp op = a.ops[mk + j];
+        float nr, ni;
+        if (op.kind == QV_CNOT) {
+            const int src = ((r >> op.k0) & 1) ? (r ^ (1 << op.k1)) : r;
+            nr = ur[src * 16 + col];
+            ni = ui[src * 16 + col];
+        } else if (op.kind == QV_CZ) {
+            const float sg = (((r >> op.k0) & 1) && ((r >> op.k1) & 1)) ? -1.f : 1.f;
+            nr = sg * ur[threadIdx.x];
+            ni = sg * ui[threadIdx.x];
+        } else {
+            const M2<float> g = mt[mk + j];
+            const int b = (r >> op.k0) & 1;
+            const int r0 = r & ~(1 << op.k0), r1 = r | (1 << op.k0);
+            const float g0r = g.re[2 * b], g0i = g.im[2 * b], g1r = g.re[2 * b + 1], g1i = g.im[2 * b + 1];
+            const float x0r = ur[r0 * 16 + col], x0i = ui[r0 * 16 + col];
+            const float x1r = ur[r1 * 16 + col], x1i = ui[r1 * 16 + col];
+            nr = g0r * x0r - g0i * x0i + g1r * x1r - g1i * x1i;
+            ni = g0r * x0i + g0i * x0r + g1r * x1i + g1i * x1r;
+        }
+        __syncthreads();
+        ur[threadIdx.x] = nr;
+        ui[threadIdx.x] = ni;
+        __syncthreads();
+    }
+    float *out = a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats;
+    for (int e = threadIdx.x; e < kFusedFloats; e += 256) {
+        const int s = e >> 6, l = e & 63;
+        const int i = l & 31, k = 2 * s + (l >> 5);
+        const int rr = i >> 1, pr = i & 1, cc = k >> 1, pc = k & 1;
+        const float re = ur[rr * 16 + cc], im = ui[rr * 16 + cc];
+        out[e] = pr == pc ? re : (pr == 0 ? -im : im);
+    }
 }
 
 // psi_b = |0...0> for every circuit; blocks cover 4096 amplitudes each.
@@ -1221,6 +1337,14 @@ int launch_matrices(const MatArgs &a, int precision, void *stream)
     const dim3 grid((unsigned)((a.n_gates + kBlock - 1) / kBlock));
     if (precision == QV_C64) hipLaunchKernelGGL((k_matrices<float>), grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL((k_matrices<double>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_fuse(const FuseArgs &a, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_fuse, dim3((unsigned)a.n_blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

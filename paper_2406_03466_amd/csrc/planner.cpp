@@ -105,7 +105,7 @@ void segment_pass(PlanPass &pp, int reg_bits)
     number_train_slots(pp);
 }
 
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits)
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, int fuse_min)
 {
     Plan pl;
     const int n = in.n;
@@ -193,7 +193,65 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits)
         segment_pass(pp, reg_bits);
         pl.passes.push_back(pp);
     }
+    if (fuse_min > 0) fuse_segments(pl, fuse_min);
     return pl;
+}
+
+void fuse_segments(Plan &pl, int fuse_min)
+{
+    int next = 0;
+    for (PlanPass &pp : pl.passes) {
+        if (pp.segs.empty()) continue;
+        std::vector<PlanOp> out;
+        std::vector<PlanSeg> segs = pp.segs;
+        for (PlanSeg &sg : segs) {
+            uint32_t R = 0;
+            int pos[64];
+            for (int i = 0; i < 64; i++) pos[i] = -1;
+            for (size_t i = 0; i < pp.lq.size(); i++) pos[pp.lq[i]] = (int)i;
+            for (int p : sg.rpos) R |= 1u << p;
+            auto local = [&](const PlanOp &op) {
+                if (!(R >> pos[op.q0] & 1u)) return false;
+                if (two_qubit(op.kind) && !(R >> pos[op.q1] & 1u)) return false;
+                return true;
+            };
+            const int b = sg.op_begin, e = sg.op_begin + sg.n_ops;
+            const int new_begin = (int)out.size();
+            for (int i = b; i < e;) {
+                int j = i;
+                while (j < e && local(pp.ops[j])) j++;
+                if (j - i >= fuse_min && next < 65535) {   // block numbers are 16-bit in the device op
+                    PlanOp m;
+                    m.gate = 0;
+                    m.kind = kFusedKind;
+                    m.q0 = pp.ops[i].q0;
+                    m.q1 = -1;
+                    m.train_slot = -1;
+                    m.fused_count = j - i;
+                    m.fused_index = next++;
+                    out.push_back(m);
+                    for (int k = i; k < j; k++) out.push_back(pp.ops[k]);
+                    i = j;
+                } else {
+                    out.push_back(pp.ops[i]);
+                    i++;
+                }
+            }
+            sg.op_begin = new_begin;
+            sg.n_ops = (int)out.size() - new_begin;
+        }
+        pp.ops = out;
+        pp.segs = segs;
+    }
+}
+
+int fused_blocks(const Plan &pl)
+{
+    int n = 0;
+    for (const PlanPass &pp : pl.passes)
+        for (const PlanOp &op : pp.ops)
+            if (op.kind == kFusedKind) n++;
+    return n;
 }
 
 Plan plan_stride(const PlanInput &in)
@@ -254,6 +312,17 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
             o.train_slot = op.train_slot;
             o.k0 = -1;
             o.k1 = -1;
+            if (op.kind == kFusedKind) {
+                // marker: block number in p0 | p1 << 8, block size in pad
+                o.kind = (uint8_t)kFusedKind;
+                o.p0 = (uint8_t)(op.fused_index & 0xFF);
+                o.p1 = (uint8_t)((op.fused_index >> 8) & 0xFF);
+                o.pad = (int16_t)op.fused_count;
+                o.flags = 0;
+                o.train_slot = -1;
+                ops.push_back(o);
+                continue;
+            }
             if (seg_of[i] >= 0) {
                 const PlanSeg &sg = pp.segs[seg_of[i]];
                 for (size_t k = 0; k < sg.rpos.size(); k++) {

@@ -14,11 +14,16 @@ struct PlanInput {
     std::vector<bool> trainable;
 };
 
+// A fused-block marker (kind kFusedKind, declared with the device op layout) heads a fused block: the
+// next fused_count ops of the segment are its gates.
+
 struct PlanOp {
-    int gate;        // index in the circuit
-    int kind;
+    int gate;        // index in the circuit (fused-block markers: 0, unused)
+    int kind;        // qv_gate_kind, or kFusedKind for a fused-block marker
     int q0, q1;      // qubits (global)
     int train_slot;  // position among the pass's trainable gates, -1 if fixed
+    int fused_count = 0;   // markers: number of gates in the block
+    int fused_index = -1;  // markers: block number within the plan
 };
 
 // A register segment of a pass (see DevSeg in engine.h): positions are local.
@@ -50,10 +55,18 @@ constexpr int kMaxTrainPerPass = 256;
 // LDS tile plan with tiles of at most `tile_qubits` qubits, the lowest `lowc` qubits always local.
 // reg_bits > 0 splits every pass of at least reg_bits qubits into register segments of 2^reg_bits
 // amplitudes per thread.
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0);
+// fuse_min > 0 turns every run of at least fuse_min consecutive gates of a segment that act on register
+// qubits only into a fused block (a marker op followed by the run).
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0, int fuse_min = 0);
 
 // Splits one pass into register segments (reorders its ops; dependencies are kept).
 void segment_pass(PlanPass &pp, int reg_bits);
+
+// Inserts fused-block markers into the segments of a plan's passes; numbers the blocks plan-wide.
+void fuse_segments(Plan &pl, int fuse_min);
+
+// Number of fused blocks of a plan.
+int fused_blocks(const Plan &pl);
 
 // One stride pass per gate.
 Plan plan_stride(const PlanInput &in);

@@ -118,6 +118,7 @@ struct qv_ctx_s {
     int contig = 0;             // qubits 0..contig-1 always local (0: 4 for complex64, 3 for complex128)
     int autotune = 1;           // 0 off, 1 cached (use a stored choice), 2 search (time candidates once)
     int persistent = 0;         // 1: one persistent work-queue launch per direction instead of one per level
+    int fuse_min = 0;           // >0: fuse runs of at least this many register-local gates into MFMA blocks
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
@@ -262,8 +263,11 @@ struct ExecSet {
 
 // Device form of a batch's plans (shared by all its circuits and parameter-shift variants).
 struct DevPlans {
-    DBuf passes, ops, rsegs;
+    DBuf passes, ops, rsegs, fused_ops;
     std::vector<int> pass_base;
+    std::vector<int64_t> op_count;      // ops per plan (fused-block markers included)
+    std::vector<int64_t> fused_base;    // per plan: first entry in fused_ops
+    std::vector<int64_t> fused_count;   // per plan: fused blocks
 };
 
 struct qv_batch_s {
@@ -300,7 +304,9 @@ struct qv_batch_s {
     bool ps_ready = false;
 
     DBuf d_gates, d_theta, d_psi, d_lam, d_energies, d_tv, d_norms, d_grad, d_upstream;
-    DBuf d_gate_circ, d_mats;   // circuit of each gate record; 2x2 matrix of each gate record
+    DBuf d_gate_circ, d_mats;   // circuit of each matrix-table entry; 2x2 matrix of each circuit's plan ops
+    DBuf d_fmats, d_fuse_fb;    // fused-block matrices; per-circuit block prefix for k_fuse
+    int64_t n_mats = 0, n_fused = 0;
     DBuf d_ps_psi, d_ps_energies, d_ps_tv, d_occ_begin, d_occ_plus, d_occ_minus, d_occ_circ;
 
     bool theta_set = false;
@@ -685,6 +691,7 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
     a.gates = bt.d_gates.as<qv_gate>();
     a.theta = bt.d_theta.as<double>();
     a.mats = bt.d_mats.p;
+    a.fmats = bt.d_fmats.as<float>();
     a.psi = psi;
     a.lam = lam;
     a.partials = es.d_adj_partials.as<double>();
@@ -717,8 +724,20 @@ static int enqueue_matrices(const qv_batch_s &bt, hipStream_t s, LaunchLog *log)
     ma.circs = bt.main.d_circs.as<DevCirc>();
     ma.theta = bt.d_theta.as<double>();
     ma.mats = bt.d_mats.p;
-    ma.n_gates = (int64_t)bt.gates.size();
-    return logged(log, s, QV_K_MATRICES, -1, 0, [&] { return launch_matrices(ma, bt.prec, s); });
+    ma.n_gates = bt.n_mats;
+    int e = logged(log, s, QV_K_MATRICES, -1, 0, [&] { return launch_matrices(ma, bt.prec, s); });
+    if (e || bt.n_fused == 0) return e;
+    FuseArgs fa;
+    fa.ops = bt.dp->ops.as<DevOp>();
+    fa.circs = bt.main.d_circs.as<DevCirc>();
+    fa.first_block = bt.d_fuse_fb.as<int64_t>();
+    fa.n_circ = bt.B;
+    fa.pad = 0;
+    fa.fused_ops = bt.dp->fused_ops.as<int64_t>();
+    fa.mats = bt.d_mats.p;
+    fa.fmats = bt.d_fmats.as<float>();
+    fa.n_blocks = bt.n_fused;
+    return logged(log, s, QV_K_FUSE, -1, 0, [&] { return launch_fuse(fa, s); });
 }
 
 // One persistent launch for all levels of a direction (see k_rtile_*_persist).
@@ -877,6 +896,14 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             else if (v == "cached") c->autotune = 1;
             else if (v == "search") c->autotune = 2;
             else return fail(QV_E_INVALID, "autotune must be \"off\", \"cached\" or \"search\"");
+        } else if (k == "fusion") {
+            if (v == "off" || v == "0") c->fuse_min = 0;
+            else if (v == "on") c->fuse_min = 6;
+            else {
+                const int fm = atoi(v.c_str());
+                if (fm < 1 || fm > 64) return fail(QV_E_INVALID, "fusion must be \"off\", \"on\" or a minimum run length 1..64");
+                c->fuse_min = fm;
+            }
         } else if (k == "fusion_k" || k == "precision" || k == "deterministic") {
             /* accepted for compatibility; the current planner ignores them */
         } else {
@@ -994,7 +1021,8 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
         }
         const int lowc = bt->contig;
         const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
-        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb));
+        const int fm = (ctx->engine == 0) ? ctx->fuse_min : 0;
+        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb, fm));
     }
     // device plan arrays
     auto dp = std::make_unique<DevPlans>();
@@ -1002,11 +1030,21 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
     std::vector<DevOp> ops;
     std::vector<DevSeg> rsegs;
     std::vector<int64_t> plan_op_base;
+    std::vector<int64_t> fused_ops;
     for (const Plan &pl : bt->plans) {
         dp->pass_base.push_back((int)passes.size());
         plan_op_base.push_back((int64_t)ops.size());
+        const size_t before = ops.size();
         lower_plan(pl, passes, ops, rsegs);
+        dp->op_count.push_back((int64_t)(ops.size() - before));
+        dp->fused_base.push_back((int64_t)fused_ops.size());
+        std::vector<int64_t> mk(fused_blocks(pl), -1);
+        for (size_t i = before; i < ops.size(); i++)
+            if (ops[i].kind == kFusedKind) mk[ops[i].p0 | (ops[i].p1 << 8)] = (int64_t)i;
+        for (int64_t v : mk) fused_ops.push_back(v);
+        dp->fused_count.push_back((int64_t)mk.size());
     }
+    HIPRET(dp->fused_ops.upload(fused_ops));
     HIPRET(dp->passes.upload(passes));
     HIPRET(dp->ops.upload(ops));
     HIPRET(dp->rsegs.upload(rsegs));
@@ -1028,10 +1066,35 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
         c.base_circ = b;
         c.pad = 0;
         c.op_base = plan_op_base[bt->plan_of[b]];
+        c.mat_off = 0;
+        c.fused_off = 0;
+        c.fused_ops = dp->fused_base[bt->plan_of[b]];
         off += (int64_t)1 << nq[b];
         pb += np[b];
     }
     es.state_amps = off;
+    // matrix table: one entry per circuit and plan op; fused blocks: one per circuit and block
+    {
+        int64_t mo = 0, fo = 0;
+        std::vector<int32_t> mat_circ;
+        std::vector<int64_t> ffb(B + 1, 0);
+        for (int b = 0; b < B; b++) {
+            const int pl = bt->plan_of[b];
+            es.circs[b].mat_off = mo;
+            es.circs[b].fused_off = fo;
+            for (int64_t k = 0; k < dp->op_count[pl]; k++) mat_circ.push_back(b);
+            mo += dp->op_count[pl];
+            const int64_t nf = prec == QV_C64 ? dp->fused_count[pl] : 0;
+            fo += nf;
+            ffb[b + 1] = ffb[b] + nf;
+        }
+        bt->n_mats = mo;
+        bt->n_fused = fo;
+        HIPRET(bt->d_gate_circ.upload(mat_circ));
+        HIPRET(bt->d_mats.alloc((size_t)std::max<int64_t>(1, mo) * 8 * (bt->amp_bytes / 2)));
+        HIPRET(bt->d_fmats.alloc(sizeof(float) * (size_t)std::max<int64_t>(1, fo) * kFusedFloats));
+        HIPRET(bt->d_fuse_fb.upload(ffb));
+    }
     build_levels(es, bt->plans, dp->pass_base, ctx->n_vqpu, bt->amp_bytes);
     ObsView ov{bt->toff.data(), bt->xm.data(), bt->zm.data(), bt->cf.data(), bt->obs_shared};
     std::vector<int> obs_of(B);
@@ -1097,13 +1160,6 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     HIPCHK(configure(bt.get(), ctx->tile_qubits, ctx->contig));
 
     HIPCHK(bt->d_gates.upload(bt->gates));
-    {
-        std::vector<int32_t> gc(bt->gates.size());
-        for (int b = 0; b < B; b++)
-            for (int64_t k = goff[b]; k < goff[b + 1]; k++) gc[k] = b;
-        HIPCHK(bt->d_gate_circ.upload(gc));
-        HIPCHK(bt->d_mats.alloc((size_t)std::max<int64_t>(1, (int64_t)bt->gates.size()) * 8 * (bt->amp_bytes / 2)));
-    }
     HIPCHK(bt->d_theta.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, bt->n_theta)));
     HIPCHK(bt->d_psi.alloc((size_t)bt->main.state_amps * bt->amp_bytes));
     HIPCHK(bt->d_energies.alloc(sizeof(double) * B));
@@ -1609,8 +1665,8 @@ qv_status qv_batch_launch_log(qv_batch bt, qv_launch_rec *out, int32_t max_recor
 }
 
 qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gates, int32_t tile_qubits,
-                          qv_precision precision, int32_t engine, int32_t max_passes, qv_pass_info *out,
-                          int32_t *n_passes, int32_t *order)
+                          qv_precision precision, int32_t engine, int32_t fuse_min, int32_t max_passes,
+                          qv_pass_info *out, int32_t *n_passes, int32_t *order)
 {
     if (!n_passes) return fail(QV_E_INVALID, "n_passes must not be NULL");
     if (max_passes > 0 && !out) return fail(QV_E_INVALID, "out must not be NULL when max_passes > 0");
@@ -1636,23 +1692,29 @@ qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gate
     }
     const int lowc = precision == QV_C64 ? 4 : 3;
     const int rb = engine == 0 ? (precision == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
-    const Plan pl = engine == 2 ? plan_stride(pin) : plan_tiled(pin, t, lowc, rb);
+    const Plan pl = engine == 2 ? plan_stride(pin) : plan_tiled(pin, t, lowc, rb, engine == 0 ? fuse_min : 0);
     *n_passes = (int32_t)pl.passes.size();
     for (int32_t i = 0; i < *n_passes && i < max_passes; i++) {
         const PlanPass &pp = pl.passes[i];
         qv_pass_info &o = out[i];
         o.local_mask = pp.local_mask;
         o.qubits = pp.t;
-        o.n_ops = (int32_t)pp.ops.size();
+        int32_t nf = 0;
+        for (const PlanOp &op : pp.ops) nf += op.kind == kFusedKind ? 1 : 0;
+        o.n_ops = (int32_t)pp.ops.size() - nf;
+        o.n_fused = nf;
         o.n_trainable = pp.n_train;
         o.n_segments = (int32_t)pp.segs.size();
-        o.first_gate = pp.ops.empty() ? -1 : pp.ops.front().gate;
+        o.first_gate = -1;
+        for (const PlanOp &op : pp.ops)
+            if (op.kind != kFusedKind) { o.first_gate = op.gate; break; }
         o.contiguous_low = pp.lowc;
     }
     if (order) {
         int64_t k = 0;
         for (const PlanPass &pp : pl.passes)
-            for (const PlanOp &op : pp.ops) order[k++] = op.gate;
+            for (const PlanOp &op : pp.ops)
+                if (op.kind != kFusedKind) order[k++] = op.gate;
     }
     return ok();
 }

@@ -44,12 +44,12 @@ class qv_launch_rec(ctypes.Structure):
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
                 "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices", "rtile_persist",
-                "rtile_adj_persist"]
+                "rtile_adj_persist", "fuse"]
 
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),
                 ("n_trainable", ctypes.c_int32), ("n_segments", ctypes.c_int32), ("first_gate", ctypes.c_int32),
-                ("contiguous_low", ctypes.c_int32)]
+                ("contiguous_low", ctypes.c_int32), ("n_fused", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -80,8 +80,8 @@ def load():
     lib.qv_batch_stats.argtypes = [P, ctypes.POINTER(qv_stats)]
     lib.qv_batch_destroy.argtypes = [P]
     lib.qv_batch_launch_log.argtypes = [P, ctypes.POINTER(qv_launch_rec), i32, ctypes.POINTER(i32)]
-    lib.qv_plan_circuit.argtypes = [i32, ctypes.c_int64, P, i32, i32, i32, i32, ctypes.POINTER(qv_pass_info),
-                                    ctypes.POINTER(i32), P]
+    lib.qv_plan_circuit.argtypes = [i32, ctypes.c_int64, P, i32, i32, i32, i32, i32,
+                                    ctypes.POINTER(qv_pass_info), ctypes.POINTER(i32), P]
     for f in ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
               "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_state",
               "qv_batch_stats", "qv_batch_destroy", "qv_batch_launch_log", "qv_plan_circuit"]:
@@ -138,7 +138,7 @@ class _Arrays:
 
 
 def plan_circuit(n: int, gates, tile_qubits: int = 0, precision: int = QV_C64, engine: int = 0,
-                 with_order: bool = False):
+                 with_order: bool = False, fuse_min: int = 0):
     """qv_plan_circuit: the passes the planner makes for one circuit (host only, no device); with
     with_order, also the gate indices in execution order."""
     g = np.ascontiguousarray(gates).astype(W.GATE_DTYPE, copy=False)
@@ -148,12 +148,12 @@ def plan_circuit(n: int, gates, tile_qubits: int = 0, precision: int = QV_C64, e
     else:
         ng = len(g)
     cnt = ctypes.c_int32(0)
-    _check(load().qv_plan_circuit(int(n), ng, _ptr(g), int(tile_qubits), int(precision), int(engine), 0, None,
-                                  ctypes.byref(cnt), None))
+    _check(load().qv_plan_circuit(int(n), ng, _ptr(g), int(tile_qubits), int(precision), int(engine),
+                                  int(fuse_min), 0, None, ctypes.byref(cnt), None))
     arr = (qv_pass_info * max(1, cnt.value))()
     order = np.zeros(max(1, ng), np.int32)
-    _check(load().qv_plan_circuit(int(n), ng, _ptr(g), int(tile_qubits), int(precision), int(engine), cnt.value,
-                                  arr, ctypes.byref(cnt), _ptr(order)))
+    _check(load().qv_plan_circuit(int(n), ng, _ptr(g), int(tile_qubits), int(precision), int(engine),
+                                  int(fuse_min), cnt.value, arr, ctypes.byref(cnt), _ptr(order)))
     passes = [{k: getattr(arr[i], k) for k, _ in qv_pass_info._fields_} for i in range(cnt.value)]
     return (passes, order[:ng]) if with_order else passes
 

@@ -66,7 +66,8 @@ def obs_scale(wl):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"engine": "lds"},
-                                  {"engine": "lds", "tile_qubits": 7}, {"graph": False}])
+                                  {"engine": "lds", "tile_qubits": 7}, {"graph": False}, {"fusion": "on"},
+                                  {"fusion": 2, "tile_qubits": 7}])
 def test_c1_expectations(qv, prec, opts):
     say(f"c1 expectations prec={prec} opts={opts}")
     wl = W.config1()
@@ -82,7 +83,8 @@ def test_c1_expectations(qv, prec, opts):
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"engine": "lds"},
                                   {"engine": "lds", "tile_qubits": 7}, {"launch": "persistent"},
-                                  {"launch": "persistent", "tile_qubits": 6}])
+                                  {"launch": "persistent", "tile_qubits": 6}, {"fusion": 2},
+                                  {"fusion": 3, "launch": "persistent", "tile_qubits": 8}])
 def test_c1_gradients(qv, prec, opts):
     say(f"c1 gradients prec={prec} opts={opts}")
     wl = W.config1()
@@ -119,7 +121,7 @@ def test_c2_full(qv, prec):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("tile,engine", [(6, "tiled"), (9, "tiled"), (None, "tiled"), (8, "lds"), (None, "lds"),
-                                         (9, "persistent"), (None, "persistent")])
+                                         (9, "persistent"), (None, "persistent"), (None, "fused"), (8, "fused")])
 def test_uneven_batch(qv, prec, tile, engine):
     """Circuits of 2..16 qubits and 0..80 gates in one batch: per-circuit energies, terms, states and
     adjoint gradients (own parameters per circuit) with upstream weights."""
@@ -128,7 +130,8 @@ def test_uneven_batch(qv, prec, tile, engine):
     e_ref, tv_ref, _, _ = oracle.expectations(wl)
     up = np.linspace(-1.0, 1.5, wl.B)
     g_ref = oracle.grad_adjoint(wl, up)
-    opts = {"launch": "persistent"} if engine == "persistent" else {"engine": engine}
+    opts = ({"launch": "persistent"} if engine == "persistent" else
+            {"fusion": 2} if engine == "fused" else {"engine": engine})
     if tile is not None:
         opts["tile_qubits"] = tile
     b = qv.Batch(ctx_for(qv, **opts), wl, prec)
@@ -350,3 +353,20 @@ def test_persistent_matches_levels_bitwise(qv, layers):
         b.close()
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("layers", [2, 8])
+def test_qcl20_fused_blocks(qv, layers):
+    """Fused 4-qubit blocks on MFMA (forward passes) at full size: energies and adjoint gradients against the
+    oracle's stored values to the complex64 bound, and the plan really holds fused blocks."""
+    say(f"qcl20 fused L={layers}")
+    gold = _golden(f"qcl20_L{layers}")
+    wl = W.config3(layers)
+    b = qv.Batch(ctx_for(qv, fusion=4, tile_qubits=13, graph=False, launch_events=True), wl, 0)
+    e, _ = b.expectations(want_terms=False)
+    check(e, np.array(gold["energies"]), 0, 1.0, "energies")
+    assert any(r["kernel"] == "fuse" for r in b.launch_log())
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
+    check(g, np.array(gold["grad"]), 0, float(np.sum(np.abs(gold["upstream"]))), "grad")
+    passes = qv.plan_circuit(20, wl.circuit(0), 13, qv.QV_C64, 0, fuse_min=4)
+    assert sum(p["n_fused"] for p in passes) > 0

@@ -83,3 +83,19 @@ def test_plan_rejects_bad_input():
         qvpu.plan_circuit(4, arr, 13, qvpu.QV_C64, 0)
     with pytest.raises(qvpu.QvError):
         qvpu.plan_circuit(4, np.array([W.gate(W.H, 0)], W.GATE_DTYPE), 3, qvpu.QV_C64, 0)
+
+
+@pytest.mark.parametrize("fuse_min", [1, 2, 4, 6])
+def test_fused_plans_keep_every_gate(fuse_min):
+    """Fused-block markers do not change the schedule: every gate appears once, in a valid order, and the
+    blocks are counted per pass."""
+    wl = W.config3(8)
+    gates = wl.circuit(0)
+    passes, order = qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 0, with_order=True, fuse_min=fuse_min)
+    _check_plan(20, gates, passes, order)
+    nf = sum(p["n_fused"] for p in passes)
+    assert nf > 0
+    plain = qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 0)
+    assert [p["local_mask"] for p in plain] == [p["local_mask"] for p in passes]
+    # the stride engine never fuses
+    assert sum(p["n_fused"] for p in qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 2, fuse_min=fuse_min)) == 0
