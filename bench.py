@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak (256 CUs at 2.4 GHz)
+TILE_KERNELS = ("rtile", "rtile_adj", "rtile_persist", "rtile_adj_persist", "tile", "tile_adj")
 
 
 def kernel_source_hash() -> str:
@@ -54,14 +56,17 @@ def pmc_traffic(kernel: str, workload: str):
 def summarize_launches(recs):
     per = {}
     for r in recs:
-        k = per.setdefault(r["kernel"], {"launches": 0, "ms": 0.0, "bytes": 0})
+        k = per.setdefault(r["kernel"], {"launches": 0, "ms": 0.0, "bytes": 0, "flops": 0.0})
         k["launches"] += 1
         k["ms"] += r["ms"]
         k["bytes"] += r["bytes"]
+        k["flops"] += r.get("flops", 0.0)
     for k in per.values():
         k["avg_ms"] = k["ms"] / k["launches"]
         k["avg_bytes"] = k["bytes"] / k["launches"]
+        k["avg_flops"] = k["flops"] / k["launches"]
         k["gbs"] = (k["avg_bytes"] / 1e9) / (k["avg_ms"] / 1e3) if k["avg_ms"] > 0 else 0.0
+        k["tflops"] = (k["avg_flops"] / 1e12) / (k["avg_ms"] / 1e3) if k["avg_ms"] > 0 else 0.0
     return per
 
 
@@ -174,13 +179,23 @@ def main():
                   "rtile_persist": "k_rtile_fwd_persist<float,4,512>"}.get(dom, dom)
     workload_tag = f"qcl20_L{args.layers}"
     traffic = pmc_traffic(dom, workload_tag)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_sym,
-                "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
-                "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
+    if dom in TILE_KERNELS:
+        # register/LDS tile passes run tens of gates per HBM round trip: bound by vector ALU issue
+        roofline = {"bound": "alu", "achieved": round(d["tflops"], 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(d["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
+                    "kernel": kernel_sym, "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
+                    "algorithmic_flops_per_launch": d["avg_flops"],
+                    "algorithmic_bytes_per_launch": int(d["avg_bytes"]),
+                    "hbm_gbs": round(achieved, 1), "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_sym,
+                    "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
+                    "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
     # forward-only circuit evals/s (the 64 circuits of one forward pass)
-    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("matrices", "init", "tile", "rtile", "rtile_persist",
-                                                          "stride", "expect", "finalize")) / args.steps
+    fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("matrices", "fuse", "init", "tile", "rtile",
+                                                          "rtile_persist", "stride", "expect",
+                                                          "finalize")) / args.steps
     circuit_evals_per_s = wl.B / (fwd_ms / 1e3)
 
     extra = {}
@@ -250,8 +265,8 @@ def main():
                    "fusion": args.fusion},
         "roofline": roofline,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
-        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1)}
-                    for k, v in per.items()},
+        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1),
+                        "tflops": round(v["tflops"], 2)} for k, v in per.items()},
         "kernel_source_hash": kernel_source_hash(),
     }
     out.update(extra)

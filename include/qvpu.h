@@ -114,8 +114,10 @@ typedef enum {
 typedef struct {
     int32_t kernel;  /* qv_kernel_id */
     int32_t level;   /* pass level within the call, -1 for other kernels */
-    int64_t bytes;
-    double ms;
+    int64_t bytes;   /* algorithmic state bytes the launch reads and writes */
+    double ms;       /* duration between HIP events recorded around the launch on the context stream */
+    double flops;    /* algorithmic flops of gate passes (per amplitude: 14 for H/RX/RY, 6 for S/T/RZ, 0 for
+                        X/Y/Z/CNOT/CZ; adjoint: twice that plus 4 per trainable gate); 0 for other kernels */
 } qv_launch_rec;
 
 typedef struct qv_ctx_s *qv_ctx;

@@ -169,9 +169,31 @@ struct Level {
     int32_t lds_t;
     int32_t kind;     // LevelKind
     int64_t bytes;    // algorithmic state bytes moved by the launch (read + write)
+    double flops;     // algorithmic floating-point operations of the launch (op_flops per amplitude)
     int32_t max_train;
     int32_t tab_bits; // largest (tile qubits - contiguous low qubits) of the level's passes
 };
+
+// Algorithmic flops per amplitude of a gate: a dense complex 2x2 product costs two complex multiplies and
+// one complex add per output amplitude (14), a diagonal phase one complex multiply (6); X, Y, Z, CNOT and
+// CZ are permutations and sign flips (0). Fused-block markers add nothing (their gates are counted).
+static double op_flops(int kind)
+{
+    switch (kind) {
+    case QV_H: case QV_RX: case QV_RY: return 14.0;
+    case QV_S: case QV_T: case QV_RZ: return 6.0;
+    default: return 0.0;
+    }
+}
+
+// Per amplitude: forward applies each gate once; the adjoint un-applies it from psi and lambda and takes
+// the imaginary part of one complex product per trainable gate (4).
+static double pass_flops(const PlanPass &pp, bool adjoint)
+{
+    double f = 0.0;
+    for (const PlanOp &op : pp.ops) f += op_flops(op.kind);
+    return adjoint ? 2.0 * f + 4.0 * pp.n_train : f;
+}
 
 static int pass_kind(const PlanPass &pp)
 {
@@ -199,7 +221,8 @@ struct LaunchLog {
 };
 
 template <typename F>
-static int logged(LaunchLog *log, hipStream_t s, int kernel, int level, int64_t bytes, F launch)
+static int logged(LaunchLog *log, hipStream_t s, int kernel, int level, int64_t bytes, F launch,
+                  double flops = 0.0)
 {
     if (!log) return launch();
     hipEvent_t a = log->next(), b = log->next();
@@ -212,6 +235,7 @@ static int logged(LaunchLog *log, hipStream_t s, int kernel, int level, int64_t 
     r.level = level;
     r.bytes = bytes;
     r.ms = 0.0;
+    r.flops = flops;
     log->recs.push_back(r);
     log->ev.emplace_back(a, b);
     return e;
@@ -428,7 +452,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
         for (int dir = 0; dir < 2; dir++) {
             for (int L = 0; L < maxp; L++) {
                 for (int kind = 0; kind < 3; kind++) {
-                    Level lv{(int64_t)es.segs.size(), 0, 0, 0, kind, 0, 0, 0};
+                    Level lv{(int64_t)es.segs.size(), 0, 0, 0, kind, 0, 0.0, 0, 0};
                     for (int c = w0; c < w1; c++) {
                         const Plan &pl = plans[es.plan_of[c]];
                         const int np = (int)pl.passes.size();
@@ -456,6 +480,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         lv.max_train = std::max(lv.max_train, pp.n_train);
                         lv.tab_bits = std::max(lv.tab_bits, pp.t - pp.lowc);
                         lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : 4) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
+                        lv.flops += pass_flops(pp, dir == 1) * (double)((int64_t)1 << es.circs[c].n);
                     }
                     if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
                 }
@@ -763,9 +788,10 @@ static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans 
     pa.error = es.d_p_error.as<int32_t>();
     pa.spin_limit = (int64_t)1 << 21;  // ~0.1 s of 128-clock sleeps
     int64_t bytes = 0;
-    for (const Level &lv : lvs) bytes += lv.bytes;
+    double flops = 0.0;
+    for (const Level &lv : lvs) { bytes += lv.bytes; flops += lv.flops; }
     return logged(log, s, dir == 0 ? QV_K_RTILE_PERSIST : QV_K_RTILE_ADJ_PERSIST, -1, bytes,
-                  [&] { return launch_persistent(pa, bt.prec, dir, s); });
+                  [&] { return launch_persistent(pa, bt.prec, dir, s); }, flops);
 }
 
 static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, void *psi, double *energies,
@@ -783,7 +809,8 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
         for (size_t L = 0; L < es.fwd.size(); L++) {
             const Level &lv = es.fwd[L];
             LevelArgs a = level_args(bt, es, dp, lv, psi, nullptr);
-            e = logged(log, s, log_id(lv, 0), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 0, s); });
+            e = logged(log, s, log_id(lv, 0), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 0, s); },
+                       lv.flops);
             if (e) return e;
         }
     }
@@ -831,7 +858,8 @@ static int enqueue_adjoint(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
         for (size_t L = 0; L < es.rev.size(); L++) {
             const Level &lv = es.rev[L];
             LevelArgs a = level_args(bt, es, dp, lv, bt.d_psi.p, bt.d_lam.p);
-            e = logged(log, s, log_id(lv, 1), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 1, s); });
+            e = logged(log, s, log_id(lv, 1), (int)L, lv.bytes, [&] { return launch_kind(lv, a, bt.prec, 1, s); },
+                       lv.flops);
             if (e) return e;
         }
     }

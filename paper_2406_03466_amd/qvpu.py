@@ -39,7 +39,7 @@ class qv_stats(ctypes.Structure):
 
 class qv_launch_rec(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("level", ctypes.c_int32), ("bytes", ctypes.c_int64),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
@@ -262,7 +262,8 @@ class Batch:
             return []
         arr = (qv_launch_rec * n.value)()
         _check(load().qv_batch_launch_log(self.h, arr, n.value, ctypes.byref(n)))
-        return [{"kernel": KERNEL_NAMES[r.kernel], "level": r.level, "bytes": r.bytes, "ms": r.ms} for r in arr]
+        return [{"kernel": KERNEL_NAMES[r.kernel], "level": r.level, "bytes": r.bytes, "ms": r.ms,
+                 "flops": r.flops} for r in arr]
 
     def close(self):
         if getattr(self, "h", None):
