@@ -88,6 +88,52 @@ def cpu_baseline(wl_full, max_seconds: float = 20.0):
                       f"{dt:.1f} s, scaled by {k}/{wl_full.B}"}
 
 
+def timed(fn, stream_sync, reps: int = 1) -> float:
+    """Seconds per call of fn after one untimed call (plans, buffers, graphs)."""
+    fn()
+    stream_sync()
+    t0 = time.time()
+    for _ in range(reps):
+        fn()
+    stream_sync()
+    return (time.time() - t0) / reps
+
+
+def other_workloads(qvpu, W, stream, sync) -> dict:
+    """Circuit-eval rates of the other workload shapes, each on its own batch (created and freed here):
+    16-qubit VQE parameter-shift gradient (513 circuits), 1024 uneven random circuits, and the 32-qubit
+    10-layer circuit (32 GiB complex64 state) forward and adjoint, with and without fused MFMA blocks."""
+    out = {}
+
+    def ctx(**o):
+        o.setdefault("graph", True)
+        return qvpu.Context(0, stream.cuda_stream, json.dumps(o))
+
+    wl = W.config2()
+    for prec, name in [(qvpu.QV_C64, "c64"), (qvpu.QV_C128, "c128")]:
+        b = qvpu.Batch(ctx(), wl, prec)
+        s = timed(lambda: b.gradient(qvpu.QV_PARAM_SHIFT), sync, 3)
+        out[f"hea16_L8_T100_param_shift_{name}"] = {"circuit_evals_per_s": round(513 / s, 1),
+                                                     "gradient_ms": round(s * 1e3, 3), "circuits": 513}
+        b.close()
+    wl = W.config4()
+    b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
+    s = timed(lambda: b.expectations(), sync, 3)
+    out["random1024_expectations_c64"] = {"circuit_evals_per_s": round(wl.B / s, 1), "ms": round(s * 1e3, 3),
+                                          "circuits": wl.B}
+    b.close()
+    wl = W.config5()
+    for fusion in ["off", "4"]:
+        b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
+        sf = timed(lambda: b.expectations(), sync, 1)
+        sg = timed(lambda: b.gradient(qvpu.QV_ADJOINT), sync, 1)
+        st = b.stats()
+        out[f"hea32_L10_c64_fusion_{fusion}"] = {"forward_ms": round(sf * 1e3, 2), "gradient_ms": round(sg * 1e3, 2),
+                                                  "passes": st["passes_per_circuit_max"]}
+        b.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +142,7 @@ def main():
     ap.add_argument("--layers", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ps", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workload shapes")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
@@ -270,6 +317,8 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
     }
     out.update(extra)
+    if not args.no_extras:
+        out["other_workloads"] = other_workloads(qvpu, W, stream, torch.cuda.synchronize)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -234,6 +234,8 @@ int launch_stride_level(const LevelArgs &a, int precision, int adjoint, void *st
 int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_persistent(const PersistArgs &a, int precision, int adjoint, void *stream);
 int persistent_blocks(int precision, int adjoint, int lds_t, int tab_bits, int max_train, int *blocks);
+// 1 when one persistent launch can hold the largest tile of the given passes in LDS.
+int persistent_fits(int precision, int adjoint, int lds_t, int tab_bits, int max_train);
 int launch_zero_u64(unsigned long long *p, int64_t n, void *stream);
 int launch_init_states(void *psi, const DevCirc *circs, const int64_t *first_block, int32_t n_circ,
                        int64_t n_blocks, int precision, void *stream);

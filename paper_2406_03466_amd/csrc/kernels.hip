@@ -1120,46 +1120,37 @@ static size_t tile_lds_bytes(int lds_t, int tab_bits, int amp_bytes, int adjoint
            sizeof(double) * (kBlock / 64);
 }
 
+// Dynamic LDS the persistent kernels may use: the whole 160 KiB less their static work-item slot.
+constexpr int kLdsLimit = 160 * 1024;
+constexpr int kPersistStaticLds = 64;
+
+static hipError_t allow_lds(const void *fn, int bytes)
+{
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 int prepare_kernels()
 {
-    const int lim = 160 * 1024;
-    hipError_t e = hipSuccess;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<float, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<float, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<double, false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_tile<double, true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd<float, kRegBitsC64, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj<float, kRegBitsC64, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd<double, kRegBitsC128, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj<double, kRegBitsC128, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    return e;
+    const int lim = kLdsLimit, plim = kLdsLimit - kPersistStaticLds;
+    const struct { const void *fn; int bytes; } ks[] = {
+        {reinterpret_cast<const void *>(&k_tile<float, false>), lim},
+        {reinterpret_cast<const void *>(&k_tile<float, true>), lim},
+        {reinterpret_cast<const void *>(&k_tile<double, false>), lim},
+        {reinterpret_cast<const void *>(&k_tile<double, true>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_fwd<float, kRegBitsC64, kRtileThreads>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_adj<float, kRegBitsC64, kRtileThreads>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_fwd<double, kRegBitsC128, kRtileThreads>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_adj<double, kRegBitsC128, kRtileThreads>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>), plim},
+        {reinterpret_cast<const void *>(&k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>), plim},
+        {reinterpret_cast<const void *>(&k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>), plim},
+        {reinterpret_cast<const void *>(&k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>), plim},
+    };
+    for (const auto &k : ks) {
+        const hipError_t e = allow_lds(k.fn, k.bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 static size_t rtile_lds_bytes(int precision, int adjoint, int lds_t, int tab_bits, int max_train)
@@ -1169,10 +1160,16 @@ static size_t rtile_lds_bytes(int precision, int adjoint, int lds_t, int tab_bit
            (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)max_train : 0);
 }
 
+int persistent_fits(int precision, int adjoint, int lds_t, int tab_bits, int max_train)
+{
+    return rtile_lds_bytes(precision, adjoint, lds_t, tab_bits, max_train) <=
+           (size_t)(kLdsLimit - kPersistStaticLds);
+}
+
 int persistent_blocks(int precision, int adjoint, int lds_t, int tab_bits, int max_train, int *blocks)
 {
     const size_t lds = rtile_lds_bytes(precision, adjoint, lds_t, tab_bits, max_train) + 64;
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > (size_t)kLdsLimit) return hipErrorInvalidValue;
     const void *k = precision == QV_C64
                         ? (adjoint ? reinterpret_cast<const void *>(&k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>)
                                    : reinterpret_cast<const void *>(&k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>))
@@ -1193,7 +1190,7 @@ int launch_persistent(const PersistArgs &a, int precision, int adjoint, void *st
     if (a.n_items <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const size_t lds = rtile_lds_bytes(precision, adjoint, a.base.lds_t, a.base.tab_bits, a.base.max_train);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > (size_t)(kLdsLimit - kPersistStaticLds)) return hipErrorInvalidValue;
     int blocks = 0;
     hipError_t e = (hipError_t)persistent_blocks(precision, adjoint, a.base.lds_t, a.base.tab_bits, a.base.max_train,
                                                  &blocks);
@@ -1225,7 +1222,7 @@ int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
     const int amp = precision == QV_C64 ? 8 : 16;
     const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint) +
                        (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)a.max_train : 0);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > (size_t)kLdsLimit) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.n_blocks), block(kRtileThreads);
     if (precision == QV_C64) {
         if (adjoint) hipLaunchKernelGGL((k_rtile_adj<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
@@ -1243,7 +1240,7 @@ int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream)
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int amp = precision == QV_C64 ? 8 : 16;
     const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > (size_t)kLdsLimit) return hipErrorInvalidValue;
     dim3 grid((unsigned)a.n_blocks), block(kBlock);
     if (precision == QV_C64) {
         if (adjoint) hipLaunchKernelGGL((k_tile<float, true>), grid, block, lds, s, a);

@@ -519,7 +519,10 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
             es.p_max_train[dir] = std::max(es.p_max_train[dir], lv.max_train);
         }
         (dir == 0 ? es.p_fwd_items : es.p_rev_items) = items;
-        (dir == 0 ? es.p_fwd_ok : es.p_rev_ok) = ok && !lvs.empty();
+        ok = ok && !lvs.empty() &&
+             persistent_fits(amp_bytes == 8 ? QV_C64 : QV_C128, dir, es.p_lds_t[dir], es.p_tab_bits[dir],
+                             es.p_max_train[dir]);
+        (dir == 0 ? es.p_fwd_ok : es.p_rev_ok) = ok;
     }
     es.algo_bytes_fwd = es.init_bytes;
     for (const Level &lv : es.fwd) es.algo_bytes_fwd += lv.bytes;
