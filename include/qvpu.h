@@ -131,9 +131,9 @@ typedef struct qv_batch_s *qv_batch;
  *                      "lds" (LDS tile passes, one gate at a time in LDS) or "stride" (one global-memory
  *                      pass per gate);
  *   "tile_qubits"    : int 6..14 or "auto" (default "auto": the autotuner's choice);
- *   "launch"         : "levels" (one launch per pass level, default) or "persistent" (all levels of a
- *                      sweep in one launch: resident workgroups take tiles from a queue in level order and
- *                      wait, with a bounded spin, until their circuit's earlier passes are complete);
+ *   "launch"         : "levels" (one launch per pass level, default). "persistent" (all levels of a
+ *                      sweep in one launch, resident workgroups taking tiles from a queue in level order)
+ *                      is disabled in this version and returns QV_E_UNSUPPORTED;
  *   "fusion"         : "off" (default), "on" (runs of >= 6 gates) or a minimum run length: within a
  *                      register segment, consecutive gates acting only on its 4 register qubits are
  *                      multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);

@@ -920,7 +920,9 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             c->launch_events = (v == "true" || v == "1");
         } else if (k == "launch") {
             if (v == "levels") c->persistent = 0;
-            else if (v == "persistent") c->persistent = 1;
+            else if (v == "persistent")
+                // switched off: its first device run did not finish and the cause is not yet known
+                return fail(QV_E_UNSUPPORTED, "launch \"persistent\" is disabled in this version; use \"levels\"");
             else return fail(QV_E_INVALID, "launch must be \"levels\" or \"persistent\"");
         } else if (k == "autotune") {
             if (v == "off") c->autotune = 0;

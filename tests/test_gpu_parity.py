@@ -20,6 +20,11 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
+# The persistent launch mode did not finish on its first device run (complex128, 10 qubits, adjoint +
+# parameter-shift); the library rejects it until the cause is found, and these cases stay skipped.
+SKIP_PERSISTENT = pytest.mark.skip(reason="persistent launch mode is disabled: its first device run did not "
+                                          "finish and the cause is not yet found")
+
 
 def say(msg):
     print(f"[gpu] {msg}", flush=True)
@@ -82,9 +87,10 @@ def test_c1_expectations(qv, prec, opts):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("opts", [{}, {"tile_qubits": 6}, {"engine": "stride"}, {"engine": "lds"},
-                                  {"engine": "lds", "tile_qubits": 7}, {"launch": "persistent"},
-                                  {"launch": "persistent", "tile_qubits": 6}, {"fusion": 2},
-                                  {"fusion": 3, "launch": "persistent", "tile_qubits": 8}])
+                                  {"engine": "lds", "tile_qubits": 7},
+                                  pytest.param({"launch": "persistent"}, marks=SKIP_PERSISTENT),
+                                  pytest.param({"launch": "persistent", "tile_qubits": 6}, marks=SKIP_PERSISTENT),
+                                  {"fusion": 2}, {"fusion": 3, "tile_qubits": 8}])
 def test_c1_gradients(qv, prec, opts):
     say(f"c1 gradients prec={prec} opts={opts}")
     wl = W.config1()
@@ -121,7 +127,9 @@ def test_c2_full(qv, prec):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("tile,engine", [(6, "tiled"), (9, "tiled"), (None, "tiled"), (8, "lds"), (None, "lds"),
-                                         (9, "persistent"), (None, "persistent"), (None, "fused"), (8, "fused")])
+                                         pytest.param(9, "persistent", marks=SKIP_PERSISTENT),
+                                         pytest.param(None, "persistent", marks=SKIP_PERSISTENT),
+                                         (None, "fused"), (8, "fused")])
 def test_uneven_batch(qv, prec, tile, engine):
     """Circuits of 2..16 qubits and 0..80 gates in one batch: per-circuit energies, terms, states and
     adjoint gradients (own parameters per circuit) with upstream weights."""
@@ -336,6 +344,7 @@ def test_autotune_search_and_cache(qv, tmp_path, monkeypatch):
     assert (st2["tile_qubits"], st2["contig_qubits"]) == (st["tile_qubits"], st["contig_qubits"])
 
 
+@SKIP_PERSISTENT
 @pytest.mark.parametrize("layers", [2, 8])
 def test_persistent_matches_levels_bitwise(qv, layers):
     """One persistent launch per sweep (work queue with per-circuit waits) gives bit-identical energies and
