@@ -86,6 +86,21 @@ struct M2 {
     R re[4], im[4];
 };
 
+// Read-only tables indexed by workgroup-uniform values: loads through the constant address space, so
+// they become scalar loads.
+template <typename T>
+__device__ __forceinline__ T ldu(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole words only");
+    const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+    uint32_t w[sizeof(T) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) w[i] = q[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
 template <typename R>
 __device__ __forceinline__ M2<R> narrow(const M2d &m)
 {
@@ -346,134 +361,162 @@ __device__ __forceinline__ uint32_t reg_pattern(int k)
     default: { constexpr int K = (RB_) > 4 ? 4 : 0; if ((RB_) > 4) { STMT; } } break; \
     }
 
+// A thread's 2^RB register amplitudes as one vector value (re, im interleaved). Every update below uses
+// compile-time element indices, so the vector stays in one fixed block of registers across the op loop and
+// its branches instead of being copied between them.
+template <typename R, int N>
+struct Regs {
+    typedef R V __attribute__((ext_vector_type(2 * N)));
+    V d;
+    __device__ __forceinline__ Cx<R> get(int j) const
+    {
+        Cx<R> c;
+        c.re = d[2 * j];
+        c.im = d[2 * j + 1];
+        return c;
+    }
+    __device__ __forceinline__ void set(int j, R re, R im)
+    {
+        d[2 * j] = re;
+        d[2 * j + 1] = im;
+    }
+    __device__ __forceinline__ void set(int j, Cx<R> c) { set(j, c.re, c.im); }
+};
+
 // [[c, -s], [s, c]] on register bit K (RY and its inverse).
 template <int K, int N, typename R>
-__device__ __forceinline__ void r_real(Cx<R> (&v)[N], R c, R s)
+__device__ __forceinline__ void r_real(Regs<R, N> &v, R c, R s)
 {
 #pragma unroll
     for (int j = 0; j < N; j++) {
         if (j & (1 << K)) continue;
         const int j1 = j | (1 << K);
-        const Cx<R> x = v[j], y = v[j1];
-        v[j].re = c * x.re - s * y.re;
-        v[j].im = c * x.im - s * y.im;
-        v[j1].re = s * x.re + c * y.re;
-        v[j1].im = s * x.im + c * y.im;
+        const Cx<R> x = v.get(j), y = v.get(j1);
+        v.set(j, c * x.re - s * y.re, c * x.im - s * y.im);
+        v.set(j1, s * x.re + c * y.re, s * x.im + c * y.im);
     }
 }
 
 template <int K, int N, typename R>
-__device__ __forceinline__ void r_gen(Cx<R> (&v)[N], const M2<R> &m)
+__device__ __forceinline__ void r_gen(Regs<R, N> &v, const M2<R> &m)
 {
 #pragma unroll
     for (int j = 0; j < N; j++) {
         if (j & (1 << K)) continue;
-        apply2(m, v[j], v[j | (1 << K)]);
+        const int j1 = j | (1 << K);
+        Cx<R> x = v.get(j), y = v.get(j1);
+        apply2(m, x, y);
+        v.set(j, x);
+        v.set(j1, y);
     }
 }
 
 // diag(d0, d1) on register bit K.
 template <int K, int N, typename R>
-__device__ __forceinline__ void r_diag(Cx<R> (&v)[N], R d0r, R d0i, R d1r, R d1i)
+__device__ __forceinline__ void r_diag(Regs<R, N> &v, R d0r, R d0i, R d1r, R d1i)
 {
 #pragma unroll
     for (int j = 0; j < N; j++) {
         const R dr = (j & (1 << K)) ? d1r : d0r, di = (j & (1 << K)) ? d1i : d0i;
-        const Cx<R> x = v[j];
-        v[j].re = dr * x.re - di * x.im;
-        v[j].im = dr * x.im + di * x.re;
+        const Cx<R> x = v.get(j);
+        v.set(j, dr * x.re - di * x.im, dr * x.im + di * x.re);
     }
 }
 
 template <int N, typename R>
-__device__ __forceinline__ void t_scale(Cx<R> (&v)[N], R dr, R di)
+__device__ __forceinline__ void t_scale(Regs<R, N> &v, R dr, R di)
 {
 #pragma unroll
     for (int j = 0; j < N; j++) {
-        const Cx<R> x = v[j];
-        v[j].re = dr * x.re - di * x.im;
-        v[j].im = dr * x.im + di * x.re;
+        const Cx<R> x = v.get(j);
+        v.set(j, dr * x.re - di * x.im, dr * x.im + di * x.re);
     }
 }
 
-// CNOT with target register bit KT; the control is register j's bit of m (pair j, j | 2^KT).
-template <int KT, int N, typename R>
-__device__ __forceinline__ void r_cnot_mask(Cx<R> (&v)[N], uint32_t m)
+// CNOT with target register bit KT and control register bit KC: a fixed permutation of the registers.
+template <int KC, int KT, int N, typename R>
+__device__ __forceinline__ void r_cnot(Regs<R, N> &v)
 {
+    if constexpr (KC == KT) return;
 #pragma unroll
     for (int j = 0; j < N; j++) {
-        if (j & (1 << KT)) continue;
+        if ((j & (1 << KT)) || !(j & (1 << KC))) continue;
         const int j1 = j | (1 << KT);
-        const bool c = (m >> j) & 1u;
-        const Cx<R> x = v[j], y = v[j1];
-        v[j] = c ? y : x;
-        v[j1] = c ? x : y;
+        const Cx<R> x = v.get(j), y = v.get(j1);
+        v.set(j, y);
+        v.set(j1, x);
     }
+}
+
+template <int KC, int RB, int N, typename R>
+__device__ __forceinline__ void r_cnot_t(Regs<R, N> &v, int kt)
+{
+    if constexpr (KC < RB) WITH_K(RB, kt, (r_cnot<KC, K>(v)));
 }
 
 // CNOT with target register bit KT, control given per thread.
 template <int KT, int N, typename R>
-__device__ __forceinline__ void t_cnot(Cx<R> (&v)[N], bool ctl)
+__device__ __forceinline__ void t_cnot(Regs<R, N> &v, bool ctl)
 {
 #pragma unroll
     for (int j = 0; j < N; j++) {
         if (j & (1 << KT)) continue;
         const int j1 = j | (1 << KT);
-        const Cx<R> x = v[j], y = v[j1];
-        v[j] = ctl ? y : x;
-        v[j1] = ctl ? x : y;
+        const Cx<R> x = v.get(j), y = v.get(j1);
+        v.set(j, ctl ? y : x);
+        v.set(j1, ctl ? x : y);
     }
 }
 
 // Negates register j where bit j of m is set.
 template <int N, typename R>
-__device__ __forceinline__ void neg_mask(Cx<R> (&v)[N], uint32_t m)
+__device__ __forceinline__ void neg_mask(Regs<R, N> &v, uint32_t m)
 {
 #pragma unroll
     for (int j = 0; j < N; j++) {
-        if (m >> j & 1u) {
-            v[j].re = -v[j].re;
-            v[j].im = -v[j].im;
-        }
+        const Cx<R> x = v.get(j);
+        const bool f = (m >> j) & 1u;
+        v.set(j, f ? -x.re : x.re, f ? -x.im : x.im);
     }
 }
 
-// Im <l| G |a> over the register pairs of bit K, G the generator of the rotation kind. FP64.
+// Im <l| G |a> over the register pairs of bit K, G the generator of the rotation kind: per pair in R
+// precision, summed in FP64.
 template <int K, int N, typename R>
-__device__ __forceinline__ double r_inner(int kind, const Cx<R> (&a)[N], const Cx<R> (&l)[N])
+__device__ __forceinline__ double r_inner(int kind, const Regs<R, N> &a, const Regs<R, N> &l)
 {
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < N; j++) {
         if (j & (1 << K)) continue;
         const int j1 = j | (1 << K);
-        acc += (double)gen_inner_r<R>(kind, a[j], a[j1], l[j], l[j1]);
+        acc += (double)gen_inner_r<R>(kind, a.get(j), a.get(j1), l.get(j), l.get(j1));
     }
     return acc;
 }
 
 // Im <l| Z_p |a> when qubit p is a thread bit with value `bit`.
 template <int N, typename R>
-__device__ __forceinline__ double t_inner_z(const Cx<R> (&a)[N], const Cx<R> (&l)[N], int bit)
+__device__ __forceinline__ double t_inner_z(const Regs<R, N> &a, const Regs<R, N> &l, int bit)
 {
     double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; j++)
-        acc += (double)(l[j].re * a[j].im - l[j].im * a[j].re);
+    for (int j = 0; j < N; j++) {
+        const Cx<R> x = a.get(j), y = l.get(j);
+        acc += (double)(y.re * x.im - y.im * x.re);
+    }
     return bit ? -acc : acc;
 }
 
 // One op applied to the registers v (the inverse when INV).
 template <bool INV, int RB, typename R>
-__device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, int kind, const M2<R> &mat,
+__device__ __forceinline__ void rop_apply(Regs<R, 1 << RB> &v, const DevOp &op, int kind, const M2<R> &mat,
                                           uint32_t Et)
 {
-    constexpr int N = 1 << RB;
     if (kind == QV_CNOT) {
         if (op.k0 >= 0) {
-            // control on a register bit: a per-register mask, so every pair swap is a select
-            const uint32_t m = reg_pattern(op.k0);
-            WITH_K(RB, op.k1, r_cnot_mask<K>(v, m));
+            // control and target both register bits: a fixed permutation of the registers
+            WITH_K(RB, op.k0, (r_cnot_t<K, RB>(v, op.k1)));
         } else {
             const bool ctl = (Et >> op.p0) & 1u;
             WITH_K(RB, op.k1, t_cnot<K>(v, ctl));
@@ -507,6 +550,84 @@ __device__ __forceinline__ void rop_apply(Cx<R> (&v)[1 << RB], const DevOp &op, 
     WITH_K(RB, op.k0, r_gen<K>(v, m));
 }
 
+// Adjoint step for one op on psi (a) and lambda (l) together, one dispatch on the op's register bit:
+// Im <l| G |a> when the op is trainable (returned through ip), then the inverse op on both.
+template <int K, int N, typename R>
+__device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s, bool train, double &ip)
+{
+    if (train) ip = r_inner<K>(QV_RY, a, l);
+    r_real<K>(a, c, s);
+    r_real<K>(l, c, s);
+}
+
+template <int K, int N, typename R>
+__device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, int kind, R d0r, R d0i, R d1r, R d1i,
+                                         bool train, double &ip)
+{
+    if (train) ip = r_inner<K>(kind, a, l);
+    r_diag<K>(a, d0r, d0i, d1r, d1i);
+    r_diag<K>(l, d0r, d0i, d1r, d1i);
+}
+
+template <int K, int N, typename R>
+__device__ __forceinline__ void adj_gen(Regs<R, N> &a, Regs<R, N> &l, int kind, const M2<R> &m, bool train,
+                                        double &ip)
+{
+    if (train) ip = r_inner<K>(kind, a, l);
+    r_gen<K>(a, m);
+    r_gen<K>(l, m);
+}
+
+template <int KC, int RB, int N, typename R>
+__device__ __forceinline__ void adj_cnot_t(Regs<R, N> &a, Regs<R, N> &l, int kt)
+{
+    if constexpr (KC < RB) WITH_K(RB, kt, (r_cnot<KC, K>(a), r_cnot<KC, K>(l)));
+}
+
+template <int RB, typename R>
+__device__ __forceinline__ double rop_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 << RB> &l, const DevOp &op, int kind,
+                                              const M2<R> &mat, uint32_t Et)
+{
+    const bool train = (op.flags & OP_TRAIN) != 0;
+    double ip = 0.0;
+    if (kind == QV_CNOT) {
+        if (op.k0 >= 0) {
+            WITH_K(RB, op.k0, (adj_cnot_t<K, RB>(a, l, op.k1)));
+        } else {
+            const bool ctl = (Et >> op.p0) & 1u;
+            WITH_K(RB, op.k1, (t_cnot<K>(a, ctl), t_cnot<K>(l, ctl)));
+        }
+        return ip;
+    }
+    if (kind == QV_CZ) {
+        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
+        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
+        neg_mask(a, ma & mb);
+        neg_mask(l, ma & mb);
+        return ip;
+    }
+    if (kind == QV_RY) {
+        const R cr = mat.re[0], sr = -mat.re[2];
+        WITH_K(RB, op.k0, (adj_real<K>(a, l, cr, sr, train, ip)));
+        return ip;
+    }
+    if (kind == QV_RZ || kind == QV_Z || kind == QV_S || kind == QV_T) {
+        const R d0r = mat.re[0], d1r = mat.re[3], d0i = -mat.im[0], d1i = -mat.im[3];
+        if (op.k0 >= 0) {
+            WITH_K(RB, op.k0, (adj_diag<K>(a, l, kind, d0r, d0i, d1r, d1i, train, ip)));
+        } else {
+            const bool b = (Et >> op.p0) & 1u;
+            if (train) ip = t_inner_z(a, l, (int)b);
+            t_scale(a, b ? d1r : d0r, b ? d1i : d0i);
+            t_scale(l, b ? d1r : d0r, b ? d1i : d0i);
+        }
+        return ip;
+    }
+    const M2<R> m = dagger_r(mat);
+    WITH_K(RB, op.k0, (adj_gen<K>(a, l, kind, m, train, ip)));
+    return ip;
+}
+
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // A fused 4-qubit block on the 16 register amplitudes of every lane, as one wave-wide real GEMM on MFMA:
@@ -515,17 +636,14 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // row k from lane half k, so permlane32 swaps pair rows 2s and 2s+1 across the lane halves: one swap
 // yields the B operand of both 32-column halves. Its result holds, per lane half, rows 8i+4h+r of a
 // column; swapping the two halves' accumulators gives every lane its own column back.
-__device__ __forceinline__ void fused_mfma(Cx<float> (&v)[16], const float *__restrict__ A, int lane)
+__device__ __forceinline__ void fused_mfma(Regs<float, 16> &v, const float *__restrict__ A, int lane)
 {
-    float x[32];
-#pragma unroll
-    for (int j = 0; j < 16; j++) { x[2 * j] = v[j].re; x[2 * j + 1] = v[j].im; }
     v16f acc0, acc1;
 #pragma unroll
     for (int q = 0; q < 16; q++) { acc0[q] = 0.f; acc1[q] = 0.f; }
 #pragma unroll
     for (int s = 0; s < 16; s++) {
-        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[2 * s]), __float_as_uint(x[2 * s + 1]),
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.d[2 * s]), __float_as_uint(v.d[2 * s + 1]),
                                                          false, false);
         const float a = A[s * 64 + lane];
         acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, __uint_as_float(sw[0]), acc0, 0, 0, 0);
@@ -536,11 +654,9 @@ __device__ __forceinline__ void fused_mfma(Cx<float> (&v)[16], const float *__re
         const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc0[q]), __float_as_uint(acc1[q]), false,
                                                          false);
         const int rlo = 8 * (q / 4) + (q % 4);
-        x[rlo] = __uint_as_float(sw[0]);
-        x[rlo + 4] = __uint_as_float(sw[1]);
+        v.d[rlo] = __uint_as_float(sw[0]);
+        v.d[rlo + 4] = __uint_as_float(sw[1]);
     }
-#pragma unroll
-    for (int j = 0; j < 16; j++) { v[j].re = x[2 * j]; v[j].im = x[2 * j + 1]; }
 }
 
 template <typename R, bool ADJ, int RB, int NT>
@@ -549,8 +665,8 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
     constexpr int N = 1 << RB;
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t tile = blk - sg.first_block;
-    const DevPass P = a.passes[sg.pass];
-    const DevCirc C = a.circs[sg.circ];
+    const DevPass P = ldu(a.passes + sg.pass);
+    const DevCirc C = ldu(a.circs + sg.circ);
     const int n = C.n, t = P.t, lowc = P.pad;
     const uint32_t T = 1u << t;
     const int TL = 1 << (a.lds_t);
@@ -595,7 +711,7 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
 
     for (int s0 = 0; s0 < P.n_seg; s0++) {
         const int si = ADJ ? P.n_seg - 1 - s0 : s0;
-        const DevSeg S = a.rsegs[P.seg_begin + si];
+        const DevSeg S = ldu(a.rsegs + P.seg_begin + si);
         uint32_t Et = 0;
 #pragma unroll
         for (int m = 0; m < 16; m++)
@@ -604,7 +720,7 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
         uint32_t rbit[RB];
 #pragma unroll
         for (int k = 0; k < RB; k++) rbit[k] = 1u << S.rpos[k];
-        Cx<R> av[N], lv[N];
+        Regs<R, N> av, lv;
 #pragma unroll
         for (int j = 0; j < N; j++) {
             uint32_t D = 0;
@@ -612,22 +728,22 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             for (int k = 0; k < RB; k++)
                 if (j >> k & 1) D |= rbit[k];
             const uint32_t addr = PE ^ swz(D);
-            av[j] = sp[addr];
-            if (ADJ) lv[j] = sl[addr];
+            av.set(j, sp[addr]);
+            if (ADJ) lv.set(j, sl[addr]);
         }
         // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
         const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.mat_off - C.op_base);
         int64_t oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
-        DevOp nop = a.ops[oi];
-        M2<R> nmat = mtab[oi];
+        DevOp nop = ldu(a.ops + oi);
+        M2<R> nmat = ldu(mtab + oi);
         for (int k0 = 0; k0 < S.n_ops; k0++) {
             const DevOp op = nop;
             M2<R> mat = nmat;
             const int64_t cur = oi;
             if (k0 + 1 < S.n_ops) {
                 oi += ADJ ? -1 : 1;
-                nop = a.ops[oi];
-                nmat = mtab[oi];
+                nop = ldu(a.ops + oi);
+                nmat = ldu(mtab + oi);
             }
             const int kind = op.kind;
             if (kind == kFusedKind) {
@@ -637,15 +753,15 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                     const int m = op.pad;
                     bool shifted = false;
                     if (C.shift_gate >= 0)
-                        for (int j = 1; j <= m; j++) shifted |= a.ops[cur + j].gate == C.shift_gate;
+                        for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
                     if (!shifted) {
                         const int f = op.p0 | (op.p1 << 8);
                         fused_mfma(av, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
                         k0 += m;
                         if (k0 + 1 < S.n_ops) {
                             oi = cur + m + 1;
-                            nop = a.ops[oi];
-                            nmat = mtab[oi];
+                            nop = ldu(a.ops + oi);
+                            nmat = ldu(mtab + oi);
                         }
                     }
                 }
@@ -653,20 +769,12 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             }
             if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
             if (ADJ) {
+                double ip = rop_adjoint<RB, R>(av, lv, op, kind, mat, Et);
                 if (op.flags & OP_TRAIN) {
-                    double ip;
-                    if (kind == QV_RZ && op.k0 < 0) {
-                        ip = t_inner_z(av, lv, (int)((Et >> op.p0) & 1u));
-                    } else {
-                        ip = 0.0;
-                        WITH_K(RB, op.k0, ip = r_inner<K>(kind, av, lv));
-                    }
                     if (!active) ip = 0.0;
                     ip = wave_sum_to_63(ip);
                     if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
                 }
-                rop_apply<true, RB, R>(av, op, kind, mat, Et);
-                rop_apply<true, RB, R>(lv, op, kind, mat, Et);
             } else {
                 rop_apply<false, RB, R>(av, op, kind, mat, Et);
             }
@@ -679,8 +787,8 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                 for (int k = 0; k < RB; k++)
                     if (j >> k & 1) D |= rbit[k];
                 const uint32_t addr = PE ^ swz(D);
-                sp[addr] = av[j];
-                if (ADJ) sl[addr] = lv[j];
+                sp[addr] = av.get(j);
+                if (ADJ) sl[addr] = lv.get(j);
             }
         }
         __syncthreads();
