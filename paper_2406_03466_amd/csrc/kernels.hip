@@ -196,16 +196,22 @@ __device__ __forceinline__ int find_prefix(const int64_t *pre, int n, int64_t bl
 // angle a parameter-shift variant moves.
 // The table is laid out in plan order (entry mat_off + o - op_base for the plan's op o, fused-block markers
 // included), so an op's matrix can be fetched without first reading the op record.
+// Out of line: the shifted gate is rare, and its trigonometry should not hold registers in the op loops.
+template <typename R>
+__device__ __attribute__((noinline)) M2<R> shifted_matrix(const qv_gate *gates, const double *theta, int64_t gate_off,
+                                                          int64_t param_base, int32_t gate, double shift)
+{
+    const qv_gate g = gates[gate_off + gate];
+    const double ang = (g.param >= 0 ? theta[param_base + g.param] : g.angle) + shift;
+    M2d md;
+    gate_matrix(g.kind, ang, md);
+    return narrow<R>(md);
+}
+
 template <typename R>
 __device__ __forceinline__ M2<R> op_matrix(const LevelArgs &a, const DevCirc &C, const DevOp &op, int64_t oi)
 {
-    if (op.gate == C.shift_gate) {
-        const qv_gate g = a.gates[C.gate_off + op.gate];
-        const double ang = (g.param >= 0 ? a.theta[C.param_base + g.param] : g.angle) + C.shift;
-        M2d md;
-        gate_matrix(g.kind, ang, md);
-        return narrow<R>(md);
-    }
+    if (op.gate == C.shift_gate) return shifted_matrix<R>(a.gates, a.theta, C.gate_off, C.param_base, op.gate, C.shift);
     return reinterpret_cast<const M2<R> *>(a.mats)[C.mat_off + (oi - C.op_base)];
 }
 
@@ -659,6 +665,10 @@ __device__ __forceinline__ void fused_mfma(Regs<float, 16> &v, const float *__re
     }
 }
 
+// Amplitudes each thread moves between HBM and LDS per batch of independent loads (or stores).
+template <typename R>
+constexpr int tile_batch() { return sizeof(R) == 4 ? 8 : 4; }
+
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, const Seg &sg)
 {
@@ -695,10 +705,27 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
     } else {
         for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < T; e += NT) {
-            const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
-            sp[swz(e)] = gpsi[g];
-            if (ADJ) sl[swz(e)] = glam[g];
+        // tile_batch<R>() independent loads in flight per thread before any is written to LDS
+        constexpr int TB = tile_batch<R>();
+        for (uint32_t e0 = threadIdx.x; e0 < T; e0 += TB * NT) {
+            Regs<R, TB> bp, bl;
+#pragma unroll
+            for (int u = 0; u < TB; u++) {
+                const uint32_t e = e0 + (uint32_t)u * NT;
+                if (e < T) {
+                    const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+                    bp.set(u, gpsi[g]);
+                    if (ADJ) bl.set(u, glam[g]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TB; u++) {
+                const uint32_t e = e0 + (uint32_t)u * NT;
+                if (e < T) {
+                    sp[swz(e)] = bp.get(u);
+                    if (ADJ) sl[swz(e)] = bl.get(u);
+                }
+            }
         }
     }
     __syncthreads();
@@ -780,13 +807,21 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             }
         }
         if (active) {
+            // recompute the addresses rather than keep 2^RB of them live through the op loop
+            uint32_t pe = PE, rb2[RB];
+            asm volatile("" : "+v"(pe));
+#pragma unroll
+            for (int k = 0; k < RB; k++) {
+                rb2[k] = rbit[k];
+                asm volatile("" : "+s"(rb2[k]));
+            }
 #pragma unroll
             for (int j = 0; j < N; j++) {
                 uint32_t D = 0;
 #pragma unroll
                 for (int k = 0; k < RB; k++)
-                    if (j >> k & 1) D |= rbit[k];
-                const uint32_t addr = PE ^ swz(D);
+                    if (j >> k & 1) D |= rb2[k];
+                const uint32_t addr = pe ^ swz(D);
                 sp[addr] = av.get(j);
                 if (ADJ) sl[addr] = lv.get(j);
             }
@@ -805,10 +840,28 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
         for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
         __syncthreads();
     }
-    for (uint32_t e = threadIdx.x; e < T; e += NT) {
-        const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
-        gpsi[g] = sp[swz(e)];
-        if (ADJ) glam[g] = sl[swz(e)];
+    constexpr int TB = tile_batch<R>();
+    typedef unsigned long long GI __attribute__((ext_vector_type(TB)));
+    for (uint32_t e0 = threadIdx.x; e0 < T; e0 += TB * NT) {
+        Regs<R, TB> bp, bl;
+        GI gi;
+#pragma unroll
+        for (int u = 0; u < TB; u++) {
+            const uint32_t e = e0 + (uint32_t)u * NT;
+            if (e < T) {
+                gi[u] = base | segtab[e >> lowc] | (e & lmask);
+                bp.set(u, sp[swz(e)]);
+                if (ADJ) bl.set(u, sl[swz(e)]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < TB; u++) {
+            const uint32_t e = e0 + (uint32_t)u * NT;
+            if (e < T) {
+                gpsi[gi[u]] = bp.get(u);
+                if (ADJ) glam[gi[u]] = bl.get(u);
+            }
+        }
     }
 }
 
