@@ -17,7 +17,6 @@ oracle timed on the host on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,12 +32,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak (256 CUs a
 TILE_KERNELS = ("rtile", "rtile_adj", "rtile_persist", "rtile_adj_persist", "tile", "tile_adj")
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ["kernels.hip", "engine.h"]:
-        with open(os.path.join(ROOT, "paper_2406_03466_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+from paper_2406_03466_amd.profile_summary import kernel_source_hash  # noqa: E402
 
 
 def pmc_traffic(kernel: str, workload: str):
@@ -147,7 +141,8 @@ def main():
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
     ap.add_argument("--launch", default="levels", choices=["levels", "persistent"])
-    ap.add_argument("--fusion", default="off", help='fused 4-qubit MFMA blocks: "off", "on" or a minimum run length')
+    ap.add_argument("--fusion", default="8",
+                    help='fused 4-qubit MFMA blocks in forward passes: "off", "on" or a minimum run length')
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--levels", action="store_true", help="print per-launch times of one step")
@@ -248,7 +243,7 @@ def main():
     extra = {}
     if not args.no_ps:
         # parameter-shift gradient through the same batched tiled engine, measured in full
-        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False}))
+        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False, "fusion": args.fusion}))
         b_ps = qvpu.Batch(ctx_ps, wl, qvpu.QV_C64)
         with torch.no_grad():
             f = expectation(theta.detach(), batch)
