@@ -556,6 +556,84 @@ __device__ __forceinline__ void rop_apply(Regs<R, 1 << RB> &v, const DevOp &op, 
     WITH_K(RB, op.k0, r_gen<K>(v, m));
 }
 
+// Adjoint step for one op on psi (a) and lambda (l) together, one dispatch on the op's register bit:
+// Im <l| G |a> when the op is trainable (returned through ip), then the inverse op on both.
+template <int K, int N, typename R>
+__device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s, bool train, double &ip)
+{
+    if (train) ip = r_inner<K>(QV_RY, a, l);
+    r_real<K>(a, c, s);
+    r_real<K>(l, c, s);
+}
+
+template <int K, int N, typename R>
+__device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, int kind, R d0r, R d0i, R d1r, R d1i,
+                                         bool train, double &ip)
+{
+    if (train) ip = r_inner<K>(kind, a, l);
+    r_diag<K>(a, d0r, d0i, d1r, d1i);
+    r_diag<K>(l, d0r, d0i, d1r, d1i);
+}
+
+template <int K, int N, typename R>
+__device__ __forceinline__ void adj_gen(Regs<R, N> &a, Regs<R, N> &l, int kind, const M2<R> &m, bool train,
+                                        double &ip)
+{
+    if (train) ip = r_inner<K>(kind, a, l);
+    r_gen<K>(a, m);
+    r_gen<K>(l, m);
+}
+
+template <int KC, int RB, int N, typename R>
+__device__ __forceinline__ void adj_cnot_t(Regs<R, N> &a, Regs<R, N> &l, int kt)
+{
+    if constexpr (KC < RB) WITH_K(RB, kt, (r_cnot<KC, K>(a), r_cnot<KC, K>(l)));
+}
+
+template <int RB, typename R>
+__device__ __forceinline__ double rop_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 << RB> &l, const DevOp &op, int kind,
+                                              const M2<R> &mat, uint32_t Et)
+{
+    const bool train = (op.flags & OP_TRAIN) != 0;
+    double ip = 0.0;
+    if (kind == QV_CNOT) {
+        if (op.k0 >= 0) {
+            WITH_K(RB, op.k0, (adj_cnot_t<K, RB>(a, l, op.k1)));
+        } else {
+            const bool ctl = (Et >> op.p0) & 1u;
+            WITH_K(RB, op.k1, (t_cnot<K>(a, ctl), t_cnot<K>(l, ctl)));
+        }
+        return ip;
+    }
+    if (kind == QV_CZ) {
+        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
+        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
+        neg_mask(a, ma & mb);
+        neg_mask(l, ma & mb);
+        return ip;
+    }
+    if (kind == QV_RY) {
+        const R cr = mat.re[0], sr = -mat.re[2];
+        WITH_K(RB, op.k0, (adj_real<K>(a, l, cr, sr, train, ip)));
+        return ip;
+    }
+    if (kind == QV_RZ || kind == QV_Z || kind == QV_S || kind == QV_T) {
+        const R d0r = mat.re[0], d1r = mat.re[3], d0i = -mat.im[0], d1i = -mat.im[3];
+        if (op.k0 >= 0) {
+            WITH_K(RB, op.k0, (adj_diag<K>(a, l, kind, d0r, d0i, d1r, d1i, train, ip)));
+        } else {
+            const bool b = (Et >> op.p0) & 1u;
+            if (train) ip = t_inner_z(a, l, (int)b);
+            t_scale(a, b ? d1r : d0r, b ? d1i : d0i);
+            t_scale(l, b ? d1r : d0r, b ? d1i : d0i);
+        }
+        return ip;
+    }
+    const M2<R> m = dagger_r(mat);
+    WITH_K(RB, op.k0, (adj_gen<K>(a, l, kind, m, train, ip)));
+    return ip;
+}
+
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // A fused 4-qubit block on the 16 register amplitudes of every lane, as one wave-wide real GEMM on MFMA:
@@ -719,15 +797,7 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             }
             if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
             if (ADJ) {
-                // Im <l| G |a> before the op is undone; one register-bit dispatch per vector keeps each
-                // vector's registers in place through the branches
-                double ip = 0.0;
-                if (op.flags & OP_TRAIN) {
-                    if (op.k0 < 0) ip = t_inner_z(av, lv, (int)((Et >> op.p0) & 1u));
-                    else WITH_K(RB, op.k0, (ip = r_inner<K>(kind, av, lv)));
-                }
-                rop_apply<true, RB, R>(av, op, kind, mat, Et);
-                rop_apply<true, RB, R>(lv, op, kind, mat, Et);
+                double ip = rop_adjoint<RB, R>(av, lv, op, kind, mat, Et);
                 if (op.flags & OP_TRAIN) {
                     if (!active) ip = 0.0;
                     ip = wave_sum_to_63(ip);
