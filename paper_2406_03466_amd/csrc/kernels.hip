@@ -226,16 +226,6 @@ __device__ __forceinline__ M2<R> dagger_r(const M2<R> &m)
     return o;
 }
 
-// Im <lambda| G |psi> on one amplitude pair in the state's own precision (the caller accumulates in FP64).
-template <typename R>
-__device__ __forceinline__ R gen_inner_r(int kind, Cx<R> a0, Cx<R> a1, Cx<R> l0, Cx<R> l1)
-{
-    if (kind == QV_RX)
-        return (l0.re * a1.im - l0.im * a1.re) + (l1.re * a0.im - l1.im * a0.re);
-    if (kind == QV_RY)
-        return -(l0.re * a1.re + l0.im * a1.im) + (l1.re * a0.re + l1.im * a0.im);
-    return (l0.re * a0.im - l0.im * a0.re) - (l1.re * a1.im - l1.im * a1.re);
-}
 
 // ------------------------------------------------------------------------------------------------------
 // LDS tile pass. One workgroup owns one tile: the 2^t amplitudes whose non-local bits equal the tile's
@@ -486,32 +476,44 @@ __device__ __forceinline__ void neg_mask(Regs<R, N> &v, uint32_t m)
     }
 }
 
-// Im <l| G |a> over the register pairs of bit K, G the generator of the rotation kind: per pair in R
-// precision, summed in FP64.
-template <int K, int N, typename R>
-__device__ __forceinline__ double r_inner(int kind, const Regs<R, N> &a, const Regs<R, N> &l)
+// Im <l| G |a> over the register pairs of bit K, G the generator of rotation kind GEN (RX: X, RY: Y, RZ: Z):
+// a thread's products are summed in R precision (two interleaved accumulators), the result in FP64.
+template <int K, int GEN, int N, typename R>
+__device__ __forceinline__ double r_inner(const Regs<R, N> &a, const Regs<R, N> &l)
 {
-    double acc = 0.0;
+    R acc[2] = {(R)0, (R)0};
 #pragma unroll
-    for (int j = 0; j < N; j++) {
+    for (int j = 0, n = 0; j < N; j++) {
         if (j & (1 << K)) continue;
         const int j1 = j | (1 << K);
-        acc += (double)gen_inner_r<R>(kind, a.get(j), a.get(j1), l.get(j), l.get(j1));
+        const Cx<R> a0 = a.get(j), a1 = a.get(j1), l0 = l.get(j), l1 = l.get(j1);
+        R &s = acc[n++ & 1];
+        if constexpr (GEN == QV_RX) {
+            // conj(l0) (-i a1) + conj(l1) (-i a0)
+            s += l0.re * a1.im - l0.im * a1.re + l1.re * a0.im - l1.im * a0.re;
+        } else if constexpr (GEN == QV_RY) {
+            // conj(l0) (-i a1) + conj(l1) (i a0)
+            s += l1.re * a0.re + l1.im * a0.im - l0.re * a1.re - l0.im * a1.im;
+        } else {
+            // conj(l0) a0 - conj(l1) a1
+            s += l0.re * a0.im - l0.im * a0.re - l1.re * a1.im + l1.im * a1.re;
+        }
     }
-    return acc;
+    return (double)acc[0] + (double)acc[1];
 }
 
 // Im <l| Z_p |a> when qubit p is a thread bit with value `bit`.
 template <int N, typename R>
 __device__ __forceinline__ double t_inner_z(const Regs<R, N> &a, const Regs<R, N> &l, int bit)
 {
-    double acc = 0.0;
+    R acc[2] = {(R)0, (R)0};
 #pragma unroll
     for (int j = 0; j < N; j++) {
         const Cx<R> x = a.get(j), y = l.get(j);
-        acc += (double)(y.re * x.im - y.im * x.re);
+        acc[j & 1] += y.re * x.im - y.im * x.re;
     }
-    return bit ? -acc : acc;
+    const double t = (double)acc[0] + (double)acc[1];
+    return bit ? -t : t;
 }
 
 // One op applied to the registers v (the inverse when INV).
@@ -561,7 +563,7 @@ __device__ __forceinline__ void rop_apply(Regs<R, 1 << RB> &v, const DevOp &op, 
 template <int K, int N, typename R>
 __device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s, bool train, double &ip)
 {
-    if (train) ip = r_inner<K>(QV_RY, a, l);
+    if (train) ip = r_inner<K, QV_RY>(a, l);
     r_real<K>(a, c, s);
     r_real<K>(l, c, s);
 }
@@ -570,7 +572,8 @@ template <int K, int N, typename R>
 __device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, int kind, R d0r, R d0i, R d1r, R d1i,
                                          bool train, double &ip)
 {
-    if (train) ip = r_inner<K>(kind, a, l);
+    // of the diagonal kinds only RZ carries a parameter
+    if (train) ip = r_inner<K, QV_RZ>(a, l);
     r_diag<K>(a, d0r, d0i, d1r, d1i);
     r_diag<K>(l, d0r, d0i, d1r, d1i);
 }
@@ -579,7 +582,8 @@ template <int K, int N, typename R>
 __device__ __forceinline__ void adj_gen(Regs<R, N> &a, Regs<R, N> &l, int kind, const M2<R> &m, bool train,
                                         double &ip)
 {
-    if (train) ip = r_inner<K>(kind, a, l);
+    // of the dense kinds only RX carries a parameter
+    if (train) ip = r_inner<K, QV_RX>(a, l);
     r_gen<K>(a, m);
     r_gen<K>(l, m);
 }
