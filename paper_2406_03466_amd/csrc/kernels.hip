@@ -669,6 +669,73 @@ __device__ __forceinline__ void fused_mfma(Regs<float, 16> &v, const float *__re
     }
 }
 
+// Position in a register segment's op list: index k of n, the op record and matrix of op k already
+// loaded (one op ahead), and its global index oi.
+template <typename R>
+struct OpCursor {
+    int k, n;
+    int64_t oi;
+    DevOp op;
+    M2<R> mat;
+};
+
+// One step of a register segment: the next op (or fused block) applied to (ai, li), result in (ao, lo).
+template <typename R, bool ADJ, int RB, int NT>
+__device__ __forceinline__ void seg_step(const LevelArgs &a, const DevCirc &C, const M2<R> *mtab, OpCursor<R> &oc,
+                                         uint32_t Et, bool active, int lane, int wave, double *red,
+                                         const Regs<R, 1 << RB> &ai, const Regs<R, 1 << RB> &li,
+                                         Regs<R, 1 << RB> &ao, Regs<R, 1 << RB> &lo)
+{
+    DevOp op = oc.op;
+    M2<R> mat = oc.mat;
+    int64_t cur = oc.oi;
+    auto advance = [&](int by, int64_t to) {
+        oc.k += by;
+        if (oc.k < oc.n) {
+            oc.oi = to;
+            oc.op = ldu(a.ops + to);
+            oc.mat = ldu(mtab + to);
+        }
+    };
+    advance(1, cur + (ADJ ? -1 : 1));
+    if (op.kind == kFusedKind) {
+        // A fused block: forward applies its product on MFMA and skips its gates; the adjoint (which needs
+        // the state at every trainable gate), complex128 and a block holding a shifted gate run the gates.
+        if constexpr (!ADJ && RB == 4 && sizeof(R) == 4) {
+            const int m = op.pad;
+            bool shifted = false;
+            if (C.shift_gate >= 0)
+                for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
+            if (!shifted) {
+                const int f = op.p0 | (op.p1 << 8);
+                ao = ai;
+                fused_mfma(ao, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
+                advance(m, cur + m + 1);
+                return;
+            }
+        }
+        // a marker is always followed by its gates in the same segment: take the first of them
+        op = oc.op;
+        mat = oc.mat;
+        cur = oc.oi;
+        advance(1, cur + (ADJ ? -1 : 1));
+    }
+    const int kind = op.kind;
+    if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
+    ao = ai;
+    if (ADJ) {
+        lo = li;
+        double ip = rop_adjoint<RB, R>(ao, lo, op, kind, mat, Et);
+        if (op.flags & OP_TRAIN) {
+            if (!active) ip = 0.0;
+            ip = wave_sum_to_63(ip);
+            if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
+        }
+    } else {
+        rop_apply<false, RB, R>(ao, op, kind, mat, Et);
+    }
+}
+
 // Amplitudes each thread moves between HBM and LDS per batch of independent loads (or stores).
 template <typename R>
 constexpr int tile_batch() { return sizeof(R) == 4 ? 8 : 4; }
@@ -765,51 +832,23 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
         }
         // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
         const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.mat_off - C.op_base);
-        int64_t oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
-        DevOp nop = ldu(a.ops + oi);
-        M2<R> nmat = ldu(mtab + oi);
-        for (int k0 = 0; k0 < S.n_ops; k0++) {
-            const DevOp op = nop;
-            M2<R> mat = nmat;
-            const int64_t cur = oi;
-            if (k0 + 1 < S.n_ops) {
-                oi += ADJ ? -1 : 1;
-                nop = ldu(a.ops + oi);
-                nmat = ldu(mtab + oi);
+        OpCursor<R> oc;
+        oc.k = 0;
+        oc.n = S.n_ops;
+        oc.oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
+        oc.op = ldu(a.ops + oc.oi);
+        oc.mat = ldu(mtab + oc.oi);
+        // Steps alternate between two register sets (av -> aw, aw -> av), so no step has to leave its result
+        // in the registers it read from and the branches of a step need no copies to agree.
+        Regs<R, N> aw, lw;
+        while (oc.k < oc.n) {
+            seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
+            if (oc.k >= oc.n) {
+                av = aw;
+                if (ADJ) lv = lw;
+                break;
             }
-            const int kind = op.kind;
-            if (kind == kFusedKind) {
-                // A fused block: forward applies its product on MFMA and skips its gates; the adjoint (which
-                // needs the state at every trainable gate) and complex128 run the gates one by one.
-                if constexpr (!ADJ && RB == 4 && sizeof(R) == 4) {
-                    const int m = op.pad;
-                    bool shifted = false;
-                    if (C.shift_gate >= 0)
-                        for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
-                    if (!shifted) {
-                        const int f = op.p0 | (op.p1 << 8);
-                        fused_mfma(av, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
-                        k0 += m;
-                        if (k0 + 1 < S.n_ops) {
-                            oi = cur + m + 1;
-                            nop = ldu(a.ops + oi);
-                            nmat = ldu(mtab + oi);
-                        }
-                    }
-                }
-                continue;
-            }
-            if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
-            if (ADJ) {
-                double ip = rop_adjoint<RB, R>(av, lv, op, kind, mat, Et);
-                if (op.flags & OP_TRAIN) {
-                    if (!active) ip = 0.0;
-                    ip = wave_sum_to_63(ip);
-                    if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
-                }
-            } else {
-                rop_apply<false, RB, R>(av, op, kind, mat, Et);
-            }
+            seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
         }
         if (active) {
             // recompute the addresses rather than keep 2^RB of them live through the op loop
