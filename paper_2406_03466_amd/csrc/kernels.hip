@@ -838,17 +838,23 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
         oc.oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
         oc.op = ldu(a.ops + oc.oi);
         oc.mat = ldu(mtab + oc.oi);
-        // Steps alternate between two register sets (av -> aw, aw -> av), so no step has to leave its result
-        // in the registers it read from and the branches of a step need no copies to agree.
-        Regs<R, N> aw, lw;
-        while (oc.k < oc.n) {
-            seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
-            if (oc.k >= oc.n) {
-                av = aw;
-                if (ADJ) lv = lw;
-                break;
+        if constexpr (ADJ) {
+            // Adjoint steps alternate between two register sets (av -> aw, aw -> av), so no step has to leave
+            // its result in the registers it read from and the branches of a step need no copies to agree.
+            Regs<R, N> aw, lw;
+            while (oc.k < oc.n) {
+                seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
+                if (oc.k >= oc.n) {
+                    av = aw;
+                    lv = lw;
+                    break;
+                }
+                seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
             }
-            seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
+        } else {
+            // forward steps update one register set in place (within the 128-register budget of two
+            // workgroups per CU)
+            while (oc.k < oc.n) seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, av, lv);
         }
         if (active) {
             // recompute the addresses rather than keep 2^RB of them live through the op loop
