@@ -852,9 +852,45 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                 seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
             }
         } else {
-            // forward steps update one register set in place (within the 128-register budget of two
+            // forward ops update one register set in place (within the 128-register budget of two
             // workgroups per CU)
-            while (oc.k < oc.n) seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, av, lv);
+            int64_t oi = oc.oi;
+            DevOp nop = oc.op;
+            M2<R> nmat = oc.mat;
+            for (int k0 = 0; k0 < S.n_ops; k0++) {
+                const DevOp op = nop;
+                M2<R> mat = nmat;
+                const int64_t cur = oi;
+                if (k0 + 1 < S.n_ops) {
+                    oi += 1;
+                    nop = ldu(a.ops + oi);
+                    nmat = ldu(mtab + oi);
+                }
+                const int kind = op.kind;
+                if (kind == kFusedKind) {
+                    // A fused block: its product on MFMA, its gates skipped (complex128, and a block that holds
+                    // a parameter-shift variant's shifted gate, run the gates one by one).
+                    if constexpr (RB == 4 && sizeof(R) == 4) {
+                        const int m = op.pad;
+                        bool shifted = false;
+                        if (C.shift_gate >= 0)
+                            for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
+                        if (!shifted) {
+                            const int f = op.p0 | (op.p1 << 8);
+                            fused_mfma(av, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
+                            k0 += m;
+                            if (k0 + 1 < S.n_ops) {
+                                oi = cur + m + 1;
+                                nop = ldu(a.ops + oi);
+                                nmat = ldu(mtab + oi);
+                            }
+                        }
+                    }
+                    continue;
+                }
+                if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
+                rop_apply<false, RB, R>(av, op, kind, mat, Et);
+            }
         }
         if (active) {
             // recompute the addresses rather than keep 2^RB of them live through the op loop
