@@ -141,8 +141,6 @@ def main():
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
     ap.add_argument("--launch", default="levels", choices=["levels", "persistent"])
-    ap.add_argument("--diagonal-runs", default="on", choices=["on", "off"],
-                    help="apply runs of diagonal gates as one diagonal")
     ap.add_argument("--fusion", default="8",
                     help='fused 4-qubit MFMA blocks in forward passes: "off", "on" or a minimum run length')
     ap.add_argument("--copy-calibration", action="store_true",
@@ -172,7 +170,7 @@ def main():
     wl = W.config3(args.layers)
     stream = torch.cuda.current_stream(dev)
     opts = {"graph": False, "launch_events": True, "engine": args.engine, "launch": args.launch,
-            "fusion": args.fusion, "diagonal_runs": args.diagonal_runs}
+            "fusion": args.fusion}
     if args.tile_qubits:
         opts["tile_qubits"] = args.tile_qubits
     if args.contig:
@@ -245,8 +243,7 @@ def main():
     extra = {}
     if not args.no_ps:
         # parameter-shift gradient through the same batched tiled engine, measured in full
-        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False, "fusion": args.fusion,
-                                                                "diagonal_runs": args.diagonal_runs}))
+        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False, "fusion": args.fusion}))
         b_ps = qvpu.Batch(ctx_ps, wl, qvpu.QV_C64)
         with torch.no_grad():
             f = expectation(theta.detach(), batch)
@@ -307,7 +304,7 @@ def main():
                    "precision": "c64", "engine": args.engine, "tile_qubits": tuned["tile_qubits"],
                    "contig_qubits": tuned["contig_qubits"], "passes": tuned["passes_per_circuit_max"],
                    "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch,
-                   "fusion": args.fusion, "diagonal_runs": args.diagonal_runs},
+                   "fusion": args.fusion},
         "roofline": roofline,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1),

@@ -134,9 +134,6 @@ typedef struct qv_batch_s *qv_batch;
  *   "launch"         : "levels" (one launch per pass level, default). "persistent" (all levels of a
  *                      sweep in one launch, resident workgroups taking tiles from a queue in level order)
  *                      is disabled in this version and returns QV_E_UNSUPPORTED;
- *   "diagonal_runs"  : "on" (default) or "off": within a register segment, single-qubit diagonal gates
- *                      (Z, S, T, RZ) are moved next to each other where no gate in between shares their
- *                      qubit, and each run of two or more is applied as one diagonal;
  *   "fusion"         : "off" (default), "on" (runs of >= 6 gates) or a minimum run length: within a
  *                      register segment, consecutive gates acting only on its 4 register qubits are
  *                      multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);

@@ -695,8 +695,10 @@ __device__ __forceinline__ void diag_mul_reg(DiagRun<R, RB> &d, R d0r, R d0i, R 
     d.used |= 1u << K;
 }
 
-template <int RB, typename R>
-__device__ __forceinline__ void diag_init(DiagRun<R, RB> &d)
+// Multiplies the m gates first.. of a run into d (their inverses when INV).
+template <bool INV, int RB, typename R>
+__device__ __forceinline__ void diag_collect(DiagRun<R, RB> &d, const LevelArgs &a, const DevCirc &C,
+                                             const M2<R> *mtab, int64_t first, int m, uint32_t Et)
 {
 #pragma unroll
     for (int k = 0; k < RB; k++) {
@@ -707,41 +709,20 @@ __device__ __forceinline__ void diag_init(DiagRun<R, RB> &d)
     d.ti = (R)0;
     d.used = 0;
     d.any_t = false;
-}
-
-// Multiplies one gate of a run into d (its inverse when INV).
-template <bool INV, int RB, typename R>
-__device__ __forceinline__ void diag_gate(DiagRun<R, RB> &d, const DevOp &g, const M2<R> &mat, uint32_t Et)
-{
-    const R d0r = mat.re[0], d1r = mat.re[3];
-    const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
-    if (g.k0 >= 0) {
-        WITH_K(RB, g.k0, (diag_mul_reg<K, RB, R>(d, d0r, d0i, d1r, d1i)));
-    } else {
-        const bool b = (Et >> g.p0) & 1u;
-        cmul_into(d.tr, d.ti, b ? d1r : d0r, b ? d1i : d0i);
-        d.any_t = true;
-    }
-}
-
-// Multiplies the m gates first.. of a run into d (their inverses when INV); records and matrices are
-// loaded one gate ahead.
-template <bool INV, int RB, typename R>
-__device__ __forceinline__ void diag_collect(DiagRun<R, RB> &d, const LevelArgs &a, const DevCirc &C,
-                                             const M2<R> *mtab, int64_t first, int m, uint32_t Et)
-{
-    diag_init(d);
-    DevOp g = ldu(a.ops + first);
-    M2<R> mat = ldu(mtab + first);
     for (int j = 0; j < m; j++) {
-        const DevOp gc = g;
-        M2<R> mc = mat;
-        if (j + 1 < m) {
-            g = ldu(a.ops + first + j + 1);
-            mat = ldu(mtab + first + j + 1);
+        const int64_t oi = first + j;
+        const DevOp g = ldu(a.ops + oi);
+        M2<R> mat = ldu(mtab + oi);
+        if (g.gate == C.shift_gate) mat = op_matrix<R>(a, C, g, oi);
+        const R d0r = mat.re[0], d1r = mat.re[3];
+        const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
+        if (g.k0 >= 0) {
+            WITH_K(RB, g.k0, (diag_mul_reg<K, RB, R>(d, d0r, d0i, d1r, d1i)));
+        } else {
+            const bool b = (Et >> g.p0) & 1u;
+            cmul_into(d.tr, d.ti, b ? d1r : d0r, b ? d1i : d0i);
+            d.any_t = true;
         }
-        if (gc.gate == C.shift_gate) mc = op_matrix<R>(a, C, gc, first + j);
-        diag_gate<INV, RB, R>(d, gc, mc, Et);
     }
 }
 
@@ -767,13 +748,13 @@ __device__ __forceinline__ R signed_sum(const R (&p)[N])
     return s0 + s1;
 }
 
-// Adjoint of a run: partial sums of its trainable gates (all RZ), then the inverse of the run's product
-// on psi and lambda. Diagonal gates commute and scale psi and lambda alike, so Im(conj(lambda_b) psi_b) is
-// the same at every gate of the run: with p_b that value, Im <lambda| Z_q |psi> = sum_b (-1)^{b_q} p_b.
+// Adjoint partial sums of a run's trainable gates (all RZ). Diagonal gates commute and scale psi and
+// lambda alike, so Im(conj(lambda_b) psi_b) is the same at every gate of the run: with p_b that value,
+// Im <lambda| Z_q |psi> = sum_b (-1)^{b_q} p_b for each gate's qubit q.
 template <int RB, int NT, typename R>
-__device__ __forceinline__ void diag_adjoint(Regs<R, 1 << RB> &av, Regs<R, 1 << RB> &lv, const LevelArgs &a,
-                                             const DevCirc &C, const M2<R> *mtab, int64_t first, int m,
-                                             uint32_t Et, bool active, int lane, int wave, double *red)
+__device__ __forceinline__ void diag_grads(const Regs<R, 1 << RB> &av, const Regs<R, 1 << RB> &lv,
+                                           const LevelArgs &a, int64_t first, int m, uint32_t Et, bool active,
+                                           int lane, int wave, double *red)
 {
     constexpr int N = 1 << RB;
     R p[N];
@@ -789,33 +770,19 @@ __device__ __forceinline__ void diag_adjoint(Regs<R, 1 << RB> &av, Regs<R, 1 << 
         sodd += p[j + 1];
     }
     sall += sodd;
-    DiagRun<R, RB> d;
-    diag_init(d);
-    DevOp g = ldu(a.ops + first);
-    M2<R> mat = ldu(mtab + first);
     for (int j = 0; j < m; j++) {
-        const DevOp gc = g;
-        M2<R> mc = mat;
-        if (j + 1 < m) {
-            g = ldu(a.ops + first + j + 1);
-            mat = ldu(mtab + first + j + 1);
+        const DevOp g = ldu(a.ops + first + j);
+        if (!(g.flags & OP_TRAIN)) continue;
+        R s = (R)0;
+        if (g.k0 >= 0) {
+            WITH_K(RB, g.k0, (s = signed_sum<K, N, R>(p)));
+        } else {
+            s = ((Et >> g.p0) & 1u) ? -sall : sall;
         }
-        if (gc.gate == C.shift_gate) mc = op_matrix<R>(a, C, gc, first + j);
-        diag_gate<true, RB, R>(d, gc, mc, Et);
-        if (gc.flags & OP_TRAIN) {
-            R s = (R)0;
-            if (gc.k0 >= 0) {
-                WITH_K(RB, gc.k0, (s = signed_sum<K, N, R>(p)));
-            } else {
-                s = ((Et >> gc.p0) & 1u) ? -sall : sall;
-            }
-            double ip = active ? (double)s : 0.0;
-            ip = wave_sum_to_63(ip);
-            if (lane == 63) red[gc.train_slot * (NT / 64) + wave] = ip;
-        }
+        double ip = active ? (double)s : 0.0;
+        ip = wave_sum_to_63(ip);
+        if (lane == 63) red[g.train_slot * (NT / 64) + wave] = ip;
     }
-    diag_apply<RB, R>(av, d);
-    diag_apply<RB, R>(lv, d);
 }
 
 // Position in a register segment's op list: index k of n, the op record and matrix of op k already
@@ -857,7 +824,11 @@ __device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, c
     if (op.kind == kDiagKind) {
         // the marker behind a run: its gates are cur - m .. cur - 1, the marker in front is cur - m - 1
         const int m = op.pad;
-        diag_adjoint<RB, NT, R>(ao, lo, a, C, mtab, cur - m, m, Et, active, lane, wave, red);
+        diag_grads<RB, NT, R>(ao, lo, a, cur - m, m, Et, active, lane, wave, red);
+        DiagRun<R, RB> d;
+        diag_collect<true, RB, R>(d, a, C, mtab, cur - m, m, Et);
+        diag_apply<RB, R>(ao, d);
+        diag_apply<RB, R>(lo, d);
         advance(m + 2, cur - m - 2);
         return;
     }

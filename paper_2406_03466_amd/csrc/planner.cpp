@@ -112,7 +112,7 @@ void segment_pass(PlanPass &pp, int reg_bits)
     number_train_slots(pp);
 }
 
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, int fuse_min, bool diag_runs)
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, int fuse_min)
 {
     Plan pl;
     const int n = in.n;
@@ -198,7 +198,7 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, in
         pp.local_mask = L;
         finish_pass(pp, n);
         segment_pass(pp, reg_bits);
-        if (diag_runs) group_diagonals(pp);
+        group_diagonals(pp);
         pl.passes.push_back(pp);
     }
     if (fuse_min > 0) fuse_segments(pl, fuse_min);

@@ -57,9 +57,7 @@ constexpr int kMaxTrainPerPass = 256;
 // amplitudes per thread.
 // fuse_min > 0 turns every run of at least fuse_min consecutive gates of a segment that act on register
 // qubits only into a fused block (a marker op followed by the run).
-// diag_runs groups diagonal gates into runs inside register segments (group_diagonals).
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0, int fuse_min = 0,
-                bool diag_runs = true);
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0, int fuse_min = 0);
 
 // Within each register segment, moves single-qubit diagonal gates (Z, S, T, RZ) next to the previous such
 // gate when no gate in between touches their qubit, and brackets every run of two or more with markers.

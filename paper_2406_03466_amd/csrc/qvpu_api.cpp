@@ -119,7 +119,6 @@ struct qv_ctx_s {
     int autotune = 1;           // 0 off, 1 cached (use a stored choice), 2 search (time candidates once)
     int persistent = 0;         // 1: one persistent work-queue launch per direction instead of one per level
     int fuse_min = 0;           // >0: fuse runs of at least this many register-local gates into MFMA blocks
-    int diag_runs = 1;          // group diagonal gates into runs applied as one diagonal
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
@@ -930,10 +929,6 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             else if (v == "cached") c->autotune = 1;
             else if (v == "search") c->autotune = 2;
             else return fail(QV_E_INVALID, "autotune must be \"off\", \"cached\" or \"search\"");
-        } else if (k == "diagonal_runs") {
-            if (v == "on" || v == "1" || v == "true") c->diag_runs = 1;
-            else if (v == "off" || v == "0" || v == "false") c->diag_runs = 0;
-            else return fail(QV_E_INVALID, "diagonal_runs must be \"on\" or \"off\"");
         } else if (k == "fusion") {
             if (v == "off" || v == "0") c->fuse_min = 0;
             else if (v == "on") c->fuse_min = 6;
@@ -1060,7 +1055,7 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
         const int lowc = bt->contig;
         const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
         const int fm = (ctx->engine == 0) ? ctx->fuse_min : 0;
-        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb, fm, ctx->diag_runs != 0));
+        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb, fm));
     }
     // device plan arrays
     auto dp = std::make_unique<DevPlans>();
