@@ -230,7 +230,7 @@ typedef struct {
     int32_t first_gate;   /* circuit index of the pass's first gate in execution order */
     int32_t contiguous_low; /* qubits 0..contiguous_low-1 are all local (length of contiguous runs) */
     int32_t n_fused;      /* fused blocks among the pass's gates */
-    int32_t n_diag_runs;  /* runs of two or more diagonal gates applied as one diagonal */
+    int32_t pad;
 } qv_pass_info;
 
 /* Plans one circuit without a device, as qv_batch_create would for a batch with the given engine

@@ -76,8 +76,6 @@ struct DevCirc {
 };
 
 constexpr int kFusedKind = 100;      // op kind of a fused-block marker (its gates follow it)
-constexpr int kDiagKind = 101;       // op kind of a diagonal-run marker: one before and one after the run's gates
-                                     // (pad = number of gates, p0 = 0 before / 1 after)
 constexpr int kFusedFloats = 1024;   // one fused 4-qubit block: the 32x32 real form of a 16x16 complex matrix
 
 // One (circuit, pass) of a level launch; blocks [first_block, next segment's first_block) run it.

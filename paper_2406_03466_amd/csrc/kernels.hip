@@ -669,122 +669,6 @@ __device__ __forceinline__ void fused_mfma(Regs<float, 16> &v, const float *__re
     }
 }
 
-// A run of diagonal gates acts as one diagonal: per register bit k the product diag(e0[k], e1[k]) of the
-// run's gates on that bit (the same in every thread), and per thread one phase for the gates on thread bits.
-template <typename R, int RB>
-struct DiagRun {
-    R e0r[RB], e0i[RB], e1r[RB], e1i[RB];
-    R tr, ti;
-    uint32_t used;  // register bits that carry gates of the run
-    bool any_t;     // gates on thread bits
-};
-
-template <typename R>
-__device__ __forceinline__ void cmul_into(R &xr, R &xi, R yr, R yi)
-{
-    const R r = xr * yr - xi * yi, i = xr * yi + xi * yr;
-    xr = r;
-    xi = i;
-}
-
-template <int K, int RB, typename R>
-__device__ __forceinline__ void diag_mul_reg(DiagRun<R, RB> &d, R d0r, R d0i, R d1r, R d1i)
-{
-    cmul_into(d.e0r[K], d.e0i[K], d0r, d0i);
-    cmul_into(d.e1r[K], d.e1i[K], d1r, d1i);
-    d.used |= 1u << K;
-}
-
-// Multiplies the m gates first.. of a run into d (their inverses when INV).
-template <bool INV, int RB, typename R>
-__device__ __forceinline__ void diag_collect(DiagRun<R, RB> &d, const LevelArgs &a, const DevCirc &C,
-                                             const M2<R> *mtab, int64_t first, int m, uint32_t Et)
-{
-#pragma unroll
-    for (int k = 0; k < RB; k++) {
-        d.e0r[k] = d.e1r[k] = (R)1;
-        d.e0i[k] = d.e1i[k] = (R)0;
-    }
-    d.tr = (R)1;
-    d.ti = (R)0;
-    d.used = 0;
-    d.any_t = false;
-    for (int j = 0; j < m; j++) {
-        const int64_t oi = first + j;
-        const DevOp g = ldu(a.ops + oi);
-        M2<R> mat = ldu(mtab + oi);
-        if (g.gate == C.shift_gate) mat = op_matrix<R>(a, C, g, oi);
-        const R d0r = mat.re[0], d1r = mat.re[3];
-        const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
-        if (g.k0 >= 0) {
-            WITH_K(RB, g.k0, (diag_mul_reg<K, RB, R>(d, d0r, d0i, d1r, d1i)));
-        } else {
-            const bool b = (Et >> g.p0) & 1u;
-            cmul_into(d.tr, d.ti, b ? d1r : d0r, b ? d1i : d0i);
-            d.any_t = true;
-        }
-    }
-}
-
-template <int RB, typename R>
-__device__ __forceinline__ void diag_apply(Regs<R, 1 << RB> &v, const DiagRun<R, RB> &d)
-{
-    if (d.used & 1u) r_diag<0>(v, d.e0r[0], d.e0i[0], d.e1r[0], d.e1i[0]);
-    if constexpr (RB > 1) if (d.used & 2u) r_diag<1>(v, d.e0r[1], d.e0i[1], d.e1r[1], d.e1i[1]);
-    if constexpr (RB > 2) if (d.used & 4u) r_diag<2>(v, d.e0r[2], d.e0i[2], d.e1r[2], d.e1i[2]);
-    if constexpr (RB > 3) if (d.used & 8u) r_diag<3>(v, d.e0r[3], d.e0i[3], d.e1r[3], d.e1i[3]);
-    if (d.any_t) t_scale(v, d.tr, d.ti);
-}
-
-template <int K, int N, typename R>
-__device__ __forceinline__ R signed_sum(const R (&p)[N])
-{
-    R s0 = (R)0, s1 = (R)0;
-#pragma unroll
-    for (int j = 0; j < N; j += 2) {
-        s0 += ((j >> K) & 1) ? -p[j] : p[j];
-        s1 += (((j + 1) >> K) & 1) ? -p[j + 1] : p[j + 1];
-    }
-    return s0 + s1;
-}
-
-// Adjoint partial sums of a run's trainable gates (all RZ). Diagonal gates commute and scale psi and
-// lambda alike, so Im(conj(lambda_b) psi_b) is the same at every gate of the run: with p_b that value,
-// Im <lambda| Z_q |psi> = sum_b (-1)^{b_q} p_b for each gate's qubit q.
-template <int RB, int NT, typename R>
-__device__ __forceinline__ void diag_grads(const Regs<R, 1 << RB> &av, const Regs<R, 1 << RB> &lv,
-                                           const LevelArgs &a, int64_t first, int m, uint32_t Et, bool active,
-                                           int lane, int wave, double *red)
-{
-    constexpr int N = 1 << RB;
-    R p[N];
-#pragma unroll
-    for (int j = 0; j < N; j++) {
-        const Cx<R> x = av.get(j), y = lv.get(j);
-        p[j] = y.re * x.im - y.im * x.re;
-    }
-    R sall = (R)0, sodd = (R)0;
-#pragma unroll
-    for (int j = 0; j < N; j += 2) {
-        sall += p[j];
-        sodd += p[j + 1];
-    }
-    sall += sodd;
-    for (int j = 0; j < m; j++) {
-        const DevOp g = ldu(a.ops + first + j);
-        if (!(g.flags & OP_TRAIN)) continue;
-        R s = (R)0;
-        if (g.k0 >= 0) {
-            WITH_K(RB, g.k0, (s = signed_sum<K, N, R>(p)));
-        } else {
-            s = ((Et >> g.p0) & 1u) ? -sall : sall;
-        }
-        double ip = active ? (double)s : 0.0;
-        ip = wave_sum_to_63(ip);
-        if (lane == 63) red[g.train_slot * (NT / 64) + wave] = ip;
-    }
-}
-
 // Position in a register segment's op list: index k of n, the op record and matrix of op k already
 // loaded (one op ahead), and its global index oi.
 template <typename R>
@@ -795,14 +679,16 @@ struct OpCursor {
     M2<R> mat;
 };
 
-// One adjoint step of a register segment, walking the ops backwards: the next op (or diagonal run) undone
-// on (ai, li) with its partial sums, result in (ao, lo).
-template <typename R, int RB, int NT>
-__device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, const M2<R> *mtab, OpCursor<R> &oc,
+// One step of a register segment: the next op (or fused block) applied to (ai, li), result in (ao, lo).
+template <typename R, bool ADJ, int RB, int NT>
+__device__ __forceinline__ void seg_step(const LevelArgs &a, const DevCirc &C, const M2<R> *mtab, OpCursor<R> &oc,
                                          uint32_t Et, bool active, int lane, int wave, double *red,
                                          const Regs<R, 1 << RB> &ai, const Regs<R, 1 << RB> &li,
                                          Regs<R, 1 << RB> &ao, Regs<R, 1 << RB> &lo)
 {
+    DevOp op = oc.op;
+    M2<R> mat = oc.mat;
+    int64_t cur = oc.oi;
     auto advance = [&](int by, int64_t to) {
         oc.k += by;
         if (oc.k < oc.n) {
@@ -811,35 +697,42 @@ __device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, c
             oc.mat = ldu(mtab + to);
         }
     };
-    ao = ai;
-    lo = li;
-    // fused-block markers and the markers in front of diagonal runs carry no adjoint work (the gates of a
-    // fused block are undone one by one; a diagonal run is handled at the marker behind it)
-    while (oc.k < oc.n && (oc.op.kind == kFusedKind || (oc.op.kind == kDiagKind && oc.op.p0 == 0)))
-        advance(1, oc.oi - 1);
-    if (oc.k >= oc.n) return;
-    const DevOp op = oc.op;
-    M2<R> mat = oc.mat;
-    const int64_t cur = oc.oi;
-    if (op.kind == kDiagKind) {
-        // the marker behind a run: its gates are cur - m .. cur - 1, the marker in front is cur - m - 1
-        const int m = op.pad;
-        diag_grads<RB, NT, R>(ao, lo, a, cur - m, m, Et, active, lane, wave, red);
-        DiagRun<R, RB> d;
-        diag_collect<true, RB, R>(d, a, C, mtab, cur - m, m, Et);
-        diag_apply<RB, R>(ao, d);
-        diag_apply<RB, R>(lo, d);
-        advance(m + 2, cur - m - 2);
-        return;
+    advance(1, cur + (ADJ ? -1 : 1));
+    if (op.kind == kFusedKind) {
+        // A fused block: forward applies its product on MFMA and skips its gates; the adjoint (which needs
+        // the state at every trainable gate), complex128 and a block holding a shifted gate run the gates.
+        if constexpr (!ADJ && RB == 4 && sizeof(R) == 4) {
+            const int m = op.pad;
+            bool shifted = false;
+            if (C.shift_gate >= 0)
+                for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
+            if (!shifted) {
+                const int f = op.p0 | (op.p1 << 8);
+                ao = ai;
+                fused_mfma(ao, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
+                advance(m, cur + m + 1);
+                return;
+            }
+        }
+        // a marker is always followed by its gates in the same segment: take the first of them
+        op = oc.op;
+        mat = oc.mat;
+        cur = oc.oi;
+        advance(1, cur + (ADJ ? -1 : 1));
     }
-    advance(1, cur - 1);
     const int kind = op.kind;
     if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
-    double ip = rop_adjoint<RB, R>(ao, lo, op, kind, mat, Et);
-    if (op.flags & OP_TRAIN) {
-        if (!active) ip = 0.0;
-        ip = wave_sum_to_63(ip);
-        if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
+    ao = ai;
+    if (ADJ) {
+        lo = li;
+        double ip = rop_adjoint<RB, R>(ao, lo, op, kind, mat, Et);
+        if (op.flags & OP_TRAIN) {
+            if (!active) ip = 0.0;
+            ip = wave_sum_to_63(ip);
+            if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
+        }
+    } else {
+        rop_apply<false, RB, R>(ao, op, kind, mat, Et);
     }
 }
 
@@ -950,13 +843,13 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             // its result in the registers it read from and the branches of a step need no copies to agree.
             Regs<R, N> aw, lw;
             while (oc.k < oc.n) {
-                adj_step<R, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
+                seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
                 if (oc.k >= oc.n) {
                     av = aw;
                     lv = lw;
                     break;
                 }
-                adj_step<R, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
+                seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
             }
         } else {
             // forward ops update one register set in place (within the 128-register budget of two
@@ -991,22 +884,6 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                                 nop = ldu(a.ops + oi);
                                 nmat = ldu(mtab + oi);
                             }
-                        }
-                    }
-                    continue;
-                }
-                if (kind == kDiagKind) {
-                    // a diagonal run: the product of its gates at once (the marker behind a run does nothing)
-                    if (op.p0 == 0) {
-                        const int m = op.pad;
-                        DiagRun<R, RB> d;
-                        diag_collect<false, RB, R>(d, a, C, mtab, cur + 1, m, Et);
-                        diag_apply<RB, R>(av, d);
-                        k0 += m + 1;
-                        if (k0 + 1 < S.n_ops) {
-                            oi = cur + m + 2;
-                            nop = ldu(a.ops + oi);
-                            nmat = ldu(mtab + oi);
                         }
                     }
                     continue;
@@ -1228,7 +1105,7 @@ __global__ __launch_bounds__(kBlock) void k_matrices(MatArgs a)
     const DevCirc C = a.circs[a.gate_circ[i]];
     const DevOp op = a.ops[C.op_base + (i - C.mat_off)];
     M2d md;
-    if (op.kind >= kFusedKind) {
+    if (op.kind == kFusedKind) {
         gate_matrix(-1, 0.0, md);
         reinterpret_cast<M2<R> *>(a.mats)[i] = narrow<R>(md);
         return;
@@ -1263,7 +1140,6 @@ __global__ __launch_bounds__(256) void k_fuse(FuseArgs a)
     const M2<float> *mt = reinterpret_cast<const M2<float> *>(a.mats) + (C.mat_off - C.op_base);
     for (int j = 1; j <= m; j++) {
         const DevOp op = a.ops[mk + j];
-        if (op.kind >= kFusedKind) continue;  // diagonal-run markers inside the block
         float nr, ni;
         if (op.kind == QV_CNOT) {
             const int src = ((r >> op.k0) & 1) ? (r ^ (1 << op.k1)) : r;

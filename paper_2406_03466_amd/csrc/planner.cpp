@@ -19,13 +19,6 @@ static bool diagonal(int kind)
     return kind == QV_Z || kind == QV_S || kind == QV_T || kind == QV_RZ || kind == QV_CZ;
 }
 
-static bool diagonal1(int kind) { return kind == QV_Z || kind == QV_S || kind == QV_T || kind == QV_RZ; }
-
-static bool touches(const PlanOp &op, int q)
-{
-    return op.q0 == q || (two_qubit(op.kind) && op.q1 == q);
-}
-
 static void number_train_slots(PlanPass &pp)
 {
     int slot = 0;
@@ -198,65 +191,10 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, in
         pp.local_mask = L;
         finish_pass(pp, n);
         segment_pass(pp, reg_bits);
-        group_diagonals(pp);
         pl.passes.push_back(pp);
     }
     if (fuse_min > 0) fuse_segments(pl, fuse_min);
     return pl;
-}
-
-void group_diagonals(PlanPass &pp)
-{
-    if (pp.segs.empty()) return;
-    std::vector<PlanOp> out;
-    for (PlanSeg &sg : pp.segs) {
-        const int b = sg.op_begin, e = sg.op_begin + sg.n_ops;
-        std::vector<PlanOp> seg;
-        int run_end = -1;  // position just past the most recent diagonal run in seg
-        for (int i = b; i < e; i++) {
-            const PlanOp &op = pp.ops[i];
-            if (!diagonal1(op.kind)) {
-                seg.push_back(op);
-                continue;
-            }
-            bool join = run_end >= 0;
-            for (int k = run_end; join && k < (int)seg.size(); k++)
-                if (touches(seg[k], op.q0)) join = false;
-            if (join) {
-                seg.insert(seg.begin() + run_end, op);
-                run_end++;
-            } else {
-                seg.push_back(op);
-                run_end = (int)seg.size();
-            }
-        }
-        const int new_begin = (int)out.size();
-        for (size_t i = 0; i < seg.size();) {
-            size_t j = i;
-            while (j < seg.size() && diagonal1(seg[j].kind)) j++;
-            if (j - i >= 2) {
-                PlanOp m;
-                m.gate = 0;
-                m.kind = kDiagKind;
-                m.q0 = seg[i].q0;
-                m.q1 = -1;
-                m.train_slot = -1;
-                m.fused_count = (int)(j - i);
-                m.fused_index = 0;
-                out.push_back(m);
-                for (size_t k = i; k < j; k++) out.push_back(seg[k]);
-                m.fused_index = 1;
-                out.push_back(m);
-                i = j;
-            } else {
-                out.push_back(seg[i]);
-                i++;
-            }
-        }
-        sg.op_begin = new_begin;
-        sg.n_ops = (int)out.size() - new_begin;
-    }
-    pp.ops = out;
 }
 
 void fuse_segments(Plan &pl, int fuse_min)
@@ -279,17 +217,9 @@ void fuse_segments(Plan &pl, int fuse_min)
             };
             const int b = sg.op_begin, e = sg.op_begin + sg.n_ops;
             const int new_begin = (int)out.size();
-            // length of the unit starting at k: a diagonal run with its two markers, or one gate
-            auto unit = [&](int k) { return pp.ops[k].kind == kDiagKind ? pp.ops[k].fused_count + 2 : 1; };
-            auto unit_local = [&](int k) {
-                if (pp.ops[k].kind != kDiagKind) return local(pp.ops[k]);
-                for (int u = 1; u <= pp.ops[k].fused_count; u++)
-                    if (!local(pp.ops[k + u])) return false;
-                return true;
-            };
             for (int i = b; i < e;) {
                 int j = i;
-                while (j < e && unit_local(j)) j += unit(j);
+                while (j < e && local(pp.ops[j])) j++;
                 if (j - i >= fuse_min && next < 65535) {   // block numbers are 16-bit in the device op
                     PlanOp m;
                     m.gate = 0;
@@ -303,9 +233,8 @@ void fuse_segments(Plan &pl, int fuse_min)
                     for (int k = i; k < j; k++) out.push_back(pp.ops[k]);
                     i = j;
                 } else {
-                    const int u = unit(i);
-                    for (int k = i; k < i + u; k++) out.push_back(pp.ops[k]);
-                    i += u;
+                    out.push_back(pp.ops[i]);
+                    i++;
                 }
             }
             sg.op_begin = new_begin;
@@ -383,17 +312,6 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
             o.train_slot = op.train_slot;
             o.k0 = -1;
             o.k1 = -1;
-            if (op.kind == kDiagKind) {
-                // diagonal-run marker: run length in pad, p0 = 0 before the run / 1 after it
-                o.kind = (uint8_t)kDiagKind;
-                o.p0 = (uint8_t)op.fused_index;
-                o.p1 = 0;
-                o.pad = (int16_t)op.fused_count;
-                o.flags = 0;
-                o.train_slot = -1;
-                ops.push_back(o);
-                continue;
-            }
             if (op.kind == kFusedKind) {
                 // marker: block number in p0 | p1 << 8, block size in pad
                 o.kind = (uint8_t)kFusedKind;

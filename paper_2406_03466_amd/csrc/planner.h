@@ -22,8 +22,8 @@ struct PlanOp {
     int kind;        // qv_gate_kind, or kFusedKind for a fused-block marker
     int q0, q1;      // qubits (global)
     int train_slot;  // position among the pass's trainable gates, -1 if fixed
-    int fused_count = 0;   // markers: number of gates in the block (fused) or run (diagonal)
-    int fused_index = -1;  // fused markers: block number within the plan; diagonal markers: 0 before, 1 after
+    int fused_count = 0;   // markers: number of gates in the block
+    int fused_index = -1;  // markers: block number within the plan
 };
 
 // A register segment of a pass (see DevSeg in engine.h): positions are local.
@@ -58,10 +58,6 @@ constexpr int kMaxTrainPerPass = 256;
 // fuse_min > 0 turns every run of at least fuse_min consecutive gates of a segment that act on register
 // qubits only into a fused block (a marker op followed by the run).
 Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0, int fuse_min = 0);
-
-// Within each register segment, moves single-qubit diagonal gates (Z, S, T, RZ) next to the previous such
-// gate when no gate in between touches their qubit, and brackets every run of two or more with markers.
-void group_diagonals(PlanPass &pp);
 
 // Splits one pass into register segments (reorders its ops; dependencies are kept).
 void segment_pass(PlanPass &pp, int reg_bits);

@@ -1733,27 +1733,21 @@ qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gate
         o.local_mask = pp.local_mask;
         o.qubits = pp.t;
         int32_t nf = 0;
-        int32_t nm = 0;
-        for (const PlanOp &op : pp.ops) {
-            nf += op.kind == kFusedKind ? 1 : 0;
-            nm += op.kind >= kFusedKind ? 1 : 0;
-        }
-        o.n_ops = (int32_t)pp.ops.size() - nm;
-        o.n_diag_runs = 0;
-        for (const PlanOp &op : pp.ops) o.n_diag_runs += (op.kind == kDiagKind && op.fused_index == 0) ? 1 : 0;
+        for (const PlanOp &op : pp.ops) nf += op.kind == kFusedKind ? 1 : 0;
+        o.n_ops = (int32_t)pp.ops.size() - nf;
         o.n_fused = nf;
         o.n_trainable = pp.n_train;
         o.n_segments = (int32_t)pp.segs.size();
         o.first_gate = -1;
         for (const PlanOp &op : pp.ops)
-            if (op.kind < kFusedKind) { o.first_gate = op.gate; break; }
+            if (op.kind != kFusedKind) { o.first_gate = op.gate; break; }
         o.contiguous_low = pp.lowc;
     }
     if (order) {
         int64_t k = 0;
         for (const PlanPass &pp : pl.passes)
             for (const PlanOp &op : pp.ops)
-                if (op.kind < kFusedKind) order[k++] = op.gate;
+                if (op.kind != kFusedKind) order[k++] = op.gate;
     }
     return ok();
 }

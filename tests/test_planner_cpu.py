@@ -99,24 +99,3 @@ def test_fused_plans_keep_every_gate(fuse_min):
     assert [p["local_mask"] for p in plain] == [p["local_mask"] for p in passes]
     # the stride engine never fuses
     assert sum(p["n_fused"] for p in qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 2, fuse_min=fuse_min)) == 0
-
-
-def test_diagonal_runs_keep_every_gate():
-    """Runs of diagonal gates are grouped inside register segments (moved only past gates on other
-    qubits): the circuit-learning plan holds such runs, every gate still appears once in a valid order, and
-    for a 10-qubit random circuit the planned order gives the program-order state."""
-    wl = W.config3(8)
-    gates = wl.circuit(0)
-    passes, order = qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 0, with_order=True, fuse_min=8)
-    _check_plan(20, gates, passes, order)
-    assert sum(p["n_diag_runs"] for p in passes) > 0
-    rz = set(int(i) for i in np.flatnonzero(gates["kind"] == W.RZ))
-    # RZ gates of a layer end up next to each other in the execution order
-    adjacent = sum(1 for x, y in zip(order[:-1], order[1:]) if int(x) in rz and int(y) in rz)
-    assert adjacent > len(rz) // 2
-    wl = W.hea_vqe(10, 3, 4, 7, "diag")
-    g10 = wl.circuit(0)
-    passes, order = qvpu.plan_circuit(10, g10, 8, qvpu.QV_C64, 0, with_order=True)
-    _check_plan(10, g10, passes, order)
-    th = wl.theta_of(0)
-    np.testing.assert_allclose(oracle.final_state(10, g10, th), oracle.final_state(10, g10[order], th), atol=1e-13)
