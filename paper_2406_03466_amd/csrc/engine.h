@@ -85,7 +85,8 @@ struct Seg {
     int32_t circ;
     int32_t pass;
     int32_t first;        // 1: first pass of the circuit -- the tile starts as |0...0> instead of a load
-    int32_t pad;
+    int32_t last;         // adjoint: 1 for the circuit's first pass (undone last) -- psi and lambda are not
+                          // needed afterwards, so the tile is not written back
     int64_t wait;         // persistent launch: tiles of this circuit that must be finished first
 };
 

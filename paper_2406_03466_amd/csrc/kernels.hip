@@ -922,6 +922,7 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             a.partials[sg.partial_base + tile * P.n_train + slot] = s;
         }
     }
+    if (ADJ && sg.last) return;  // psi and lambda of a fully undone circuit are not read again
     if (sg.first && !ADJ) {
         for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
         __syncthreads();

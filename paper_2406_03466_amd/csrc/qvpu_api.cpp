@@ -466,7 +466,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         s.circ = c;
                         s.pass = pass_base[es.plan_of[c]] + p;
                         s.first = (dir == 0 && p == 0 && !pp.stride) ? 1 : 0;
-                        s.pad = 0;
+                        s.last = (dir == 1 && p == 0) ? 1 : 0;
                         s.wait = 0;
                         if (dir == 0) {
                             for (int q = 0; q < p; q++) s.wait += tiles_of(es.circs[c], pl, q);
