@@ -94,15 +94,34 @@ def timed(fn, stream_sync, reps: int = 1) -> float:
 
 
 def other_workloads(qvpu, W, stream, sync) -> dict:
-    """Circuit-eval rates of the other workload shapes, each on its own batch (created and freed here):
-    16-qubit VQE parameter-shift gradient (513 circuits), 1024 uneven random circuits, and the 32-qubit
-    10-layer circuit (32 GiB complex64 state) forward and adjoint, with and without fused MFMA blocks."""
+    """The other workload shapes, each on its own batch (created and freed here): circuit learning with 2
+    and 4 layers (adjoint vs parameter-shift gradients/s), the 16-qubit VQE parameter-shift gradient (513
+    circuits), 1024 uneven random circuits, and the 32-qubit 10-layer circuit (32 GiB complex64 state)
+    forward and adjoint, with and without fused MFMA blocks."""
     out = {}
 
     def ctx(**o):
         o.setdefault("graph", True)
         return qvpu.Context(0, stream.cuda_stream, json.dumps(o))
 
+    # circuit learning at 20 qubits with 2 and 4 layers: adjoint gradient vs parameter-shift, same engine
+    for layers in (2, 4):
+        wl = W.config3(layers)
+        b = qvpu.Batch(ctx(fusion="8"), wl, qvpu.QV_C64)
+        e, _ = b.expectations(want_terms=False)
+        up = 2.0 * (e - wl.extra["y"]) / wl.B
+
+        def grad(method):
+            b.expectations(want_terms=False)
+            b.gradient(method, upstream=up)
+
+        s_ad = timed(lambda: grad(qvpu.QV_ADJOINT), sync, 3)
+        s_ps = timed(lambda: b.gradient(qvpu.QV_PARAM_SHIFT, upstream=up), sync, 1)
+        out[f"qcl20_L{layers}_S64"] = {"adjoint_gradients_per_s": round(1.0 / s_ad, 3),
+                                       "param_shift_gradients_per_s": round(1.0 / s_ps, 4),
+                                       "speedup": round(s_ps / s_ad, 1),
+                                       "param_shift_circuits": wl.B * (2 * wl.n_grad() + 1)}
+        b.close()
     wl = W.config2()
     for prec, name in [(qvpu.QV_C64, "c64"), (qvpu.QV_C128, "c128")]:
         b = qvpu.Batch(ctx(), wl, prec)
@@ -117,7 +136,7 @@ def other_workloads(qvpu, W, stream, sync) -> dict:
                                           "circuits": wl.B}
     b.close()
     wl = W.config5()
-    for fusion in ["off", "4"]:
+    for fusion in ["off", "8"]:
         b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
         sf = timed(lambda: b.expectations(), sync, 1)
         sg = timed(lambda: b.gradient(qvpu.QV_ADJOINT), sync, 1)

@@ -479,7 +479,10 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         lv.lds_t = std::max(lv.lds_t, pp.t);
                         lv.max_train = std::max(lv.max_train, pp.n_train);
                         lv.tab_bits = std::max(lv.tab_bits, pp.t - pp.lowc);
-                        lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : 4) * (((int64_t)1 << es.circs[c].n) * amp_bytes);
+                        // forward: read + write (first pass: write only); adjoint: psi and lambda read + write
+                        // (the circuit's last reverse pass: read only)
+                        const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
+                        lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : (s.last ? 2 : 4)) * S;
                         lv.flops += pass_flops(pp, dir == 1) * (double)((int64_t)1 << es.circs[c].n);
                     }
                     if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
