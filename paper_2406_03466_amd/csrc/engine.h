@@ -24,6 +24,21 @@ constexpr int kRegBitsC128 = 3;      // 8 complex128 amplitudes per thread (2^12
 
 enum OpFlags : uint8_t { OP_TRAIN = 1 };
 
+// Register-segment op codes, stored in DevOp::flags above the OP_TRAIN bit: one code per gate class and
+// register bit(s), so a tile kernel picks an op's code path with one switch.
+enum OpCode : int {
+    OC_NONE = 0,        // not in a register segment (op-by-op LDS passes, stride passes)
+    OC_RY = 1,          // + register bit k (1..4): [[c, -s], [s, c]]
+    OC_DIAG = 5,        // + register bit k (5..8): RZ, Z, S, T on a register qubit
+    OC_DIAG_T = 9,      // RZ, Z, S, T on a thread qubit
+    OC_GEN = 10,        // + register bit k (10..13): H, X, Y, RX (dense 2x2)
+    OC_CNOT_RR = 14,    // + 4 * control bit + target bit (14..29): a register permutation
+    OC_CNOT_TR = 30,    // + target bit (30..33): control on a thread qubit
+    OC_CZ = 34,
+    OC_FUSED = 35,      // fused-block marker
+};
+constexpr int kOpCodeShift = 1;
+
 // One gate inside a pass, with its qubits translated to tile-local bit positions.
 struct DevOp {
     int32_t gate;        // gate index within its circuit (angle and parameter are read per circuit)

@@ -638,6 +638,84 @@ __device__ __forceinline__ double rop_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 << 
     return ip;
 }
 
+// Register-bit cases of an op-code switch: BASE + k runs STMT with the compile-time register bit K = k
+// (codes for register bits the kernel does not have are never generated).
+#define K4_CASES(BASE, STMT)                                                                  \
+    case (BASE) + 0: { constexpr int K = 0; STMT; } break;                                    \
+    case (BASE) + 1: { constexpr int K = 1; if constexpr (K < RB) { STMT; } } break;          \
+    case (BASE) + 2: { constexpr int K = 2; if constexpr (K < RB) { STMT; } } break;          \
+    case (BASE) + 3: { constexpr int K = 3; if constexpr (K < RB) { STMT; } } break;
+#define CNOT_CASE(KC_, KT_, STMT)                                                             \
+    case OC_CNOT_RR + 4 * (KC_) + (KT_): {                                                    \
+        constexpr int KC = KC_, KT = KT_;                                                     \
+        if constexpr (KC < RB && KT < RB && KC != KT) { STMT; }                               \
+    } break;
+#define CNOT_CASES(STMT)                                                                      \
+    CNOT_CASE(0, 1, STMT) CNOT_CASE(0, 2, STMT) CNOT_CASE(0, 3, STMT)                         \
+    CNOT_CASE(1, 0, STMT) CNOT_CASE(1, 2, STMT) CNOT_CASE(1, 3, STMT)                         \
+    CNOT_CASE(2, 0, STMT) CNOT_CASE(2, 1, STMT) CNOT_CASE(2, 3, STMT)                         \
+    CNOT_CASE(3, 0, STMT) CNOT_CASE(3, 1, STMT) CNOT_CASE(3, 2, STMT)
+
+// One register-segment op on v by its op code (the inverse when INV).
+template <bool INV, int RB, typename R>
+__device__ __forceinline__ void code_apply(Regs<R, 1 << RB> &v, int code, const DevOp &op, const M2<R> &mat,
+                                           uint32_t Et)
+{
+    const R cr = mat.re[0], sr = INV ? -mat.re[2] : mat.re[2];
+    const R d0r = mat.re[0], d1r = mat.re[3];
+    const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
+    switch (code) {
+    K4_CASES(OC_RY, (r_real<K>(v, cr, sr)))
+    K4_CASES(OC_DIAG, (r_diag<K>(v, d0r, d0i, d1r, d1i)))
+    case OC_DIAG_T: {
+        const bool b = (Et >> op.p0) & 1u;
+        t_scale(v, b ? d1r : d0r, b ? d1i : d0i);
+    } break;
+    K4_CASES(OC_GEN, (r_gen<K>(v, INV ? dagger_r(mat) : mat)))
+    CNOT_CASES((r_cnot<KC, KT>(v)))
+    K4_CASES(OC_CNOT_TR, (t_cnot<K>(v, ((Et >> op.p0) & 1u) != 0)))
+    case OC_CZ: {
+        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
+        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
+        neg_mask(v, ma & mb);
+    } break;
+    default: break;
+    }
+}
+
+// One adjoint register-segment op by its op code: Im <l| G |a> when the op is trainable, then the inverse
+// op on a and l.
+template <int RB, typename R>
+__device__ __forceinline__ double code_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 << RB> &l, int code, const DevOp &op,
+                                               const M2<R> &mat, uint32_t Et)
+{
+    const bool train = (op.flags & OP_TRAIN) != 0;
+    double ip = 0.0;
+    const R cr = mat.re[0], sr = -mat.re[2];
+    const R d0r = mat.re[0], d1r = mat.re[3], d0i = -mat.im[0], d1i = -mat.im[3];
+    switch (code) {
+    K4_CASES(OC_RY, (adj_real<K>(a, l, cr, sr, train, ip)))
+    K4_CASES(OC_DIAG, (adj_diag<K>(a, l, op.kind, d0r, d0i, d1r, d1i, train, ip)))
+    case OC_DIAG_T: {
+        const bool b = (Et >> op.p0) & 1u;
+        if (train) ip = t_inner_z(a, l, (int)b);
+        t_scale(a, b ? d1r : d0r, b ? d1i : d0i);
+        t_scale(l, b ? d1r : d0r, b ? d1i : d0i);
+    } break;
+    K4_CASES(OC_GEN, (adj_gen<K>(a, l, op.kind, dagger_r(mat), train, ip)))
+    CNOT_CASES((r_cnot<KC, KT>(a), r_cnot<KC, KT>(l)))
+    K4_CASES(OC_CNOT_TR, (t_cnot<K>(a, ((Et >> op.p0) & 1u) != 0), t_cnot<K>(l, ((Et >> op.p0) & 1u) != 0)))
+    case OC_CZ: {
+        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
+        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
+        neg_mask(a, ma & mb);
+        neg_mask(l, ma & mb);
+    } break;
+    default: break;
+    }
+    return ip;
+}
+
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 // A fused 4-qubit block on the 16 register amplitudes of every lane, as one wave-wide real GEMM on MFMA:
@@ -725,7 +803,7 @@ __device__ __forceinline__ void seg_step(const LevelArgs &a, const DevCirc &C, c
     ao = ai;
     if (ADJ) {
         lo = li;
-        double ip = rop_adjoint<RB, R>(ao, lo, op, kind, mat, Et);
+        double ip = code_adjoint<RB, R>(ao, lo, op.flags >> kOpCodeShift, op, mat, Et);
         if (op.flags & OP_TRAIN) {
             if (!active) ip = 0.0;
             ip = wave_sum_to_63(ip);
@@ -889,7 +967,7 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                     continue;
                 }
                 if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
-                rop_apply<false, RB, R>(av, op, kind, mat, Et);
+                code_apply<false, RB, R>(av, op.flags >> kOpCodeShift, op, mat, Et);
             }
         }
         if (active) {

@@ -318,7 +318,7 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
                 o.p0 = (uint8_t)(op.fused_index & 0xFF);
                 o.p1 = (uint8_t)((op.fused_index >> 8) & 0xFF);
                 o.pad = (int16_t)op.fused_count;
-                o.flags = 0;
+                o.flags = (uint8_t)(OC_FUSED << kOpCodeShift);
                 o.train_slot = -1;
                 ops.push_back(o);
                 continue;
@@ -329,6 +329,15 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
                     if (sg.rpos[k] == o.p0) o.k0 = (int8_t)k;
                     if (op.q1 >= 0 && sg.rpos[k] == o.p1) o.k1 = (int8_t)k;
                 }
+                int code = OC_NONE;
+                switch (op.kind) {
+                case QV_RY: code = OC_RY + o.k0; break;
+                case QV_RZ: case QV_Z: case QV_S: case QV_T: code = o.k0 >= 0 ? OC_DIAG + o.k0 : OC_DIAG_T; break;
+                case QV_CNOT: code = o.k0 >= 0 ? OC_CNOT_RR + 4 * o.k0 + o.k1 : OC_CNOT_TR + o.k1; break;
+                case QV_CZ: code = OC_CZ; break;
+                default: code = OC_GEN + o.k0; break;  // H, X, Y, RX: the qubit is a register qubit
+                }
+                o.flags = (uint8_t)(o.flags | (code << kOpCodeShift));
             }
             o.pad = 0;
             ops.push_back(o);
