@@ -444,11 +444,6 @@ __device__ __forceinline__ void r_cnot(Regs<R, N> &v)
     }
 }
 
-template <int KC, int RB, int N, typename R>
-__device__ __forceinline__ void r_cnot_t(Regs<R, N> &v, int kt)
-{
-    if constexpr (KC < RB) WITH_K(RB, kt, (r_cnot<KC, K>(v)));
-}
 
 // CNOT with target register bit KT, control given per thread.
 template <int KT, int N, typename R>
@@ -516,50 +511,8 @@ __device__ __forceinline__ double t_inner_z(const Regs<R, N> &a, const Regs<R, N
     return bit ? -t : t;
 }
 
-// One op applied to the registers v (the inverse when INV).
-template <bool INV, int RB, typename R>
-__device__ __forceinline__ void rop_apply(Regs<R, 1 << RB> &v, const DevOp &op, int kind, const M2<R> &mat,
-                                          uint32_t Et)
-{
-    if (kind == QV_CNOT) {
-        if (op.k0 >= 0) {
-            // control and target both register bits: a fixed permutation of the registers
-            WITH_K(RB, op.k0, (r_cnot_t<K, RB>(v, op.k1)));
-        } else {
-            const bool ctl = (Et >> op.p0) & 1u;
-            WITH_K(RB, op.k1, t_cnot<K>(v, ctl));
-        }
-        return;
-    }
-    if (kind == QV_CZ) {
-        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
-        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
-        neg_mask(v, ma & mb);
-        return;
-    }
-    if (kind == QV_RY) {
-        // [[c, -s], [s, c]]; the inverse is the transpose
-        const R cr = mat.re[0], sr = INV ? -mat.re[2] : mat.re[2];
-        WITH_K(RB, op.k0, r_real<K>(v, cr, sr));
-        return;
-    }
-    if (kind == QV_RZ || kind == QV_Z || kind == QV_S || kind == QV_T) {
-        const R d0r = mat.re[0], d1r = mat.re[3];
-        const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
-        if (op.k0 >= 0) {
-            WITH_K(RB, op.k0, r_diag<K>(v, d0r, d0i, d1r, d1i));
-        } else {
-            const bool b = (Et >> op.p0) & 1u;
-            t_scale(v, b ? d1r : d0r, b ? d1i : d0i);
-        }
-        return;
-    }
-    const M2<R> m = INV ? dagger_r(mat) : mat;
-    WITH_K(RB, op.k0, r_gen<K>(v, m));
-}
-
-// Adjoint step for one op on psi (a) and lambda (l) together, one dispatch on the op's register bit:
-// Im <l| G |a> when the op is trainable (returned through ip), then the inverse op on both.
+// Adjoint step for one op on psi (a) and lambda (l) together on register bit K: Im <l| G |a> when the op
+// is trainable (returned through ip), then the inverse op on both.
 template <int K, int N, typename R>
 __device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s, bool train, double &ip)
 {
@@ -586,56 +539,6 @@ __device__ __forceinline__ void adj_gen(Regs<R, N> &a, Regs<R, N> &l, int kind, 
     if (train) ip = r_inner<K, QV_RX>(a, l);
     r_gen<K>(a, m);
     r_gen<K>(l, m);
-}
-
-template <int KC, int RB, int N, typename R>
-__device__ __forceinline__ void adj_cnot_t(Regs<R, N> &a, Regs<R, N> &l, int kt)
-{
-    if constexpr (KC < RB) WITH_K(RB, kt, (r_cnot<KC, K>(a), r_cnot<KC, K>(l)));
-}
-
-template <int RB, typename R>
-__device__ __forceinline__ double rop_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 << RB> &l, const DevOp &op, int kind,
-                                              const M2<R> &mat, uint32_t Et)
-{
-    const bool train = (op.flags & OP_TRAIN) != 0;
-    double ip = 0.0;
-    if (kind == QV_CNOT) {
-        if (op.k0 >= 0) {
-            WITH_K(RB, op.k0, (adj_cnot_t<K, RB>(a, l, op.k1)));
-        } else {
-            const bool ctl = (Et >> op.p0) & 1u;
-            WITH_K(RB, op.k1, (t_cnot<K>(a, ctl), t_cnot<K>(l, ctl)));
-        }
-        return ip;
-    }
-    if (kind == QV_CZ) {
-        const uint32_t ma = op.k0 >= 0 ? reg_pattern(op.k0) : (((Et >> op.p0) & 1u) ? 0xFFFFFFFFu : 0u);
-        const uint32_t mb = op.k1 >= 0 ? reg_pattern(op.k1) : (((Et >> op.p1) & 1u) ? 0xFFFFFFFFu : 0u);
-        neg_mask(a, ma & mb);
-        neg_mask(l, ma & mb);
-        return ip;
-    }
-    if (kind == QV_RY) {
-        const R cr = mat.re[0], sr = -mat.re[2];
-        WITH_K(RB, op.k0, (adj_real<K>(a, l, cr, sr, train, ip)));
-        return ip;
-    }
-    if (kind == QV_RZ || kind == QV_Z || kind == QV_S || kind == QV_T) {
-        const R d0r = mat.re[0], d1r = mat.re[3], d0i = -mat.im[0], d1i = -mat.im[3];
-        if (op.k0 >= 0) {
-            WITH_K(RB, op.k0, (adj_diag<K>(a, l, kind, d0r, d0i, d1r, d1i, train, ip)));
-        } else {
-            const bool b = (Et >> op.p0) & 1u;
-            if (train) ip = t_inner_z(a, l, (int)b);
-            t_scale(a, b ? d1r : d0r, b ? d1i : d0i);
-            t_scale(l, b ? d1r : d0r, b ? d1i : d0i);
-        }
-        return ip;
-    }
-    const M2<R> m = dagger_r(mat);
-    WITH_K(RB, op.k0, (adj_gen<K>(a, l, kind, m, train, ip)));
-    return ip;
 }
 
 // Register-bit cases of an op-code switch: BASE + k runs STMT with the compile-time register bit K = k
@@ -757,60 +660,37 @@ struct OpCursor {
     M2<R> mat;
 };
 
-// One step of a register segment: the next op (or fused block) applied to (ai, li), result in (ao, lo).
-template <typename R, bool ADJ, int RB, int NT>
-__device__ __forceinline__ void seg_step(const LevelArgs &a, const DevCirc &C, const M2<R> *mtab, OpCursor<R> &oc,
+// One adjoint step of a register segment, walking its ops backwards: the next op undone on (ai, li) with
+// its partial sum, result in (ao, lo). Fused-block markers carry no adjoint work (the adjoint needs the
+// state at every trainable gate, so a block's gates are undone one by one).
+template <typename R, int RB, int NT>
+__device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, const M2<R> *mtab, OpCursor<R> &oc,
                                          uint32_t Et, bool active, int lane, int wave, double *red,
                                          const Regs<R, 1 << RB> &ai, const Regs<R, 1 << RB> &li,
                                          Regs<R, 1 << RB> &ao, Regs<R, 1 << RB> &lo)
 {
-    DevOp op = oc.op;
-    M2<R> mat = oc.mat;
-    int64_t cur = oc.oi;
-    auto advance = [&](int by, int64_t to) {
-        oc.k += by;
+    auto advance = [&]() {
+        oc.k += 1;
         if (oc.k < oc.n) {
-            oc.oi = to;
-            oc.op = ldu(a.ops + to);
-            oc.mat = ldu(mtab + to);
+            oc.oi -= 1;
+            oc.op = ldu(a.ops + oc.oi);
+            oc.mat = ldu(mtab + oc.oi);
         }
     };
-    advance(1, cur + (ADJ ? -1 : 1));
-    if (op.kind == kFusedKind) {
-        // A fused block: forward applies its product on MFMA and skips its gates; the adjoint (which needs
-        // the state at every trainable gate), complex128 and a block holding a shifted gate run the gates.
-        if constexpr (!ADJ && RB == 4 && sizeof(R) == 4) {
-            const int m = op.pad;
-            bool shifted = false;
-            if (C.shift_gate >= 0)
-                for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
-            if (!shifted) {
-                const int f = op.p0 | (op.p1 << 8);
-                ao = ai;
-                fused_mfma(ao, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
-                advance(m, cur + m + 1);
-                return;
-            }
-        }
-        // a marker is always followed by its gates in the same segment: take the first of them
-        op = oc.op;
-        mat = oc.mat;
-        cur = oc.oi;
-        advance(1, cur + (ADJ ? -1 : 1));
-    }
-    const int kind = op.kind;
-    if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
     ao = ai;
-    if (ADJ) {
-        lo = li;
-        double ip = code_adjoint<RB, R>(ao, lo, op.flags >> kOpCodeShift, op, mat, Et);
-        if (op.flags & OP_TRAIN) {
-            if (!active) ip = 0.0;
-            ip = wave_sum_to_63(ip);
-            if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
-        }
-    } else {
-        rop_apply<false, RB, R>(ao, op, kind, mat, Et);
+    lo = li;
+    while (oc.k < oc.n && oc.op.kind == kFusedKind) advance();
+    if (oc.k >= oc.n) return;
+    const DevOp op = oc.op;
+    M2<R> mat = oc.mat;
+    const int64_t cur = oc.oi;
+    advance();
+    if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
+    double ip = code_adjoint<RB, R>(ao, lo, op.flags >> kOpCodeShift, op, mat, Et);
+    if (op.flags & OP_TRAIN) {
+        if (!active) ip = 0.0;
+        ip = wave_sum_to_63(ip);
+        if (lane == 63) red[op.train_slot * (NT / 64) + wave] = ip;
     }
 }
 
@@ -921,13 +801,13 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             // its result in the registers it read from and the branches of a step need no copies to agree.
             Regs<R, N> aw, lw;
             while (oc.k < oc.n) {
-                seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
+                adj_step<R, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
                 if (oc.k >= oc.n) {
                     av = aw;
                     lv = lw;
                     break;
                 }
-                seg_step<R, ADJ, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
+                adj_step<R, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
             }
         } else {
             // forward ops update one register set in place (within the 128-register budget of two
