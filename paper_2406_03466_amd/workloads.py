@@ -237,13 +237,14 @@ def config3(layers: int = 8) -> Workload:
 
 
 def random_batch(n_circuits: int = 1024, n_min: int = 8, n_max: int = 22, g_min: int = 10, g_max: int = 200,
-                 n_terms: int = 8, seed_index: int = 4) -> Workload:
+                 n_terms: int = 8, seed_index: int = 4, kinds=None) -> Workload:
     """Uneven batch of random circuits. Per circuit: n ~ U{n_min..n_max}, gate count ~ U{g_min..g_max},
-    each gate uniform over {H, RX, RY, RZ, CNOT, CZ} on uniform qubits (ordered distinct pairs for
-    two-qubit gates); every rotation has its own parameter, theta ~ U[0, 2pi). Then n_terms random Pauli
-    strings with N(0,1) weights. Draw order: per circuit (n, G, gates, angles), then all observables."""
+    each gate uniform over `kinds` (default {H, RX, RY, RZ, CNOT, CZ}) on uniform qubits (ordered distinct
+    pairs for two-qubit gates); every rotation has its own parameter, theta ~ U[0, 2pi). Then n_terms
+    random Pauli strings with N(0,1) weights. Draw order: per circuit (n, G, gates, angles), then all
+    observables."""
     rng = np.random.default_rng(SEED_BASE + seed_index)
-    kinds = [H, RX, RY, RZ, CNOT, CZ]
+    kinds = list(kinds) if kinds is not None else [H, RX, RY, RZ, CNOT, CZ]
     circuits, nqs, nps, thetas = [], [], [], []
     for _ in range(n_circuits):
         n = int(rng.integers(n_min, n_max + 1))

@@ -379,3 +379,41 @@ def test_qcl20_fused_blocks(qv, layers):
     check(g, np.array(gold["grad"]), 0, float(np.sum(np.abs(gold["upstream"]))), "grad")
     passes = qv.plan_circuit(20, wl.circuit(0), 13, qv.QV_C64, 0, fuse_min=4)
     assert sum(p["n_fused"] for p in passes) > 0
+
+
+ALL_KINDS = [W.H, W.X, W.Y, W.Z, W.S, W.T, W.RX, W.RY, W.RZ, W.CNOT, W.CZ]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("opts", [{}, {"fusion": 2}, {"tile_qubits": 7}, {"engine": "lds"}, {"engine": "stride"}])
+def test_all_gate_kinds(qv, prec, opts):
+    """Random circuits over all eleven gate kinds (every op code of the register segments: dense, real and
+    diagonal one-qubit gates on register and thread qubits, CNOT with register or thread control, CZ):
+    energies, term values and adjoint and parameter-shift gradients against the oracle."""
+    say(f"all kinds prec={prec} opts={opts}")
+    wl = W.random_batch(12, 3, 13, 20, 120, 4, seed_index=77, kinds=ALL_KINDS)
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    up = np.linspace(0.5, -1.0, wl.B)
+    g_ref = oracle.grad_adjoint(wl, up)
+    b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    g_ad, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+    check(g_ad, g_ref, prec, s * float(np.sum(np.abs(up))), "adjoint grad")
+    g_ps, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
+    check(g_ps, g_ref, prec, s * float(np.sum(np.abs(up))), "param-shift grad")
+
+
+def test_qcl20_full_size_complex128(qv):
+    """20 qubits, 64 samples, 2 layers in complex128 (register tiles of 2^12 amplitudes, 8 per thread):
+    every energy and gradient component against the oracle's stored values to 1e-12."""
+    say("qcl20 L=2 c128")
+    gold = _golden("qcl20_L2")
+    wl = W.config3(2)
+    b = qv.Batch(ctx_for(qv), wl, 1)
+    e, _ = b.expectations(want_terms=False)
+    check(e, np.array(gold["energies"]), 1, 1.0, "energies")
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
+    check(g, np.array(gold["grad"]), 1, 1.0, "grad")
