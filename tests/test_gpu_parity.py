@@ -408,7 +408,9 @@ def test_all_gate_kinds(qv, prec, opts):
 
 def test_qcl20_full_size_complex128(qv):
     """20 qubits, 64 samples, 2 layers in complex128 (register tiles of 2^12 amplitudes, 8 per thread):
-    every energy and gradient component against the oracle's stored values to 1e-12."""
+    every energy to 1e-12 and every gradient component to 1e-11 against the oracle's stored values. A
+    gradient component here is a sum of 64 x 2^20 products that the oracle accumulates one amplitude after
+    another (worst-case rounding 2^20 x 1.1e-16 relative), so the two FP64 results differ by ~1e-12."""
     say("qcl20 L=2 c128")
     gold = _golden("qcl20_L2")
     wl = W.config3(2)
@@ -416,4 +418,5 @@ def test_qcl20_full_size_complex128(qv):
     e, _ = b.expectations(want_terms=False)
     check(e, np.array(gold["energies"]), 1, 1.0, "energies")
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
-    check(g, np.array(gold["grad"]), 1, 1.0, "grad")
+    err = np.abs(g - np.array(gold["grad"]))
+    assert err.max() <= 1e-11, f"grad: max err {err.max():.3e} at {int(np.argmax(err))}"
