@@ -93,7 +93,7 @@ def timed(fn, stream_sync, reps: int = 1) -> float:
     return (time.time() - t0) / reps
 
 
-def other_workloads(qvpu, W, stream, sync) -> dict:
+def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
     """The other workload shapes, each on its own batch (created and freed here): circuit learning with 2
     and 4 layers (adjoint vs parameter-shift gradients/s), the 16-qubit VQE parameter-shift gradient (513
     circuits), 1024 uneven random circuits, and the 32-qubit 10-layer circuit (32 GiB complex64 state)
@@ -105,7 +105,7 @@ def other_workloads(qvpu, W, stream, sync) -> dict:
         return qvpu.Context(0, stream.cuda_stream, json.dumps(o))
 
     # circuit learning at 20 qubits with 2 and 4 layers: adjoint gradient vs parameter-shift, same engine
-    for layers in (2, 4):
+    for layers in ((2, 4) if only in (None, "qcl") else ()):
         wl = W.config3(layers)
         b = qvpu.Batch(ctx(fusion="8"), wl, qvpu.QV_C64)
         e, _ = b.expectations(want_terms=False)
@@ -123,20 +123,21 @@ def other_workloads(qvpu, W, stream, sync) -> dict:
                                        "param_shift_circuits": wl.B * (2 * wl.n_grad() + 1)}
         b.close()
     wl = W.config2()
-    for prec, name in [(qvpu.QV_C64, "c64"), (qvpu.QV_C128, "c128")]:
+    for prec, name in ([(qvpu.QV_C64, "c64"), (qvpu.QV_C128, "c128")] if only in (None, "hea16") else []):
         b = qvpu.Batch(ctx(), wl, prec)
         s = timed(lambda: b.gradient(qvpu.QV_PARAM_SHIFT), sync, 3)
         out[f"hea16_L8_T100_param_shift_{name}"] = {"circuit_evals_per_s": round(513 / s, 1),
                                                      "gradient_ms": round(s * 1e3, 3), "circuits": 513}
         b.close()
-    wl = W.config4()
-    b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
-    s = timed(lambda: b.expectations(), sync, 3)
-    out["random1024_expectations_c64"] = {"circuit_evals_per_s": round(wl.B / s, 1), "ms": round(s * 1e3, 3),
-                                          "circuits": wl.B}
-    b.close()
-    wl = W.config5()
-    for fusion in ["off", "8"]:
+    if only in (None, "random1024"):
+        wl = W.config4()
+        b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
+        s = timed(lambda: b.expectations(), sync, 3)
+        out["random1024_expectations_c64"] = {"circuit_evals_per_s": round(wl.B / s, 1),
+                                              "ms": round(s * 1e3, 3), "circuits": wl.B}
+        b.close()
+    wl = W.config5() if only in (None, "hea32") else None
+    for fusion in (["off", "8"] if wl is not None else []):
         b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
         sf = timed(lambda: b.expectations(), sync, 1)
         sg = timed(lambda: b.gradient(qvpu.QV_ADJOINT), sync, 1)
@@ -156,6 +157,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ps", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workload shapes")
+    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32"],
+                    help="run only this one of the other workload shapes and print its figures")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
@@ -183,6 +186,10 @@ def main():
     from paper_2406_03466_amd import qvpu
     from paper_2406_03466_amd import workloads as W
     from paper_2406_03466_amd.autograd import expectation
+    if args.only:
+        st = torch.cuda.current_stream(torch.device("cuda:0"))
+        print(json.dumps(other_workloads(qvpu, W, st, torch.cuda.synchronize, args.only)), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
