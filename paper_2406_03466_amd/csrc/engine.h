@@ -202,6 +202,7 @@ struct ExpArgs {
 
 struct FinalizeArgs {
     int32_t n_circ;
+    int64_t n_terms;             // output terms of all circuits (tv_begin[n_circ])
     const int64_t *tv_begin;     // [n_circ + 1] output term ranges
     const PartialRef *term_refs; // per output term
     const double *coeff;         // per output term

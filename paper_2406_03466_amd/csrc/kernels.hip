@@ -1219,29 +1219,32 @@ __global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(FinalizeArgs a)
+// Second stage of the expectation reduction: one workgroup per output (a term value, or a circuit's norm)
+// sums that output's partials -- a fixed strided share per thread, then a fixed tree -- so the result does
+// not depend on scheduling.
+__global__ __launch_bounds__(kBlock) void k_finalize_refs(FinalizeArgs a)
 {
-    const double *partials = a.partials;
-    const int b = blockIdx.x;
-    const int64_t t0 = a.tv_begin[b], t1 = a.tv_begin[b + 1];
-    for (int64_t o = t0 + threadIdx.x; o < t1; o += kBlock) {
-        const PartialRef r = a.term_refs[o];
-        double s = 0.0;
-        for (int32_t c = 0; c < r.count; c++) s += partials[r.base + (int64_t)c * r.stride];
-        a.term_values[o] = s;
-    }
-    if (threadIdx.x == 0 && a.norm_refs && a.norms) {
-        const PartialRef r = a.norm_refs[b];
-        double s = 0.0;
-        for (int32_t c = 0; c < r.count; c++) s += partials[r.base + (int64_t)c * r.stride];
-        a.norms[b] = s;
-    }
-    __syncthreads();
+    __shared__ double red[kBlock / 64];
+    const int64_t o = (int64_t)blockIdx.x;
+    const bool term = o < a.n_terms;
+    const PartialRef r = term ? a.term_refs[o] : a.norm_refs[o - a.n_terms];
+    double s = 0.0;
+    for (int32_t c = threadIdx.x; c < r.count; c += kBlock) s += a.partials[r.base + (int64_t)c * r.stride];
+    s = block_sum(s, red);
     if (threadIdx.x == 0) {
-        double e = 0.0;
-        for (int64_t o = t0; o < t1; o++) e += a.coeff[o] * a.term_values[o];
-        a.energies[b] = e;
+        if (term) a.term_values[o] = s;
+        else a.norms[o - a.n_terms] = s;
     }
+}
+
+// E_b = sum_t c_t <P_t>, in term order.
+__global__ __launch_bounds__(kBlock) void k_finalize_energies(FinalizeArgs a)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= a.n_circ) return;
+    double e = 0.0;
+    for (int64_t o = a.tv_begin[b]; o < a.tv_begin[b + 1]; o++) e += a.coeff[o] * a.term_values[o];
+    a.energies[b] = e;
 }
 
 // lambda_b[o] = w_b sum_t c_t (P_t psi_b)[o], (P psi)[o] = i^{ny} (-1)^{popcount((o^x) & z)} psi[o ^ x].
@@ -1260,9 +1263,14 @@ __global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
     for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
         const uint64_t o = o0 + e;
         if (o >= dim) break;
-        double sr = 0.0, si = 0.0;
+        // diagonal terms (x-mask 0) scale psi[o] itself: their signed coefficients are summed first
+        double d = 0.0, sr = 0.0, si = 0.0;
         for (int64_t t = tb; t < te; t++) {
-            const DevObsTerm term = a.obs[t];
+            const DevObsTerm term = ldu(a.obs + t);
+            if (term.xmask == 0) {
+                d += parity64(o & term.zmask) ? -term.coeff : term.coeff;
+                continue;
+            }
             const uint64_t b = o ^ term.xmask;
             const Cx<R> v = st[b];
             double vr = v.re, vi = v.im, pr, pi;
@@ -1276,6 +1284,9 @@ __global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
             sr += cf * pr;
             si += cf * pi;
         }
+        const Cx<R> v0 = st[o];
+        sr += d * (double)v0.re;
+        si += d * (double)v0.im;
         Cx<R> out;
         out.re = (R)(w * sr);
         out.im = (R)(w * si);
@@ -1502,7 +1513,9 @@ int launch_finalize(const FinalizeArgs &a, void *stream)
 {
     if (a.n_circ <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.n_circ), dim3(kBlock), 0, s, a);
+    const int64_t outs = a.n_terms + ((a.norm_refs && a.norms) ? a.n_circ : 0);
+    if (outs > 0) hipLaunchKernelGGL(k_finalize_refs, dim3((unsigned)outs), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_finalize_energies, dim3((unsigned)((a.n_circ + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

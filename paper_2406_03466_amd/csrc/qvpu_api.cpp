@@ -832,6 +832,7 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     if (e) return e;
     FinalizeArgs fa;
     fa.n_circ = es.n_circ;
+    fa.n_terms = (int64_t)es.term_refs.size();
     fa.tv_begin = es.d_tv_begin.as<int64_t>();
     fa.term_refs = es.d_term_refs.as<PartialRef>();
     fa.coeff = es.d_coeff.as<double>();
