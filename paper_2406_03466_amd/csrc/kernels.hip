@@ -696,7 +696,7 @@ __device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, c
 
 // Amplitudes each thread moves between HBM and LDS per batch of independent loads (or stores).
 template <typename R>
-constexpr int tile_batch() { return sizeof(R) == 4 ? 8 : 4; }
+constexpr int tile_batch() { return sizeof(R) == 4 ? 16 : 8; }
 
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, const Seg &sg)
