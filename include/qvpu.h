@@ -21,8 +21,9 @@
  *   - states are never renormalised; expectations are <psi|P|psi>.
  *
  * Precision
- *   QV_C64:  complex64 amplitudes, FP32 gate arithmetic; expectation reductions, the norm and the
- *            adjoint inner products are accumulated in FP64.
+ *   QV_C64:  complex64 amplitudes, FP32 gate arithmetic; expectation reductions and the norm are
+ *            accumulated in FP64; the adjoint inner products are summed over a thread's 16 amplitudes in
+ *            FP32 and across threads, tiles and circuits in FP64.
  *   QV_C128: complex128 amplitudes, FP64 everywhere.
  *
  * Errors
