@@ -699,7 +699,8 @@ template <typename R>
 constexpr int tile_batch() { return sizeof(R) == 4 ? 16 : 8; }
 
 template <typename R, bool ADJ, int RB, int NT>
-__device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, const Seg &sg)
+__device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, const Seg &sg, bool preloaded,
+                                           int64_t next_blk)
 {
     static_assert(RB >= 1 && RB <= 4, "register-bit dispatch covers register bits 0..3");
     constexpr int N = 1 << RB;
@@ -723,8 +724,16 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
     const uint32_t lmask = (1u << lowc) - 1u;
     Cx<R> *gpsi = reinterpret_cast<Cx<R> *>(a.psi) + C.state_off;
     Cx<R> *glam = ADJ ? reinterpret_cast<Cx<R> *>(a.lam) + C.state_off : nullptr;
+    // The next tile of the same (circuit, pass) is loaded straight into LDS while the last register segment
+    // of this one runs (the segment holds the whole tile in registers, so LDS is free); this tile then
+    // goes from registers to HBM directly.
+    constexpr int APP = 64 * 16 / (int)sizeof(Cx<R>);  // amplitudes one 16-byte-per-lane load moves
+    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && T >= (uint32_t)APP;
 
-    if (!ADJ && sg.first) {
+    if (preloaded) {
+        // this tile was loaded by the previous tile's last segment (same pass: the run table is in place)
+        __builtin_amdgcn_s_waitcnt(0);
+    } else if (!ADJ && sg.first) {
         // first pass of the circuit: the tile of |0...0> is zero except amplitude 0 of tile 0
         for (uint32_t e = threadIdx.x; e < T; e += NT) {
             Cx<R> z;
@@ -788,6 +797,25 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             av.set(j, sp[addr]);
             if (ADJ) lv.set(j, sl[addr]);
         }
+        const bool last_seg = s0 == P.n_seg - 1;
+        if (pf && last_seg) {
+            __syncthreads();  // every wave has its registers: LDS may be overwritten
+            const uint64_t nbase = deposit((uint64_t)(next_blk - sg.first_block), full & ~P.local_mask);
+            const Cx<R> *npsi = gpsi;
+            for (uint32_t c = (uint32_t)wave; c < T / APP; c += NT / 64) {
+                // lane l fills LDS positions c*APP + l*(APP/64) ...: elements swz(position), contiguous in HBM
+                const uint32_t pos = c * APP + (uint32_t)lane * (APP / 64);
+                const uint32_t e = swz(pos);
+                const uint64_t g = nbase | segtab[e >> lowc] | (e & lmask);
+                __builtin_amdgcn_global_load_lds(
+                    (const void __attribute__((address_space(1))) *)(npsi + g),
+                    (void __attribute__((address_space(3))) *)(sp + c * APP), 16, 0, 0);
+                if (ADJ)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void __attribute__((address_space(1))) *)(glam + g),
+                        (void __attribute__((address_space(3))) *)(sl + c * APP), 16, 0, 0);
+            }
+        }
         // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
         const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.mat_off - C.op_base);
         OpCursor<R> oc;
@@ -850,7 +878,29 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
                 code_apply<false, RB, R>(av, op.flags >> kOpCodeShift, op, mat, Et);
             }
         }
-        if (active) {
+        if (pf && last_seg) {
+            // straight to HBM from registers: register j holds element Et | D_j of the tile
+            if (active && !(ADJ && sg.last)) {
+                uint32_t et = Et, rb2[RB];
+                asm volatile("" : "+v"(et));
+#pragma unroll
+                for (int k = 0; k < RB; k++) {
+                    rb2[k] = rbit[k];
+                    asm volatile("" : "+s"(rb2[k]));
+                }
+#pragma unroll
+                for (int j = 0; j < N; j++) {
+                    uint32_t D = 0;
+#pragma unroll
+                    for (int k = 0; k < RB; k++)
+                        if (j >> k & 1) D |= rb2[k];
+                    const uint32_t e = et | D;
+                    const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+                    gpsi[g] = av.get(j);
+                    if (ADJ) glam[g] = lv.get(j);
+                }
+            }
+        } else if (active) {
             // recompute the addresses rather than keep 2^RB of them live through the op loop
             uint32_t pe = PE, rb2[RB];
             asm volatile("" : "+v"(pe));
@@ -880,7 +930,8 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             a.partials[sg.partial_base + tile * P.n_train + slot] = s;
         }
     }
-    if (ADJ && sg.last) return;  // psi and lambda of a fully undone circuit are not read again
+    if (ADJ && sg.last) return pf;  // psi and lambda of a fully undone circuit are not read again
+    if (pf) return true;            // stored from registers in the last segment
     if (sg.first && !ADJ) {
         for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
         __syncthreads();
@@ -908,6 +959,29 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
             }
         }
     }
+    return false;
+}
+
+// A level launch: workgroups take chunks of kTileChunk consecutive tiles (grid-stride over chunks); within
+// a chunk, a tile whose successor belongs to the same (circuit, pass) prefetches it.
+constexpr int kTileChunk = 8;
+
+template <typename R, bool ADJ, int RB, int NT>
+__device__ __forceinline__ void rtile_tiles(const LevelArgs &a)
+{
+    const int64_t nchunks = (a.n_blocks + kTileChunk - 1) / kTileChunk;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t b0 = c * kTileChunk, b1 = b0 + kTileChunk < a.n_blocks ? b0 + kTileChunk : a.n_blocks;
+        bool pre = false;
+        for (int64_t blk = b0; blk < b1; blk++) {
+            const int si = find_block(a.segs, a.n_segs, blk);
+            const Seg sg = a.segs[si];
+            const int64_t send = si + 1 < a.n_segs ? a.segs[si + 1].first_block : a.n_blocks;
+            const int64_t nxt = (blk + 1 < b1 && blk + 1 < send) ? blk + 1 : -1;
+            pre = rtile_body<R, ADJ, RB, NT>(a, blk, sg, pre, nxt);
+            __syncthreads();
+        }
+    }
 }
 
 // Forward passes ask for two workgroups per CU (at most 128 VGPRs); the adjoint keeps psi and lambda in
@@ -915,15 +989,13 @@ __device__ __forceinline__ void rtile_body(const LevelArgs &a, int64_t blk, cons
 template <typename R, int RB, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rtile_fwd(LevelArgs a)
 {
-    const int64_t blk = (int64_t)blockIdx.x;
-    rtile_body<R, false, RB, NT>(a, blk, a.segs[find_block(a.segs, a.n_segs, blk)]);
+    rtile_tiles<R, false, RB, NT>(a);
 }
 
 template <typename R, int RB, int NT>
 __global__ __launch_bounds__(NT) void k_rtile_adj(LevelArgs a)
 {
-    const int64_t blk = (int64_t)blockIdx.x;
-    rtile_body<R, true, RB, NT>(a, blk, a.segs[find_block(a.segs, a.n_segs, blk)]);
+    rtile_tiles<R, true, RB, NT>(a);
 }
 
 // Persistent form: workgroups stay resident and claim items from a queue. Items are the blocks of all
@@ -961,7 +1033,7 @@ __device__ __forceinline__ void persistent_body(const PersistArgs &pa)
             __threadfence();
         }
         __syncthreads();
-        rtile_body<R, ADJ, RB, NT>(a, blk, sg);
+        rtile_body<R, ADJ, RB, NT>(a, blk, sg, false, -1);
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();
