@@ -727,7 +727,10 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
     // The next tile of the same (circuit, pass) is loaded straight into LDS while the last register segment
     // of this one runs (the segment holds the whole tile in registers, so LDS is free); this tile then
     // goes from registers to HBM directly.
-    constexpr int APP = 64 * 16 / (int)sizeof(Cx<R>);  // amplitudes one 16-byte-per-lane load moves
+    // complex64 moves one float per lane (64 floats = 32 amplitudes per load): the swizzle can put the two
+    // floats of an LDS amplitude pair in either order of the HBM pair, so pairs cannot move as one 16-byte
+    // unit. complex128 moves one 16-byte amplitude per lane (64 amplitudes per load).
+    constexpr int APP = sizeof(R) == 4 ? 32 : 64;
     const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && T >= (uint32_t)APP;
 
     if (preloaded) {
@@ -801,19 +804,33 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
         if (pf && last_seg) {
             __syncthreads();  // every wave has its registers: LDS may be overwritten
             const uint64_t nbase = deposit((uint64_t)(next_blk - sg.first_block), full & ~P.local_mask);
-            const Cx<R> *npsi = gpsi;
             for (uint32_t c = (uint32_t)wave; c < T / APP; c += NT / 64) {
-                // lane l fills LDS positions c*APP + l*(APP/64) ...: elements swz(position), contiguous in HBM
-                const uint32_t pos = c * APP + (uint32_t)lane * (APP / 64);
-                const uint32_t e = swz(pos);
-                const uint64_t g = nbase | segtab[e >> lowc] | (e & lmask);
-                __builtin_amdgcn_global_load_lds(
-                    (const void __attribute__((address_space(1))) *)(npsi + g),
-                    (void __attribute__((address_space(3))) *)(sp + c * APP), 16, 0, 0);
-                if (ADJ)
-                    __builtin_amdgcn_global_load_lds(
-                        (const void __attribute__((address_space(1))) *)(glam + g),
-                        (void __attribute__((address_space(3))) *)(sl + c * APP), 16, 0, 0);
+                // load c covers LDS positions [c*APP, (c+1)*APP); position q holds element swz(q)
+                if constexpr (sizeof(R) == 4) {
+                    const uint32_t d = c * 64 + (uint32_t)lane;  // float d of the tile: part d&1 of position d>>1
+                    const uint32_t e = swz(d >> 1);
+                    const uint64_t g = nbase | segtab[e >> lowc] | (e & lmask);
+                    const float *src = reinterpret_cast<const float *>(gpsi + g) + (d & 1u);
+                    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                                                     (void __attribute__((address_space(3))) *)(sp + c * APP),
+                                                     4, 0, 0);
+                    if (ADJ) {
+                        const float *lsrc = reinterpret_cast<const float *>(glam + g) + (d & 1u);
+                        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)lsrc,
+                                                         (void __attribute__((address_space(3))) *)(sl + c * APP),
+                                                         4, 0, 0);
+                    }
+                } else {
+                    const uint32_t e = swz(c * APP + (uint32_t)lane);
+                    const uint64_t g = nbase | segtab[e >> lowc] | (e & lmask);
+                    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(gpsi + g),
+                                                     (void __attribute__((address_space(3))) *)(sp + c * APP),
+                                                     16, 0, 0);
+                    if (ADJ)
+                        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(glam + g),
+                                                         (void __attribute__((address_space(3))) *)(sl + c * APP),
+                                                         16, 0, 0);
+                }
             }
         }
         // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
