@@ -152,6 +152,7 @@ struct LevelArgs {
     const qv_gate *gates;
     const double *theta;
     const void *mats;     // per circuit and plan op: its 2x2 matrix (8 reals, R precision), built from theta
+    const void *smats;    // per circuit of the launch: the matrix of its shifted gate (parameter-shift variants)
     const float *fmats;   // fused blocks: kFusedFloats per block, in the order the MFMA A operand reads them
     void *psi;
     void *lam;
@@ -188,6 +189,16 @@ struct MatArgs {
     const double *theta;
     void *mats;
     int64_t n_gates;
+};
+
+// Shifted-gate matrices of a set of parameter-shift variants: entry c is the 2x2 matrix of circuit c's
+// shifted gate at its moved angle (circuits without a shift are skipped).
+struct ShiftMatArgs {
+    const DevCirc *circs;
+    const qv_gate *gates;
+    const double *theta;
+    void *smats;
+    int64_t n_circ;
 };
 
 struct ExpArgs {
@@ -263,6 +274,7 @@ int launch_grad_reduce(const GradReduceArgs &a, void *stream);
 int launch_shift_combine(const ShiftCombineArgs &a, void *stream);
 int launch_fill(double *p, int64_t n, double v, void *stream);
 int launch_matrices(const MatArgs &a, int precision, void *stream);
+int launch_shift_matrices(const ShiftMatArgs &a, int precision, void *stream);
 
 // Fused 4-qubit blocks: for every circuit and block, the product of the block's gates (16x16 complex),
 // written as the 32x32 real matrix [[Re, -Im], [Im, Re]] interleaved per amplitude, in MFMA A order.

@@ -134,16 +134,17 @@ __device__ __forceinline__ double gen_inner(int kind, Cx<R> a0, Cx<R> a1, Cx<R> 
 }
 
 // DPP move of a double: both 32-bit halves go through the same lane permutation. Lanes of rows outside
-// row_mask receive 0.
+// row_mask are left undefined (callers only use lanes that every step writes).
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_f64(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROW_MASK, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wave with DPP lane moves (no LDS); the total ends up in lane 63.
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS); the total ends up in lane 63 (other lanes
+// hold partial or undefined values).
 // quad_perm [1,0,3,2] and [2,3,0,1] sum each quad, row_half_mirror each 8 lanes, row_mirror each row of
 // 16; row_bcast15 adds row 0 into row 1 and row 2 into row 3; row_bcast31 adds lane 31 into rows 2 and 3.
 __device__ __forceinline__ double wave_sum_to_63(double v)
@@ -192,26 +193,14 @@ __device__ __forceinline__ int find_prefix(const int64_t *pre, int n, int64_t bl
     return lo;
 }
 
-// Matrix of op for circuit C: from the batch's matrix table, or built on the spot for the one gate whose
-// angle a parameter-shift variant moves.
+// Matrix of op for circuit `circ` (record C) of a launch: from the batch's matrix table, or, for the one gate
+// whose angle a parameter-shift variant moves, from the launch's shifted-gate table.
 // The table is laid out in plan order (entry mat_off + o - op_base for the plan's op o, fused-block markers
 // included), so an op's matrix can be fetched without first reading the op record.
-// Out of line: the shifted gate is rare, and its trigonometry should not hold registers in the op loops.
 template <typename R>
-__device__ __attribute__((noinline)) M2<R> shifted_matrix(const qv_gate *gates, const double *theta, int64_t gate_off,
-                                                          int64_t param_base, int32_t gate, double shift)
+__device__ __forceinline__ M2<R> op_matrix(const LevelArgs &a, const DevCirc &C, int circ, const DevOp &op, int64_t oi)
 {
-    const qv_gate g = gates[gate_off + gate];
-    const double ang = (g.param >= 0 ? theta[param_base + g.param] : g.angle) + shift;
-    M2d md;
-    gate_matrix(g.kind, ang, md);
-    return narrow<R>(md);
-}
-
-template <typename R>
-__device__ __forceinline__ M2<R> op_matrix(const LevelArgs &a, const DevCirc &C, const DevOp &op, int64_t oi)
-{
-    if (op.gate == C.shift_gate) return shifted_matrix<R>(a.gates, a.theta, C.gate_off, C.param_base, op.gate, C.shift);
+    if (op.gate == C.shift_gate) return reinterpret_cast<const M2<R> *>(a.smats)[circ];
     return reinterpret_cast<const M2<R> *>(a.mats)[C.mat_off + (oi - C.op_base)];
 }
 
@@ -306,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(LevelArgs a)
                 const double s = block_sum(acc, red);
                 if (threadIdx.x == 0) a.partials[sg.partial_base + tile * P.n_train + op.train_slot] = s;
             }
-            M2<R> m = op_matrix<R>(a, C, op, P.op_begin + k);
+            M2<R> m = op_matrix<R>(a, C, sg.circ, op, P.op_begin + k);
             if (ADJ) m = dagger_r(m);
             for (uint32_t i = threadIdx.x; i < (T >> 1); i += kBlock) {
                 const uint32_t i0 = insert0(i, p), i1 = i0 | bit;
@@ -522,8 +511,8 @@ __device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s,
 }
 
 template <int K, int N, typename R>
-__device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, int kind, R d0r, R d0i, R d1r, R d1i,
-                                         bool train, double &ip)
+__device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, R d0r, R d0i, R d1r, R d1i, bool train,
+                                         double &ip)
 {
     // of the diagonal kinds only RZ carries a parameter
     if (train) ip = r_inner<K, QV_RZ>(a, l);
@@ -532,8 +521,7 @@ __device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, int kind,
 }
 
 template <int K, int N, typename R>
-__device__ __forceinline__ void adj_gen(Regs<R, N> &a, Regs<R, N> &l, int kind, const M2<R> &m, bool train,
-                                        double &ip)
+__device__ __forceinline__ void adj_gen(Regs<R, N> &a, Regs<R, N> &l, const M2<R> &m, bool train, double &ip)
 {
     // of the dense kinds only RX carries a parameter
     if (train) ip = r_inner<K, QV_RX>(a, l);
@@ -598,14 +586,14 @@ __device__ __forceinline__ double code_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 <<
     const R d0r = mat.re[0], d1r = mat.re[3], d0i = -mat.im[0], d1i = -mat.im[3];
     switch (code) {
     K4_CASES(OC_RY, (adj_real<K>(a, l, cr, sr, train, ip)))
-    K4_CASES(OC_DIAG, (adj_diag<K>(a, l, op.kind, d0r, d0i, d1r, d1i, train, ip)))
+    K4_CASES(OC_DIAG, (adj_diag<K>(a, l, d0r, d0i, d1r, d1i, train, ip)))
     case OC_DIAG_T: {
         const bool b = (Et >> op.p0) & 1u;
         if (train) ip = t_inner_z(a, l, (int)b);
         t_scale(a, b ? d1r : d0r, b ? d1i : d0i);
         t_scale(l, b ? d1r : d0r, b ? d1i : d0i);
     } break;
-    K4_CASES(OC_GEN, (adj_gen<K>(a, l, op.kind, dagger_r(mat), train, ip)))
+    K4_CASES(OC_GEN, (adj_gen<K>(a, l, dagger_r(mat), train, ip)))
     CNOT_CASES((r_cnot<KC, KT>(a), r_cnot<KC, KT>(l)))
     K4_CASES(OC_CNOT_TR, (t_cnot<K>(a, ((Et >> op.p0) & 1u) != 0), t_cnot<K>(l, ((Et >> op.p0) & 1u) != 0)))
     case OC_CZ: {
@@ -629,6 +617,11 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // column; swapping the two halves' accumulators gives every lane its own column back.
 __device__ __forceinline__ void fused_mfma(Regs<float, 16> &v, const float *__restrict__ A, int lane)
 {
+    // all 16 A-operand loads are issued before the first product, so their latencies overlap
+    v16f am;
+#pragma unroll
+    for (int s = 0; s < 16; s++) am[s] = A[s * 64 + lane];
+    __builtin_amdgcn_sched_barrier(0);
     v16f acc0, acc1;
 #pragma unroll
     for (int q = 0; q < 16; q++) { acc0[q] = 0.f; acc1[q] = 0.f; }
@@ -636,9 +629,8 @@ __device__ __forceinline__ void fused_mfma(Regs<float, 16> &v, const float *__re
     for (int s = 0; s < 16; s++) {
         const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v.d[2 * s]), __float_as_uint(v.d[2 * s + 1]),
                                                          false, false);
-        const float a = A[s * 64 + lane];
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, __uint_as_float(sw[0]), acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, __uint_as_float(sw[1]), acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(am[s], __uint_as_float(sw[0]), acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(am[s], __uint_as_float(sw[1]), acc1, 0, 0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 16; q++) {
@@ -660,12 +652,71 @@ struct OpCursor {
     M2<R> mat;
 };
 
-// One adjoint step of a register segment, walking its ops backwards: the next op undone on (ai, li) with
-// its partial sum, result in (ao, lo). Fused-block markers carry no adjoint work (the adjoint needs the
-// state at every trainable gate, so a block's gates are undone one by one).
+// Moves the cursor `by` ops on (forward: up the list; adjoint: down) and fetches that op's record and matrix.
+template <typename R, bool ADJ>
+__device__ __forceinline__ void cursor_advance(const LevelArgs &a, const M2<R> *mtab, OpCursor<R> &oc, int by = 1)
+{
+    oc.k += by;
+    if (oc.k < oc.n) {
+        oc.oi += ADJ ? -by : by;
+        oc.op = ldu(a.ops + oc.oi);
+        oc.mat = ldu(mtab + oc.oi);
+    }
+}
+
+// Moves the cursor past fused-block markers (scalar work only).
+template <typename R, bool ADJ>
+__device__ __forceinline__ void cursor_skip_markers(const LevelArgs &a, const M2<R> *mtab, OpCursor<R> &oc)
+{
+    while (oc.k < oc.n && oc.op.kind == kFusedKind) cursor_advance<R, ADJ>(a, mtab, oc);
+}
+
+// The register-segment op loops below run two steps per iteration, reading one register set and writing
+// the other (vi -> vo, then vo -> vi), so no branch of the gate dispatch has to leave its result in the
+// registers it read. The forward loop stores from whichever set holds the result; the adjoint loop moves it
+// into the first set at its exit.
+
+// One forward step: the next op (or fused block) applied to vi, result in vo. FUSE: fused-block markers
+// are executed (complex64 with 16 amplitudes per thread); otherwise the caller keeps the cursor off them.
+template <typename R, int RB, bool FUSE>
+__device__ __forceinline__ void fwd_step(const LevelArgs &a, const DevCirc &C, int circ, const M2<R> *mtab,
+                                         OpCursor<R> &oc, uint32_t Et, int lane, const Regs<R, 1 << RB> &vi,
+                                         Regs<R, 1 << RB> &vo)
+{
+    const DevOp op = oc.op;
+    M2<R> mat = oc.mat;
+    const int64_t cur = oc.oi;
+    cursor_advance<R, false>(a, mtab, oc);
+    vo = vi;
+    if constexpr (FUSE) {
+        if (op.kind == kFusedKind) {
+            // A fused block: its product on MFMA and its gates skipped. A block that holds a parameter-shift
+            // variant's shifted gate is left to its gates, one by one (the cursor is on its first gate).
+            const int m = op.pad;
+            bool shifted = false;
+            if (C.shift_gate >= 0)
+                for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
+            if (!shifted) {
+                fused_mfma(vo, a.fmats + (C.fused_off + (op.p0 | (op.p1 << 8))) * (int64_t)kFusedFloats, lane);
+                cursor_advance<R, false>(a, mtab, oc, m);
+            }
+            return;
+        }
+    } else {
+        (void)cur;
+        (void)lane;
+    }
+    if (op.gate == C.shift_gate) mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
+    code_apply<false, RB, R>(vo, op.flags >> kOpCodeShift, op, mat, Et);
+    if constexpr (!FUSE) cursor_skip_markers<R, false>(a, mtab, oc);
+}
+
+// One adjoint step, walking the segment's ops backwards: the next op undone on (ai, li) with its partial
+// sum, result in (ao, lo). Fused-block markers carry no adjoint work (the adjoint needs the state at every
+// trainable gate, so a block's gates are undone one by one).
 template <typename R, int RB, int NT>
-__device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, const M2<R> *mtab, OpCursor<R> &oc,
-                                         uint32_t Et, bool active, int lane, int wave, double *red,
+__device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, int circ, const M2<R> *mtab,
+                                         OpCursor<R> &oc, uint32_t Et, bool active, int lane, int wave, double *red,
                                          const Regs<R, 1 << RB> &ai, const Regs<R, 1 << RB> &li,
                                          Regs<R, 1 << RB> &ao, Regs<R, 1 << RB> &lo)
 {
@@ -683,9 +734,8 @@ __device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, c
     if (oc.k >= oc.n) return;
     const DevOp op = oc.op;
     M2<R> mat = oc.mat;
-    const int64_t cur = oc.oi;
     advance();
-    if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
+    if (op.gate == C.shift_gate) mat = reinterpret_cast<const M2<R> *>(a.smats)[circ];
     double ip = code_adjoint<RB, R>(ao, lo, op.flags >> kOpCodeShift, op, mat, Et);
     if (op.flags & OP_TRAIN) {
         if (!active) ip = 0.0;
@@ -833,73 +883,34 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
                 }
             }
         }
-        // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
-        const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.mat_off - C.op_base);
-        OpCursor<R> oc;
-        oc.k = 0;
-        oc.n = S.n_ops;
-        oc.oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
-        oc.op = ldu(a.ops + oc.oi);
-        oc.mat = ldu(mtab + oc.oi);
-        if constexpr (ADJ) {
-            // Adjoint steps alternate between two register sets (av -> aw, aw -> av), so no step has to leave
-            // its result in the registers it read from and the branches of a step need no copies to agree.
-            Regs<R, N> aw, lw;
-            while (oc.k < oc.n) {
-                adj_step<R, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
-                if (oc.k >= oc.n) {
-                    av = aw;
-                    lv = lw;
-                    break;
-                }
-                adj_step<R, RB, NT>(a, C, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
-            }
-        } else {
-            // forward ops update one register set in place (within the 128-register budget of two
-            // workgroups per CU)
-            int64_t oi = oc.oi;
-            DevOp nop = oc.op;
-            M2<R> nmat = oc.mat;
-            for (int k0 = 0; k0 < S.n_ops; k0++) {
-                const DevOp op = nop;
-                M2<R> mat = nmat;
-                const int64_t cur = oi;
-                if (k0 + 1 < S.n_ops) {
-                    oi += 1;
-                    nop = ldu(a.ops + oi);
-                    nmat = ldu(mtab + oi);
-                }
-                const int kind = op.kind;
-                if (kind == kFusedKind) {
-                    // A fused block: its product on MFMA, its gates skipped (complex128, and a block that holds
-                    // a parameter-shift variant's shifted gate, run the gates one by one).
-                    if constexpr (RB == 4 && sizeof(R) == 4) {
-                        const int m = op.pad;
-                        bool shifted = false;
-                        if (C.shift_gate >= 0)
-                            for (int j = 1; j <= m; j++) shifted |= ldu(a.ops + cur + j).gate == C.shift_gate;
-                        if (!shifted) {
-                            const int f = op.p0 | (op.p1 << 8);
-                            fused_mfma(av, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
-                            k0 += m;
-                            if (k0 + 1 < S.n_ops) {
-                                oi = cur + m + 1;
-                                nop = ldu(a.ops + oi);
-                                nmat = ldu(mtab + oi);
-                            }
-                        }
+        // segment result from registers: straight to HBM (last segment of a prefetching tile), else to LDS
+        auto store = [&](const Regs<R, N> &v, const Regs<R, N> &l) {
+            if (pf && last_seg) {
+                // register j holds element Et | D_j of the tile
+                if (active && !(ADJ && sg.last)) {
+                    uint32_t et = Et, rb2[RB];
+                    asm volatile("" : "+v"(et));
+#pragma unroll
+                    for (int k = 0; k < RB; k++) {
+                        rb2[k] = rbit[k];
+                        asm volatile("" : "+s"(rb2[k]));
                     }
-                    continue;
+#pragma unroll
+                    for (int j = 0; j < N; j++) {
+                        uint32_t D = 0;
+#pragma unroll
+                        for (int k = 0; k < RB; k++)
+                            if (j >> k & 1) D |= rb2[k];
+                        const uint32_t e = et | D;
+                        const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
+                        gpsi[g] = v.get(j);
+                        if (ADJ) glam[g] = l.get(j);
+                    }
                 }
-                if (op.gate == C.shift_gate) mat = op_matrix<R>(a, C, op, cur);
-                code_apply<false, RB, R>(av, op.flags >> kOpCodeShift, op, mat, Et);
-            }
-        }
-        if (pf && last_seg) {
-            // straight to HBM from registers: register j holds element Et | D_j of the tile
-            if (active && !(ADJ && sg.last)) {
-                uint32_t et = Et, rb2[RB];
-                asm volatile("" : "+v"(et));
+            } else if (active) {
+                // recompute the addresses rather than keep 2^RB of them live through the op loop
+                uint32_t pe = PE, rb2[RB];
+                asm volatile("" : "+v"(pe));
 #pragma unroll
                 for (int k = 0; k < RB; k++) {
                     rb2[k] = rbit[k];
@@ -911,30 +922,47 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
 #pragma unroll
                     for (int k = 0; k < RB; k++)
                         if (j >> k & 1) D |= rb2[k];
-                    const uint32_t e = et | D;
-                    const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
-                    gpsi[g] = av.get(j);
-                    if (ADJ) glam[g] = lv.get(j);
+                    const uint32_t addr = pe ^ swz(D);
+                    sp[addr] = v.get(j);
+                    if (ADJ) sl[addr] = l.get(j);
                 }
             }
-        } else if (active) {
-            // recompute the addresses rather than keep 2^RB of them live through the op loop
-            uint32_t pe = PE, rb2[RB];
-            asm volatile("" : "+v"(pe));
-#pragma unroll
-            for (int k = 0; k < RB; k++) {
-                rb2[k] = rbit[k];
-                asm volatile("" : "+s"(rb2[k]));
+        };
+        // op records and matrices are fetched one op ahead, so their latency hides behind the arithmetic
+        const M2<R> *mtab = reinterpret_cast<const M2<R> *>(a.mats) + (C.mat_off - C.op_base);
+        OpCursor<R> oc;
+        oc.k = 0;
+        oc.n = S.n_ops;
+        oc.oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
+        oc.op = ldu(a.ops + oc.oi);    // a segment holds at least one op
+        oc.mat = ldu(mtab + oc.oi);
+        if constexpr (ADJ) {
+            Regs<R, N> aw, lw;
+            while (oc.k < oc.n) {
+                adj_step<R, RB, NT>(a, C, sg.circ, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
+                if (oc.k >= oc.n) {
+                    av = aw;
+                    lv = lw;
+                    break;
+                }
+                adj_step<R, RB, NT>(a, C, sg.circ, mtab, oc, Et, active, lane, wave, red, aw, lw, av, lv);
             }
-#pragma unroll
-            for (int j = 0; j < N; j++) {
-                uint32_t D = 0;
-#pragma unroll
-                for (int k = 0; k < RB; k++)
-                    if (j >> k & 1) D |= rb2[k];
-                const uint32_t addr = pe ^ swz(D);
-                sp[addr] = av.get(j);
-                if (ADJ) sl[addr] = lv.get(j);
+            store(av, lv);
+        } else {
+            constexpr bool FUSE = RB == 4 && sizeof(R) == 4;
+            if constexpr (!FUSE) cursor_skip_markers<R, false>(a, mtab, oc);
+            Regs<R, N> aw;
+            while (true) {
+                if (oc.k >= oc.n) {
+                    store(av, av);
+                    break;
+                }
+                fwd_step<R, RB, FUSE>(a, C, sg.circ, mtab, oc, Et, lane, av, aw);
+                if (oc.k >= oc.n) {
+                    store(aw, aw);
+                    break;
+                }
+                fwd_step<R, RB, FUSE>(a, C, sg.circ, mtab, oc, Et, lane, aw, av);
             }
         }
         __syncthreads();
@@ -1120,7 +1148,7 @@ __global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
     const uint64_t ngroups = 1ull << (n - 1);
     const int p = op.p0;
     const uint64_t bit = 1ull << p;
-    M2<R> m = op_matrix<R>(a, C, op, P.op_begin);
+    M2<R> m = op_matrix<R>(a, C, sg.circ, op, P.op_begin);
     if (ADJ) m = dagger_r(m);
     double acc = 0.0;
     for (uint32_t e = threadIdx.x; e < kStrideGroupsPerBlock; e += kBlock) {
@@ -1166,6 +1194,22 @@ __global__ __launch_bounds__(kBlock) void k_matrices(MatArgs a)
         gate_matrix(g.kind, ang, md);
     }
     reinterpret_cast<M2<R> *>(a.mats)[i] = narrow<R>(md);
+}
+
+// Shifted-gate matrices of parameter-shift variants (FP64 angle and trigonometry, rounded to the state
+// precision), one thread per circuit.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_shift_matrices(ShiftMatArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n_circ) return;
+    const DevCirc C = a.circs[i];
+    if (C.shift_gate < 0) return;
+    const qv_gate g = a.gates[C.gate_off + C.shift_gate];
+    const double ang = (g.param >= 0 ? a.theta[C.param_base + g.param] : g.angle) + C.shift;
+    M2d md;
+    gate_matrix(g.kind, ang, md);
+    reinterpret_cast<M2<R> *>(a.smats)[i] = narrow<R>(md);
 }
 
 // Fused-block matrices: one workgroup per (circuit, block) multiplies the block's gates into a 16x16
@@ -1642,6 +1686,16 @@ int launch_matrices(const MatArgs &a, int precision, void *stream)
     const dim3 grid((unsigned)((a.n_gates + kBlock - 1) / kBlock));
     if (precision == QV_C64) hipLaunchKernelGGL((k_matrices<float>), grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL((k_matrices<double>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_shift_matrices(const ShiftMatArgs &a, int precision, void *stream)
+{
+    if (a.n_circ <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)((a.n_circ + kBlock - 1) / kBlock));
+    if (precision == QV_C64) hipLaunchKernelGGL((k_shift_matrices<float>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_shift_matrices<double>), grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

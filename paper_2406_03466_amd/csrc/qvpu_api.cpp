@@ -277,6 +277,9 @@ struct ExecSet {
     DBuf d_circs, d_segs, d_init_fb, d_groups, d_terms, d_tv_begin, d_term_refs, d_norm_refs, d_coeff;
     DBuf d_lam_fb, d_obs_begin, d_obs, d_gref_begin, d_grefs;
     DBuf d_exp_partials, d_adj_partials;
+    // parameter-shift variants: the matrix of each circuit's shifted gate, rebuilt from theta per call
+    bool has_shift = false;
+    DBuf d_smats;
     // persistent launches (one per direction), built when every level of the direction is register-tiled
     std::vector<PersistLevel> p_fwd, p_rev;
     int64_t p_fwd_items = 0, p_rev_items = 0;
@@ -722,6 +725,7 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
     a.gates = bt.d_gates.as<qv_gate>();
     a.theta = bt.d_theta.as<double>();
     a.mats = bt.d_mats.p;
+    a.smats = es.d_smats.p;
     a.fmats = bt.d_fmats.as<float>();
     a.psi = psi;
     a.lam = lam;
@@ -808,6 +812,16 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
                                   es.init_blocks, bt.prec, s);
     });
     if (e) return e;
+    if (es.has_shift) {
+        ShiftMatArgs sa;
+        sa.circs = es.d_circs.as<DevCirc>();
+        sa.gates = bt.d_gates.as<qv_gate>();
+        sa.theta = bt.d_theta.as<double>();
+        sa.smats = es.d_smats.p;
+        sa.n_circ = es.n_circ;
+        e = logged(log, s, QV_K_MATRICES, -1, 0, [&] { return launch_shift_matrices(sa, bt.prec, s); });
+        if (e) return e;
+    }
     if (bt.ctx->persistent && es.p_fwd_ok) {
         e = enqueue_persistent(bt, es, dp, 0, psi, nullptr, s, log);
         if (e) return e;
@@ -1519,6 +1533,8 @@ static qv_status ensure_param_shift(qv_batch bt)
         }
         build_expectation(*es, ov, obs_of, out_base, ob, false, bt->amp_bytes);
         HIPCHK(upload_set(*es, false));
+        es->has_shift = true;
+        HIPCHK(es->d_smats.alloc((size_t)es->n_circ * 8 * (bt->amp_bytes / 2)));
         bt->ps_chunk_var0.push_back(v - es->n_circ);
         max_chunk_var = std::max<int64_t>(max_chunk_var, es->n_circ);
         bt->ps_chunks.push_back(std::move(es));
