@@ -652,6 +652,18 @@ struct OpCursor {
     M2<R> mat;
 };
 
+// Waits for the scalar loads that produced x right here. A parameter-shift variant's shifted matrix is loaded
+// on a rare path; waiting inside that path keeps the wait (which covers every outstanding scalar load,
+// including the next op's prefetch) out of the common path where the two meet.
+template <typename T>
+__device__ __forceinline__ void scalar_wait(const T &x)
+{
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, &x, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) asm volatile("" ::"s"(w[i]));
+}
+
 // Moves the cursor `by` ops on (forward: up the list; adjoint: down) and fetches that op's record and matrix.
 template <typename R, bool ADJ>
 __device__ __forceinline__ void cursor_advance(const LevelArgs &a, const M2<R> *mtab, OpCursor<R> &oc, int by = 1)
@@ -706,7 +718,10 @@ __device__ __forceinline__ void fwd_step(const LevelArgs &a, const DevCirc &C, i
         (void)cur;
         (void)lane;
     }
-    if (op.gate == C.shift_gate) mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
+    if (op.gate == C.shift_gate) {
+        mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
+        scalar_wait(mat);
+    }
     code_apply<false, RB, R>(vo, op.flags >> kOpCodeShift, op, mat, Et);
     if constexpr (!FUSE) cursor_skip_markers<R, false>(a, mtab, oc);
 }
@@ -735,7 +750,10 @@ __device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, i
     const DevOp op = oc.op;
     M2<R> mat = oc.mat;
     advance();
-    if (op.gate == C.shift_gate) mat = reinterpret_cast<const M2<R> *>(a.smats)[circ];
+    if (op.gate == C.shift_gate) {
+        mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
+        scalar_wait(mat);
+    }
     double ip = code_adjoint<RB, R>(ao, lo, op.flags >> kOpCodeShift, op, mat, Et);
     if (op.flags & OP_TRAIN) {
         if (!active) ip = 0.0;
