@@ -138,6 +138,9 @@ typedef struct qv_batch_s *qv_batch;
  *   "fusion"         : "off" (default), "on" (runs of >= 6 gates) or a minimum run length: within a
  *                      register segment, consecutive gates acting only on its 4 register qubits are
  *                      multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);
+ *   "fold_cnots"     : "on" (default) or "off": runs of CNOTs at either end of a register segment
+ *                      permute the tile's amplitudes, so they are folded into the segment's LDS load and
+ *                      store addresses instead of running as ops (same results, no arithmetic);
  *   "autotune"       : "off", "cached" (default: reuse a choice stored by an earlier search) or
  *                      "search" (on the first forward call, time one forward pass for each candidate tile
  *                      size and contiguous-run length and keep the fastest; stored in the text file named
@@ -231,7 +234,7 @@ typedef struct {
     int32_t first_gate;   /* circuit index of the pass's first gate in execution order */
     int32_t contiguous_low; /* qubits 0..contiguous_low-1 are all local (length of contiguous runs) */
     int32_t n_fused;      /* fused blocks among the pass's gates */
-    int32_t pad;
+    int32_t n_folded;     /* CNOTs folded into register-segment LDS addressing ("tiled" engine) */
 } qv_pass_info;
 
 /* Plans one circuit without a device, as qv_batch_create would for a batch with the given engine

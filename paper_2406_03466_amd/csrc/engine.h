@@ -60,6 +60,17 @@ struct DevSeg {
     int32_t n_ops;
     int8_t rpos[8];
     int8_t tpos[16];
+    // CNOT runs folded into the segment's LDS addressing, in program order; entry k (byte k) is the local
+    // control position | target position << 4, unused entries 0xFF. `lead` runs before the segment's ops,
+    // `trail` after them.
+    uint64_t lead;
+    uint64_t trail;
+    int8_t n_lead, n_trail;
+    int8_t pad[2];
+    // images of the register bits (1 << rpos[k]) under the inverse of the leading run (rimg_lead) and under
+    // the trailing run (rimg_trail)
+    uint16_t rimg_lead[4], rimg_trail[4];
+    int32_t pad2;
 };
 
 struct DevPass {

@@ -762,6 +762,57 @@ __device__ __forceinline__ void adj_step(const LevelArgs &a, const DevCirc &C, i
     }
 }
 
+// A run of CNOTs folded into a segment's addressing, applied to a tile index e (e ^= bit c << t for each,
+// a linear map on the index bits). w holds the run's eight entries (byte k: control | target << 4; unused
+// entries are 0xFF, bit 15 of a tile index being always clear); REV applies them last to first, which is
+// the inverse map (every CNOT is its own inverse). Straight-line, with no branch even for an empty run:
+// a loop or branch here, next to the op loop, makes the compiler keep the op loop's register sets far
+// less tidily (copies in every gate branch).
+template <bool REV>
+__device__ __forceinline__ uint32_t cnot_run(uint32_t e, uint64_t w)
+{
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int k = REV ? 7 - i : i;
+        const uint32_t b = (uint32_t)(w >> (8 * k)) & 0xFFu;
+        e ^= ((e >> (b & 15u)) & 1u) << (b >> 4);
+    }
+    return e;
+}
+
+// The folded CNOT runs of a segment, by scalar loads: entries, lengths and the register-bit images.
+struct SegRuns {
+    uint64_t lead, trail;
+    int n_lead, n_trail;
+    uint32_t rimg_lead[4], rimg_trail[4];
+};
+
+__device__ __forceinline__ SegRuns seg_runs(const DevSeg *sp)
+{
+    static_assert(offsetof(DevSeg, lead) % 8 == 0 && offsetof(DevSeg, trail) == offsetof(DevSeg, lead) + 8 &&
+                      offsetof(DevSeg, n_lead) == offsetof(DevSeg, trail) + 8 &&
+                      offsetof(DevSeg, n_trail) == offsetof(DevSeg, n_lead) + 1 &&
+                      offsetof(DevSeg, rimg_lead) == offsetof(DevSeg, n_lead) + 4 &&
+                      offsetof(DevSeg, rimg_trail) == offsetof(DevSeg, rimg_lead) + 8,
+                  "DevSeg run layout");
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(sp) + offsetof(DevSeg, lead) / 4;
+    SegRuns r;
+    r.lead = (uint64_t)ldu(w) | ((uint64_t)ldu(w + 1) << 32);
+    r.trail = (uint64_t)ldu(w + 2) | ((uint64_t)ldu(w + 3) << 32);
+    const uint32_t nn = ldu(w + 4);
+    r.n_lead = (int)(nn & 0xFFu);
+    r.n_trail = (int)((nn >> 8) & 0xFFu);
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const uint32_t a = ldu(w + 5 + i), b = ldu(w + 7 + i);
+        r.rimg_lead[2 * i] = a & 0xFFFFu;
+        r.rimg_lead[2 * i + 1] = a >> 16;
+        r.rimg_trail[2 * i] = b & 0xFFFFu;
+        r.rimg_trail[2 * i + 1] = b >> 16;
+    }
+    return r;
+}
+
 // Amplitudes each thread moves between HBM and LDS per batch of independent loads (or stores).
 template <typename R>
 constexpr int tile_batch() { return sizeof(R) == 4 ? 16 : 8; }
@@ -853,22 +904,42 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
 #pragma unroll
         for (int m = 0; m < 16; m++)
             if (m < tbits && (tid >> m & 1u)) Et |= 1u << S.tpos[m];
-        const uint32_t PE = swz(Et);
         uint32_t rbit[RB];
 #pragma unroll
         for (int k = 0; k < RB; k++) rbit[k] = 1u << S.rpos[k];
+        // Register j of this thread holds tile element Et | D_j. The segment's folded CNOT runs permute the
+        // tile, so the element is read from / written to its permuted position: forward passes read through
+        // the inverse of the leading run and write through the trailing run; the adjoint undoes the segment,
+        // so it reads through the trailing run and writes through the inverse of the leading run.
+        // The store side (ES, rs) is mapped here too, so the runs hold no registers through the op loop.
         Regs<R, N> av, lv;
+        uint32_t ES, rs[RB];
+        bool remap;  // a folded run moves amplitudes between threads
+        {
+            const SegRuns sr = seg_runs(a.rsegs + P.seg_begin + si);
+            remap = (sr.n_lead | sr.n_trail) != 0;
+            ES = ADJ ? cnot_run<true>(Et, sr.lead) : cnot_run<false>(Et, sr.trail);
+            const uint32_t PL = swz(ADJ ? cnot_run<false>(Et, sr.trail) : cnot_run<true>(Et, sr.lead));
+            uint32_t rl[RB];
 #pragma unroll
-        for (int j = 0; j < N; j++) {
-            uint32_t D = 0;
+            for (int k = 0; k < RB; k++) {
+                rs[k] = ADJ ? sr.rimg_lead[k] : sr.rimg_trail[k];
+                rl[k] = ADJ ? sr.rimg_trail[k] : sr.rimg_lead[k];
+            }
 #pragma unroll
-            for (int k = 0; k < RB; k++)
-                if (j >> k & 1) D |= rbit[k];
-            const uint32_t addr = PE ^ swz(D);
-            av.set(j, sp[addr]);
-            if (ADJ) lv.set(j, sl[addr]);
+            for (int j = 0; j < N; j++) {
+                uint32_t D = 0;
+#pragma unroll
+                for (int k = 0; k < RB; k++)
+                    if (j >> k & 1) D ^= rl[k];
+                const uint32_t addr = PL ^ swz(D);
+                av.set(j, sp[addr]);
+                if (ADJ) lv.set(j, sl[addr]);
+            }
         }
         const bool last_seg = s0 == P.n_seg - 1;
+        // With a folded run, a thread's stores may land where another thread loads: every wave loads first.
+        if (remap && !(pf && last_seg)) __syncthreads();
         if (pf && last_seg) {
             __syncthreads();  // every wave has its registers: LDS may be overwritten
             const uint64_t nbase = deposit((uint64_t)(next_blk - sg.first_block), full & ~P.local_mask);
@@ -903,43 +974,37 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
         }
         // segment result from registers: straight to HBM (last segment of a prefetching tile), else to LDS
         auto store = [&](const Regs<R, N> &v, const Regs<R, N> &l) {
-            if (pf && last_seg) {
-                // register j holds element Et | D_j of the tile
-                if (active && !(ADJ && sg.last)) {
-                    uint32_t et = Et, rb2[RB];
-                    asm volatile("" : "+v"(et));
+            // recompute the addresses rather than keep 2^RB of them live through the op loop
+            uint32_t es = ES, rb2[RB];
+            asm volatile("" : "+v"(es));
 #pragma unroll
-                    for (int k = 0; k < RB; k++) {
-                        rb2[k] = rbit[k];
-                        asm volatile("" : "+s"(rb2[k]));
-                    }
+            for (int k = 0; k < RB; k++) {
+                rb2[k] = rs[k];
+                asm volatile("" : "+s"(rb2[k]));
+            }
+            if (pf && last_seg) {
+                // register j holds tile element es ^ D_j
+                if (active && !(ADJ && sg.last)) {
 #pragma unroll
                     for (int j = 0; j < N; j++) {
                         uint32_t D = 0;
 #pragma unroll
                         for (int k = 0; k < RB; k++)
-                            if (j >> k & 1) D |= rb2[k];
-                        const uint32_t e = et | D;
+                            if (j >> k & 1) D ^= rb2[k];
+                        const uint32_t e = es ^ D;
                         const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
                         gpsi[g] = v.get(j);
                         if (ADJ) glam[g] = l.get(j);
                     }
                 }
             } else if (active) {
-                // recompute the addresses rather than keep 2^RB of them live through the op loop
-                uint32_t pe = PE, rb2[RB];
-                asm volatile("" : "+v"(pe));
-#pragma unroll
-                for (int k = 0; k < RB; k++) {
-                    rb2[k] = rbit[k];
-                    asm volatile("" : "+s"(rb2[k]));
-                }
+                const uint32_t pe = swz(es);
 #pragma unroll
                 for (int j = 0; j < N; j++) {
                     uint32_t D = 0;
 #pragma unroll
                     for (int k = 0; k < RB; k++)
-                        if (j >> k & 1) D |= rb2[k];
+                        if (j >> k & 1) D ^= rb2[k];
                     const uint32_t addr = pe ^ swz(D);
                     sp[addr] = v.get(j);
                     if (ADJ) sl[addr] = l.get(j);

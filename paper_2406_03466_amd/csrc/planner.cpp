@@ -9,6 +9,7 @@
 #include "planner.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace qv {
 
@@ -105,7 +106,7 @@ void segment_pass(PlanPass &pp, int reg_bits)
     number_train_slots(pp);
 }
 
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, int fuse_min)
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, int fuse_min, int fold)
 {
     Plan pl;
     const int n = in.n;
@@ -191,10 +192,84 @@ Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits, in
         pp.local_mask = L;
         finish_pass(pp, n);
         segment_pass(pp, reg_bits);
+        if (fold) fold_boundary_cnots(pp);
         pl.passes.push_back(pp);
     }
     if (fuse_min > 0) fuse_segments(pl, fuse_min);
     return pl;
+}
+
+void fold_boundary_cnots(PlanPass &pp)
+{
+    if (pp.segs.empty()) return;
+    std::vector<PlanSeg> segs;
+    std::vector<PlanOp> ops;
+    for (size_t s = 0; s < pp.segs.size(); s++) {
+        PlanSeg sg = pp.segs[s];
+        const int b = sg.op_begin, e = sg.op_begin + sg.n_ops;
+        int i = b, j = e;
+        while (i < j && pp.ops[i].kind == QV_CNOT && (int)sg.lead.size() < kMaxFoldedCnots) sg.lead.push_back(pp.ops[i++]);
+        if (i == j) {
+            // only CNOTs: they run between the neighbouring segments
+            if (!segs.empty() && (int)(segs.back().trail.size() + sg.lead.size()) <= kMaxFoldedCnots) {
+                for (const PlanOp &op : sg.lead) segs.back().trail.push_back(op);
+                continue;
+            }
+            if (s + 1 < pp.segs.size()) {
+                // hand them to the next segment's leading run (checked against the cap there)
+                PlanSeg &nx = pp.segs[s + 1];
+                std::vector<PlanOp> merged = sg.lead;
+                const int nb = nx.op_begin, ne = nx.op_begin + nx.n_ops;
+                int k = nb;
+                while (k < ne && pp.ops[k].kind == QV_CNOT) merged.push_back(pp.ops[k++]);
+                if ((int)merged.size() <= kMaxFoldedCnots) {
+                    nx.lead = merged;
+                    nx.n_ops -= k - nb;
+                    nx.op_begin = k;
+                    continue;
+                }
+            }
+            // no neighbour can take them: keep the last one as an op, so the segment is not empty
+            sg.lead.pop_back();
+            i--;
+        }
+        std::vector<PlanOp> tail;
+        while (j - 1 > i && pp.ops[j - 1].kind == QV_CNOT && (int)tail.size() < kMaxFoldedCnots) tail.push_back(pp.ops[--j]);
+        std::reverse(tail.begin(), tail.end());
+        sg.trail = tail;
+        sg.op_begin = (int)ops.size();
+        for (int k = i; k < j; k++) ops.push_back(pp.ops[k]);
+        sg.n_ops = j - i;
+        segs.push_back(sg);
+    }
+    pp.ops = ops;
+    pp.segs = segs;
+    number_train_slots(pp);
+}
+
+std::vector<int> pass_gate_order(const PlanPass &pp)
+{
+    std::vector<int> g;
+    if (pp.segs.empty()) {
+        for (const PlanOp &op : pp.ops)
+            if (op.kind != kFusedKind) g.push_back(op.gate);
+        return g;
+    }
+    for (const PlanSeg &sg : pp.segs) {
+        for (const PlanOp &op : sg.lead) g.push_back(op.gate);
+        for (int k = 0; k < sg.n_ops; k++)
+            if (pp.ops[sg.op_begin + k].kind != kFusedKind) g.push_back(pp.ops[sg.op_begin + k].gate);
+        for (const PlanOp &op : sg.trail) g.push_back(op.gate);
+    }
+    return g;
+}
+
+int pass_gate_count(const PlanPass &pp)
+{
+    int n = 0;
+    for (const PlanOp &op : pp.ops) n += op.kind != kFusedKind ? 1 : 0;
+    for (const PlanSeg &sg : pp.segs) n += (int)(sg.lead.size() + sg.trail.size());
+    return n;
 }
 
 void fuse_segments(Plan &pl, int fuse_min)
@@ -348,6 +423,32 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
             ds.n_ops = sg.n_ops;
             for (int k = 0; k < 8; k++) ds.rpos[k] = k < (int)sg.rpos.size() ? (int8_t)sg.rpos[k] : (int8_t)-1;
             for (int m = 0; m < 16; m++) ds.tpos[m] = m < (int)sg.tpos.size() ? (int8_t)sg.tpos[m] : (int8_t)-1;
+            auto pack = [&](const std::vector<PlanOp> &run, uint64_t &out) {
+                // positions index the tile (< t <= 15), so the folded map stays inside it
+                if (run.size() > (size_t)kMaxFoldedCnots) std::abort();
+                out = ~0ull;  // unused entries: 0xFF, a no-op on tile indices (< 2^15)
+                for (size_t k = 0; k < run.size(); k++) {
+                    const int c = pos[run[k].q0], t = pos[run[k].q1];
+                    if (c < 0 || t < 0 || c >= pp.t || t >= pp.t || c == t || pp.t > 15) std::abort();
+                    out &= ~(0xFFull << (8 * k));
+                    out |= (uint64_t)(c | (t << 4)) << (8 * k);
+                }
+                return (int8_t)run.size();
+            };
+            ds.n_lead = pack(sg.lead, ds.lead);
+            ds.n_trail = pack(sg.trail, ds.trail);
+            auto apply = [&](uint32_t e, const std::vector<PlanOp> &run, bool rev) {
+                for (size_t i = 0; i < run.size(); i++) {
+                    const PlanOp &op = run[rev ? run.size() - 1 - i : i];
+                    e ^= ((e >> pos[op.q0]) & 1u) << pos[op.q1];
+                }
+                return e;
+            };
+            for (int k = 0; k < 4; k++) {
+                const uint32_t bit = k < (int)sg.rpos.size() ? 1u << sg.rpos[k] : 0u;
+                ds.rimg_lead[k] = (uint16_t)apply(bit, sg.lead, true);
+                ds.rimg_trail[k] = (uint16_t)apply(bit, sg.trail, false);
+            }
             segs.push_back(ds);
         }
         passes.push_back(d);

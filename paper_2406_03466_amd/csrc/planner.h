@@ -32,7 +32,13 @@ struct PlanSeg {
     std::vector<int> tpos;  // thread bit -> local position
     int op_begin = 0;       // first op of the segment in the pass's (reordered) op list
     int n_ops = 0;
+    // CNOT runs folded into the segment's LDS addressing (they permute the tile's amplitudes): `lead` runs
+    // before the segment's ops, `trail` after them, each in program order.
+    std::vector<PlanOp> lead, trail;
 };
+
+// Most CNOTs one segment boundary may fold (per run; longer runs keep the rest as ops).
+constexpr int kMaxFoldedCnots = 8;
 
 struct PlanPass {
     uint64_t local_mask = 0;
@@ -57,10 +63,21 @@ constexpr int kMaxTrainPerPass = 256;
 // amplitudes per thread.
 // fuse_min > 0 turns every run of at least fuse_min consecutive gates of a segment that act on register
 // qubits only into a fused block (a marker op followed by the run).
-Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0, int fuse_min = 0);
+// fold > 0 folds the CNOT runs at register-segment boundaries into the segments' addressing.
+Plan plan_tiled(const PlanInput &in, int tile_qubits, int lowc, int reg_bits = 0, int fuse_min = 0, int fold = 1);
 
 // Splits one pass into register segments (reorders its ops; dependencies are kept).
 void segment_pass(PlanPass &pp, int reg_bits);
+
+// Moves the CNOT runs at the two ends of every register segment out of its op list into its lead / trail
+// lists (a segment left without ops hands its CNOTs to a neighbour).
+void fold_boundary_cnots(PlanPass &pp);
+
+// Gates of a pass in execution order (folded CNOTs included, fused-block markers left out).
+std::vector<int> pass_gate_order(const PlanPass &pp);
+
+// Gates of a pass: its ops other than fused-block markers, plus its folded CNOTs.
+int pass_gate_count(const PlanPass &pp);
 
 // Inserts fused-block markers into the segments of a plan's passes; numbers the blocks plan-wide.
 void fuse_segments(Plan &pl, int fuse_min);

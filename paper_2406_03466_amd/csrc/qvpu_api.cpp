@@ -119,6 +119,7 @@ struct qv_ctx_s {
     int autotune = 1;           // 0 off, 1 cached (use a stored choice), 2 search (time candidates once)
     int persistent = 0;         // 1: one persistent work-queue launch per direction instead of one per level
     int fuse_min = 0;           // >0: fuse runs of at least this many register-local gates into MFMA blocks
+    int fold_cnots = 1;         // 1: CNOT runs at register-segment boundaries fold into the LDS addressing
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
@@ -955,6 +956,10 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
                 if (fm < 1 || fm > 64) return fail(QV_E_INVALID, "fusion must be \"off\", \"on\" or a minimum run length 1..64");
                 c->fuse_min = fm;
             }
+        } else if (k == "fold_cnots") {
+            if (v == "on" || v == "1" || v == "true") c->fold_cnots = 1;
+            else if (v == "off" || v == "0" || v == "false") c->fold_cnots = 0;
+            else return fail(QV_E_INVALID, "fold_cnots must be \"on\" or \"off\"");
         } else if (k == "fusion_k" || k == "precision" || k == "deterministic") {
             /* accepted for compatibility; the current planner ignores them */
         } else {
@@ -1073,7 +1078,8 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
         const int lowc = bt->contig;
         const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
         const int fm = (ctx->engine == 0) ? ctx->fuse_min : 0;
-        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin) : plan_tiled(pin, bt->tile_qubits, lowc, rb, fm));
+        bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin)
+                                              : plan_tiled(pin, bt->tile_qubits, lowc, rb, fm, ctx->fold_cnots));
     }
     // device plan arrays
     auto dp = std::make_unique<DevPlans>();
@@ -1754,20 +1760,20 @@ qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gate
         o.qubits = pp.t;
         int32_t nf = 0;
         for (const PlanOp &op : pp.ops) nf += op.kind == kFusedKind ? 1 : 0;
-        o.n_ops = (int32_t)pp.ops.size() - nf;
+        o.n_ops = (int32_t)pass_gate_count(pp);
         o.n_fused = nf;
+        o.n_folded = 0;
+        for (const PlanSeg &sg : pp.segs) o.n_folded += (int32_t)(sg.lead.size() + sg.trail.size());
         o.n_trainable = pp.n_train;
         o.n_segments = (int32_t)pp.segs.size();
-        o.first_gate = -1;
-        for (const PlanOp &op : pp.ops)
-            if (op.kind != kFusedKind) { o.first_gate = op.gate; break; }
+        const std::vector<int> g = pass_gate_order(pp);
+        o.first_gate = g.empty() ? -1 : g[0];
         o.contiguous_low = pp.lowc;
     }
     if (order) {
         int64_t k = 0;
         for (const PlanPass &pp : pl.passes)
-            for (const PlanOp &op : pp.ops)
-                if (op.kind != kFusedKind) order[k++] = op.gate;
+            for (int gi : pass_gate_order(pp)) order[k++] = gi;
     }
     return ok();
 }

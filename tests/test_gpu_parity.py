@@ -385,7 +385,8 @@ ALL_KINDS = [W.H, W.X, W.Y, W.Z, W.S, W.T, W.RX, W.RY, W.RZ, W.CNOT, W.CZ]
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("opts", [{}, {"fusion": 2}, {"tile_qubits": 7}, {"engine": "lds"}, {"engine": "stride"}])
+@pytest.mark.parametrize("opts", [{}, {"fusion": 2}, {"tile_qubits": 7}, {"fold_cnots": "off"}, {"engine": "lds"},
+                                  {"engine": "stride"}])
 def test_all_gate_kinds(qv, prec, opts):
     """Random circuits over all eleven gate kinds (every op code of the register segments: dense, real and
     diagonal one-qubit gates on register and thread qubits, CNOT with register or thread control, CZ):
@@ -404,6 +405,28 @@ def test_all_gate_kinds(qv, prec, opts):
     check(g_ad, g_ref, prec, s * float(np.sum(np.abs(up))), "adjoint grad")
     g_ps, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
     check(g_ps, g_ref, prec, s * float(np.sum(np.abs(up))), "param-shift grad")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("opts", [{}, {"fold_cnots": "off"}, {"fusion": 4}, {"tile_qubits": 8}])
+def test_cnot_runs_folded(qv, prec, opts):
+    """Hardware-efficient circuits (a CNOT ladder after every rotation layer) and CNOT-heavy random circuits:
+    the CNOT runs at register-segment ends fold into the LDS addressing by default. Energies and adjoint
+    and parameter-shift gradients against the oracle, with folding on and off."""
+    say(f"cnot runs prec={prec} opts={opts}")
+    for wl in (W.hea_vqe(12, 5, 6, seed_index=21), W.hea_vqe(14, 3, 6, seed_index=22),
+               W.random_batch(8, 9, 13, 40, 160, 4, seed_index=23, kinds=[W.RY, W.RZ, W.CNOT, W.CNOT, W.CNOT])):
+        e_ref, _, _, _ = oracle.expectations(wl)
+        up = np.linspace(1.0, -0.5, wl.B)
+        g_ref = oracle.grad_adjoint(wl, up)
+        b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+        e, _ = b.expectations(want_terms=False)
+        s = obs_scale(wl)
+        check(e, e_ref, prec, s, "energy")
+        g_ad, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+        check(g_ad, g_ref, prec, s * float(np.sum(np.abs(up))), "adjoint grad")
+        g_ps, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
+        check(g_ps, g_ref, prec, s * float(np.sum(np.abs(up))), "param-shift grad")
 
 
 def test_qcl20_full_size_complex128(qv):

@@ -99,3 +99,43 @@ def test_fused_plans_keep_every_gate(fuse_min):
     assert [p["local_mask"] for p in plain] == [p["local_mask"] for p in passes]
     # the stride engine never fuses
     assert sum(p["n_fused"] for p in qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 2, fuse_min=fuse_min)) == 0
+
+
+def test_boundary_cnots_are_folded():
+    """CNOT runs at register-segment ends are folded into the segments' addressing: the circuit-learning
+    ansatz (CNOT ladders after every rotation layer) has some in every plan, every gate is still scheduled
+    once in a valid order, and the LDS and stride engines (no register segments) fold none."""
+    wl = W.config3(8)
+    gates = wl.circuit(0)
+    for fuse_min in (0, 8):
+        passes, order = qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, 0, with_order=True, fuse_min=fuse_min)
+        _check_plan(20, gates, passes, order)
+        folded = sum(p["n_folded"] for p in passes)
+        n_cnot = int(np.sum(gates["kind"] == W.CNOT))
+        assert 0 < folded <= n_cnot
+    for engine in (1, 2):
+        assert sum(p["n_folded"] for p in qvpu.plan_circuit(20, gates, 13, qvpu.QV_C64, engine)) == 0
+
+
+def test_folded_order_matches_state():
+    """Running a CNOT-heavy circuit in the planned order (folded CNOTs at their segment ends) gives the
+    program-order state (oracle, complex128)."""
+    rng = np.random.default_rng(11)
+    n = 9
+    circ = []
+    for layer in range(6):
+        for q in range(n):
+            circ.append(W.gate(W.RY, q, -1, len(circ), 0.0))
+        for q in range(n - 1):
+            circ.append(W.gate(W.CNOT, q, q + 1))
+        for _ in range(4):
+            a, b = rng.choice(n, size=2, replace=False)
+            circ.append(W.gate(W.CNOT, int(a), int(b)))
+    gates = np.array(circ, W.GATE_DTYPE)
+    theta = rng.uniform(0, 2 * np.pi, size=len(circ))
+    passes, order = qvpu.plan_circuit(n, gates, 6, qvpu.QV_C64, 0, with_order=True)
+    _check_plan(n, gates, passes, order)
+    assert sum(p["n_folded"] for p in passes) > 0
+    s0 = oracle.final_state(n, gates, theta)
+    s1 = oracle.final_state(n, gates[order], theta)
+    assert np.max(np.abs(s0 - s1)) < 1e-12
