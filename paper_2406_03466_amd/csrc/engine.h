@@ -84,6 +84,11 @@ struct DevPass {
     int32_t seg_begin;    // register-tiled passes: segments [seg_begin, seg_begin + n_seg)
     int32_t n_seg;        // 0: the pass runs op by op in LDS
     int8_t lq[16];        // local position -> qubit, ascending
+    // A circuit's first pass, undone last by the adjoint, needs no work below its first trainable op: the
+    // reverse sweep stops there. first_train: index (in the op array) of that op; adj_last_nseg: segments,
+    // counted from the pass's end, that hold it or later ops (0: the pass has no trainable op).
+    int32_t first_train;
+    int32_t adj_last_nseg;
 };
 
 struct DevCirc {

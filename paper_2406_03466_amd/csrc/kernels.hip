@@ -850,7 +850,11 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
     // floats of an LDS amplitude pair in either order of the HBM pair, so pairs cannot move as one 16-byte
     // unit. complex128 moves one 16-byte amplitude per lane (64 amplitudes per load).
     constexpr int APP = sizeof(R) == 4 ? 32 : 64;
-    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && T >= (uint32_t)APP;
+    // The adjoint's sweep over a circuit's first pass stops at its first trainable op (nothing below it is
+    // needed): only the last nseg segments run, the lowest of them only down to that op.
+    const bool stop_early = ADJ && sg.last;
+    const int nseg = stop_early ? P.adj_last_nseg : P.n_seg;
+    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && T >= (uint32_t)APP && nseg > 0;
 
     if (preloaded) {
         // this tile was loaded by the previous tile's last segment (same pass: the run table is in place)
@@ -897,7 +901,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
     const uint32_t tid = threadIdx.x & tmask;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    for (int s0 = 0; s0 < P.n_seg; s0++) {
+    for (int s0 = 0; s0 < nseg; s0++) {
         const int si = ADJ ? P.n_seg - 1 - s0 : s0;
         const DevSeg S = ldu(a.rsegs + P.seg_begin + si);
         uint32_t Et = 0;
@@ -937,7 +941,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
                 if (ADJ) lv.set(j, sl[addr]);
             }
         }
-        const bool last_seg = s0 == P.n_seg - 1;
+        const bool last_seg = s0 == nseg - 1;
         // With a folded run, a thread's stores may land where another thread loads: every wave loads first.
         if (remap && !(pf && last_seg)) __syncthreads();
         if (pf && last_seg) {
@@ -1016,6 +1020,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
         OpCursor<R> oc;
         oc.k = 0;
         oc.n = S.n_ops;
+        if (stop_early && S.op_begin < P.first_train) oc.n = S.op_begin + S.n_ops - P.first_train;
         oc.oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
         oc.op = ldu(a.ops + oc.oi);    // a segment holds at least one op
         oc.mat = ldu(mtab + oc.oi);

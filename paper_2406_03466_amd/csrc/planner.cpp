@@ -9,6 +9,7 @@
 #include "planner.h"
 
 #include <algorithm>
+#include <climits>
 #include <cstdlib>
 
 namespace qv {
@@ -417,6 +418,15 @@ void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp>
             o.pad = 0;
             ops.push_back(o);
         }
+        d.first_train = INT32_MAX;
+        for (size_t i = 0; i < pp.ops.size(); i++)
+            if (pp.ops[i].kind != kFusedKind && pp.ops[i].train_slot >= 0) {
+                d.first_train = d.op_begin + (int32_t)i;
+                break;
+            }
+        d.adj_last_nseg = 0;
+        for (const PlanSeg &sg : pp.segs)
+            if (d.op_begin + sg.op_begin + sg.n_ops > d.first_train) d.adj_last_nseg++;
         for (const PlanSeg &sg : pp.segs) {
             DevSeg ds{};
             ds.op_begin = d.op_begin + sg.op_begin;

@@ -188,11 +188,18 @@ static double op_flops(int kind)
 }
 
 // Per amplitude: forward applies each gate once; the adjoint un-applies it from psi and lambda and takes
-// the imaginary part of one complex product per trainable gate (4).
-static double pass_flops(const PlanPass &pp, bool adjoint)
+// the imaginary part of one complex product per trainable gate (4). The adjoint's sweep over a circuit's
+// first register-tiled pass (last_rev) stops at its first trainable gate, so the gates below it count nothing.
+static double pass_flops(const PlanPass &pp, bool adjoint, bool last_rev = false)
 {
+    size_t from = 0;
+    if (adjoint && last_rev && !pp.segs.empty()) {
+        from = pp.ops.size();
+        for (size_t i = 0; i < pp.ops.size(); i++)
+            if (pp.ops[i].kind != kFusedKind && pp.ops[i].train_slot >= 0) { from = i; break; }
+    }
     double f = 0.0;
-    for (const PlanOp &op : pp.ops) f += op_flops(op.kind);
+    for (size_t i = from; i < pp.ops.size(); i++) f += op_flops(pp.ops[i].kind);
     return adjoint ? 2.0 * f + 4.0 * pp.n_train : f;
 }
 
@@ -487,7 +494,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         // (the circuit's last reverse pass: read only)
                         const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
                         lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : (s.last ? 2 : 4)) * S;
-                        lv.flops += pass_flops(pp, dir == 1) * (double)((int64_t)1 << es.circs[c].n);
+                        lv.flops += pass_flops(pp, dir == 1, s.last != 0) * (double)((int64_t)1 << es.circs[c].n);
                     }
                     if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
                 }
