@@ -429,6 +429,61 @@ def test_cnot_runs_folded(qv, prec, opts):
         check(g_ps, g_ref, prec, s * float(np.sum(np.abs(up))), "param-shift grad")
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_adjoint_stops_at_first_trainable_gate(qv, prec):
+    """The reverse sweep over a circuit's first pass stops at its first trainable gate. Circuits whose first
+    passes start with long runs of fixed gates (and, with small tiles, first passes with no trainable gate at
+    all, which skip their segment work and the next-tile prefetch): adjoint gradients against the oracle."""
+    say(f"adjoint early stop prec={prec}")
+    rng = np.random.default_rng(31)
+    circuits = []
+    for n in (11, 12, 14):
+        g = []
+        for _ in range(3 * n):   # fixed prefix: H, CNOT ladders, fixed rotations
+            q = int(rng.integers(0, n))
+            k = int(rng.integers(0, 3))
+            if k == 0:
+                g.append(W.gate(W.H, q))
+            elif k == 1:
+                g.append(W.gate(W.CNOT, q, (q + 1) % n))
+            else:
+                g.append(W.gate(W.RY, q, -1, -1, float(rng.uniform(0, 6.28))))
+        p = 0
+        for _ in range(4 * n):
+            q = int(rng.integers(0, n))
+            kind = [W.RY, W.RZ, W.RX][int(rng.integers(0, 3))]
+            g.append(W.gate(kind, q, -1, p, 0.0))
+            p += 1
+            if rng.random() < 0.3:
+                a, b2 = rng.choice(n, size=2, replace=False)
+                g.append(W.gate(W.CNOT, int(a), int(b2)))
+        circuits.append((n, g, p))
+    # a first pass with no trainable gate at all: a fixed block on qubits 0..5 fills a 6-qubit tile
+    n, g, p = 12, [], 0
+    for i in range(30):
+        q = i % 6
+        g.append(W.gate(W.H, q) if i % 3 == 0 else
+                 (W.gate(W.CNOT, q, (q + 1) % 6) if i % 3 == 1 else W.gate(W.RY, q, -1, -1, 0.1 * i)))
+    for i in range(24):
+        g.append(W.gate([W.RY, W.RZ][i % 2], 6 + i % 6, -1, p, 0.0))
+        p += 1
+        if i % 5 == 4:
+            g.append(W.gate(W.CNOT, 5, 6 + i % 6))
+    gates6 = np.array(g, W.GATE_DTYPE)
+    assert qv.plan_circuit(n, gates6, 6, prec, 0)[0]["n_trainable"] == 0
+    circuits6 = [(n, g, p)]
+    for tile, circs in ((8, circuits), (0, circuits), (6, circuits6)):
+        for n, g, p in circs:
+            theta = rng.uniform(0, 2 * np.pi, size=p)
+            xm, zm, cf = W.random_paulis(rng, 5, n)
+            wl = W.single(f"prefix{n}", n, g, theta, (xm, zm, cf))
+            g_ref = oracle.grad_adjoint(wl)
+            opts = {"tile_qubits": tile} if tile else {}
+            b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+            g_ad, _ = b.gradient(qv.QV_ADJOINT)
+            check(g_ad, g_ref, prec, obs_scale(wl), f"adjoint grad n={n} tile={tile}")
+
+
 def test_qcl20_full_size_complex128(qv):
     """20 qubits, 64 samples, 2 layers in complex128 (register tiles of 2^12 amplitudes, 8 per thread):
     every energy to 1e-12 and every gradient component to 1e-11 against the oracle's stored values. A
