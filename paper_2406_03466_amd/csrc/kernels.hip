@@ -1095,13 +1095,17 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
     return false;
 }
 
-// A level launch: workgroups take chunks of kTileChunk consecutive tiles (grid-stride over chunks); within
-// a chunk, a tile whose successor belongs to the same (circuit, pass) prefetches it.
-constexpr int kTileChunk = 8;
+// A level launch: workgroups take chunks of tile_chunk<ADJ>() consecutive tiles (grid-stride over chunks);
+// within a chunk, a tile whose successor belongs to the same (circuit, pass) prefetches it. Forward passes
+// run two workgroups per CU and balance better with shorter chunks; the adjoint (one per CU) gains more
+// from longer prefetch chains (measured on the 20-qubit circuit-learning levels).
+template <bool ADJ>
+constexpr int tile_chunk() { return ADJ ? 8 : 4; }
 
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void rtile_tiles(const LevelArgs &a)
 {
+    constexpr int kTileChunk = tile_chunk<ADJ>();
     const int64_t nchunks = (a.n_blocks + kTileChunk - 1) / kTileChunk;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int64_t b0 = c * kTileChunk, b1 = b0 + kTileChunk < a.n_blocks ? b0 + kTileChunk : a.n_blocks;
@@ -1661,7 +1665,9 @@ int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
     const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint) +
                        (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)a.max_train : 0);
     if (lds > (size_t)kLdsLimit) return hipErrorInvalidValue;
-    dim3 grid((unsigned)a.n_blocks), block(kRtileThreads);
+    // one workgroup per chunk of tiles
+    const int chunk = adjoint ? tile_chunk<true>() : tile_chunk<false>();
+    dim3 grid((unsigned)((a.n_blocks + chunk - 1) / chunk)), block(kRtileThreads);
     if (precision == QV_C64) {
         if (adjoint) hipLaunchKernelGGL((k_rtile_adj<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_rtile_fwd<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
