@@ -96,7 +96,8 @@ def timed(fn, stream_sync, reps: int = 1) -> float:
 def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
     """The other workload shapes, each on its own batch (created and freed here): circuit learning with 2
     and 4 layers (adjoint vs parameter-shift gradients/s), the 16-qubit VQE parameter-shift gradient (513
-    circuits), 1024 uneven random circuits, and the 32-qubit 10-layer circuit (32 GiB complex64 state)
+    circuits), 1024 uneven random circuits, MC-VQE-shaped batches at 16-22 qubits (adjoint and
+    parameter-shift mean-energy gradients), and the 32-qubit 10-layer circuit (32 GiB complex64 state)
     forward and adjoint, with and without fused MFMA blocks."""
     out = {}
 
@@ -136,6 +137,20 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
         out["random1024_expectations_c64"] = {"circuit_evals_per_s": round(wl.B / s, 1),
                                               "ms": round(s * 1e3, 3), "circuits": wl.B}
         b.close()
+    # MC-VQE-shaped batches at Table 1's sizes: one circuit per CIS state, mean-energy gradient
+    for nq in ((16, 18, 20, 22) if only in (None, "mcvqe") else ()):
+        wl = W.mcvqe(nq)
+        up = np.full(wl.B, 1.0 / wl.B)
+        b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
+        s_ad = timed(lambda: b.gradient(qvpu.QV_ADJOINT, upstream=up), sync, 3)
+        s_ps = timed(lambda: b.gradient(qvpu.QV_PARAM_SHIFT, upstream=up), sync, 1)
+        nh, P = wl.extra["n_hamiltonian_terms"], wl.n_grad()
+        out[f"mcvqe{nq}_S{wl.B}_c64"] = {"adjoint_gradient_ms": round(s_ad * 1e3, 3),
+                                        "param_shift_gradient_ms": round(s_ps * 1e3, 3),
+                                        "param_shift_circuits": wl.B * (2 * P + 1),
+                                        "param_shift_circuit_evals_per_s": round(wl.B * (2 * P + 1) / s_ps, 1),
+                                        "terms": nh, "params": P, "per_state_per_term_circuits": 2 * nh * P}
+        b.close()
     wl = W.config5() if only in (None, "hea32") else None
     for fusion in (["off", "8"] if wl is not None else []):
         b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
@@ -157,7 +172,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ps", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workload shapes")
-    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32"],
+    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32", "mcvqe"],
                     help="run only this one of the other workload shapes and print its figures")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])

@@ -297,6 +297,103 @@ def config5() -> Workload:
     return large_hea(32, 10, 5)
 
 
+def cis_prep(c) -> list:
+    """Gates preparing sum_A c_A |e_A> (e_A: only qubit A excited) from |0...0>, for a real unit vector c:
+    X on qubit 0, then for k = 0..N-2 a Givens rotation between qubits k and k+1 that keeps cos(b_k) of the
+    excitation on qubit k and moves sin(b_k) of it to qubit k+1. Each Givens rotation is CNOT(k->k+1),
+    RY_{k+1}(-b), CNOT(k->k+1), RY_{k+1}(b), CNOT(k+1->k): a controlled RY(2b) followed by a CNOT back. The
+    angles are fixed (not trainable): b_k = atan2(|c_{k+1..}|, c_k), the last one atan2(c_{N-1}, c_{N-2}),
+    so that the amplitudes come out as c_0 = cos b_0, c_1 = sin b_0 cos b_1, ... with the signs of c."""
+    c = np.asarray(c, np.float64)
+    N = len(c)
+    g = [gate(X, 0)]
+    for k in range(N - 1):
+        if k < N - 2:
+            b = float(np.arctan2(np.sqrt(np.sum(c[k + 1:] ** 2)), c[k]))
+        else:
+            b = float(np.arctan2(c[N - 1], c[N - 2]))
+        g += [gate(CNOT, k, k + 1), gate(RY, k + 1, -1, -1, -b), gate(CNOT, k, k + 1), gate(RY, k + 1, -1, -1, b),
+              gate(CNOT, k + 1, k)]
+    return g
+
+
+def mcvqe_entanglers(n: int, merge: bool = True):
+    """The MC-VQE entangler layer (Section 4.1): on each adjacent pair (A, A+1), even pairs first, then odd
+    pairs, RY on both qubits, CNOT(A -> A+1), RY on both, CNOT(A -> A+1), RY on both: 6 trainable RY and 2
+    CNOTs per pair, 6(n-1) angles. With merge, an RY that directly follows another trainable RY on the same
+    qubit (the last RY of one pair's entangler and the first of the next pair's, on the shared qubit) is
+    folded into it, RY(a) RY(b) = RY(a + b), which leaves 5n - 4 parameters. Returns (gates, n_params,
+    merged_from) where merged_from[p] lists the unmerged parameter indices that parameter p stands for."""
+    raw = []
+    p = 0
+    pairs = [(a, a + 1) for a in range(0, n - 1, 2)] + [(a, a + 1) for a in range(1, n - 1, 2)]
+    for a, b in pairs:
+        for _ in range(2):
+            raw += [gate(RY, a, -1, p), gate(RY, b, -1, p + 1), gate(CNOT, a, b)]
+            p += 2
+        raw += [gate(RY, a, -1, p), gate(RY, b, -1, p + 1)]
+        p += 2
+    if not merge:
+        return raw, p, [[i] for i in range(p)]
+    out = []
+    last_on = {}  # qubit -> index in out of the last gate touching it
+    new_of = {}
+    merged_from = []
+    for g in raw:
+        kind, q0, q1, par, ang = g
+        if kind == RY and par >= 0 and q0 in last_on:
+            prev = out[last_on[q0]]
+            if prev[0] == RY and prev[3] >= 0:
+                new_of[par] = prev[3]
+                merged_from[prev[3]].append(par)
+                continue
+        if kind == RY and par >= 0:
+            new_of[par] = len(merged_from)
+            merged_from.append([par])
+            g = (kind, q0, q1, new_of[par], ang)
+        out.append(g)
+        last_on[q0] = len(out) - 1
+        if q1 >= 0:
+            last_on[q1] = len(out) - 1
+    return out, len(merged_from), merged_from
+
+
+def aiem_hamiltonian(rng, n: int):
+    """Pauli terms of the ab initio exciton model Hamiltonian (Eq. 2): a constant, X_A and Z_A on every
+    monomer A, and XX, XZ, ZX, ZZ on every adjacent pair (A, A+1): 6n - 4 Pauli terms plus the constant,
+    which is kept as an identity term (xmask = zmask = 0) at index 0. Coefficients are synthetic N(0, 1)
+    (the paper's monomer data are not published); draw order: constant, then term by term as listed."""
+    xm, zm = [0], [0]
+    for a in range(n):
+        xm += [1 << a, 0]
+        zm += [0, 1 << a]
+    for a in range(n - 1):
+        A, B = 1 << a, 1 << (a + 1)
+        xm += [A | B, A, B, 0]
+        zm += [0, B, A, A | B]
+    cf = rng.normal(0.0, 1.0, size=len(xm))
+    return np.array(xm, np.uint64), np.array(zm, np.uint64), cf
+
+
+def mcvqe(n: int = 16, n_states: Optional[int] = None, seed_index: int = 6, merge: bool = True) -> Workload:
+    """MC-VQE-shaped batch (Section 4.1): n monomers on n qubits; one circuit per CIS state (n_states of them,
+    default n), each its own CIS preparation followed by the shared entangler layer; shared parameters and
+    the shared AIEM Hamiltonian, so the mean energy over states and its gradient come from one batch call
+    with upstream weights 1/n_states. The CIS vectors are a random orthonormal set (QR of a Gaussian
+    matrix; the paper's CIS coefficients are not published). Draw order: theta ~ U[0, 2pi), the Gaussian
+    matrix, then the Hamiltonian coefficients."""
+    n_states = n if n_states is None else int(n_states)
+    rng = np.random.default_rng(SEED_BASE + seed_index)
+    ent, P, merged_from = mcvqe_entanglers(n, merge)
+    theta = rng.uniform(0.0, 2 * np.pi, size=P)
+    q, _ = np.linalg.qr(rng.normal(0.0, 1.0, size=(n, n)))
+    cis = q[:, :n_states].T.copy()                      # [n_states, n], orthonormal rows
+    xm, zm, cf = aiem_hamiltonian(rng, n)
+    circuits = [cis_prep(cis[s]) + ent for s in range(n_states)]
+    return _pack(f"mcvqe{n}_S{n_states}", circuits, [n] * n_states, [P] * n_states, True, theta, (xm, zm, cf),
+                 True, {"cis": cis, "merged_from": merged_from, "n_hamiltonian_terms": int(len(xm) - 1)})
+
+
 def ghz(n: int) -> Workload:
     """H on qubit 0 then the CNOT ladder: (|0..0> + |1..1>)/sqrt(2). No parameters, no terms."""
     g = [gate(H, 0)] + [gate(CNOT, q, q + 1) for q in range(n - 1)]
