@@ -106,7 +106,11 @@ typedef enum {
     QV_K_MATRICES = 12,     /* 2x2 matrices of every gate at the current parameters */
     QV_K_RTILE_PERSIST = 13,     /* all forward register-tiled passes in one persistent launch */
     QV_K_RTILE_ADJ_PERSIST = 14, /* all adjoint register-tiled passes in one persistent launch */
-    QV_K_FUSE = 15               /* fused 4-qubit block matrices (products of their gates) */
+    QV_K_FUSE = 15,              /* fused 4-qubit block matrices (products of their gates) */
+    QV_K_PROBS = 16,             /* output distributions |psi|^2; with a target, divergence partials and weights */
+    QV_K_DIAG_SEED = 17,         /* adjoint seed lambda = u diag(w) psi of the divergence weights */
+    QV_K_DIAG_EXPECT = 18,       /* <psi|diag(w)|psi> partial sums (parameter-shift variants) */
+    QV_K_SEGMENT_SUM = 19        /* per-circuit sums of partials in a fixed order */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -205,6 +209,28 @@ qv_status qv_batch_expectations(qv_batch batch, double *energies, double *term_v
  * forward energies are written too. upstream, grad and energies are device pointers when on_device. */
 qv_status qv_batch_gradient(qv_batch batch, qv_grad_method method, const double *upstream, double *grad,
                             double *energies, int32_t on_device);
+
+/* Output distributions (Section 4.2: running a circuit yields a probability for each of the 2^n bit
+ * strings): executes every circuit from |0...0> and writes P_b(x) = |<x|U_b|0>|^2 in FP64 for every
+ * circuit b and bit string x (x read as an amplitude index, qubit q = bit q). probs holds
+ * sum_b 2^{n_b} doubles, circuit b's distribution starting at sum_{b' < b} 2^{n_b'}; caller-owned, a
+ * device pointer when out_on_device. The final states stay on the device. */
+qv_status qv_batch_probabilities(qv_batch batch, double *probs, int32_t out_on_device);
+
+/* Jensen-Shannon divergence of Eq. 3 (the data-driven circuit-learning loss of Section 4.2) between a
+ * target distribution P_b and each circuit's output distribution Q_b,
+ *     JS_b = 1/2 sum_x [ P_b(x) log(P_b(x)/M(x)) + Q_b(x) log(Q_b(x)/M(x)) ],  M = (P_b + Q_b)/2,
+ * natural logarithm, 0 log 0 = 0, and the gradient of L = sum_b u_b JS_b with u = upstream[B] (NULL:
+ * all ones). target has the layout of qv_batch_probabilities' output; host targets are checked to be
+ * finite and non-negative (device targets are the caller's responsibility; they are not renormalised).
+ * dJS_b/dQ_b(x) = log(Q_b(x)/M(x))/2 (weight 0 where Q_b(x) = 0) turns the gradient into that of the
+ * diagonal observable diag(u_b dJS_b/dQ_b) at fixed weights: QV_ADJOINT seeds lambda_b with it and sweeps
+ * the gates backwards; QV_PARAM_SHIFT evaluates that observable on the +-pi/2 variants of every trainable
+ * gate. js[B] (may be NULL) receives the divergences; grad as in qv_batch_gradient. target, upstream, js
+ * and grad are device pointers when on_device. Buffers of sum_b 2^{n_b} doubles (target copy, weights)
+ * are allocated on first use and kept with the batch. */
+qv_status qv_batch_js_gradient(qv_batch batch, qv_grad_method method, const double *target, const double *upstream,
+                               double *js, double *grad, int32_t on_device);
 
 /* Copies the final state of circuit b after the last forward pass: 2^n complex numbers, interleaved
  * (re, im), float for QV_C64 and double for QV_C128. */

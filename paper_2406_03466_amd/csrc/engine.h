@@ -288,6 +288,48 @@ int launch_finalize(const FinalizeArgs &a, void *stream);
 int launch_lambda(const LambdaArgs &a, int precision, void *stream);
 int launch_grad_reduce(const GradReduceArgs &a, void *stream);
 int launch_shift_combine(const ShiftCombineArgs &a, void *stream);
+
+// Probability path (Section 4.2). Blocks of 4096 amplitudes; first_block is the per-circuit block prefix.
+struct ProbArgs {
+    const DevCirc *circs;
+    int32_t n_circ;
+    const int64_t *first_block;  // [n_circ + 1]
+    int64_t n_blocks;
+    const void *psi;
+    const double *target;        // [pool amplitudes] target distributions, or NULL (no divergence)
+    double *probs;               // [pool amplitudes] |psi|^2, or NULL
+    double *w;                   // [pool amplitudes] dJS/dP_theta, written when target is given
+    double *partials;            // [n_blocks] Jensen-Shannon partial sums (before the factor 1/2)
+};
+
+// Expectations of, or the adjoint seed for, the diagonal observable diag(w): w is indexed through the base
+// circuit of each entry (a parameter-shift variant uses its base circuit's weights).
+struct DiagArgs {
+    const DevCirc *circs;
+    int32_t n_circ;
+    const int64_t *first_block;  // [n_circ + 1]
+    int64_t n_blocks;
+    const DevCirc *base_circs;   // the batch's circuits (state offsets of w)
+    const double *w;
+    const double *upstream;      // seed only: [B] weights, or NULL (1)
+    const void *psi;
+    void *lam;                   // seed only
+    double *partials;            // expectation only: [n_blocks]
+};
+
+// out[c] = scale * sum of partials[first_block[c] .. first_block[c + 1]), fixed summation order.
+struct SegSumArgs {
+    const int64_t *first_block;
+    const double *partials;
+    double *out;
+    int32_t n;
+    double scale;
+};
+
+int launch_probs(const ProbArgs &a, int precision, void *stream);
+int launch_diag_seed(const DiagArgs &a, int precision, void *stream);
+int launch_diag_expect(const DiagArgs &a, int precision, void *stream);
+int launch_segment_sum(const SegSumArgs &a, void *stream);
 int launch_fill(double *p, int64_t n, double v, void *stream);
 int launch_matrices(const MatArgs &a, int precision, void *stream);
 int launch_shift_matrices(const ShiftMatArgs &a, int precision, void *stream);

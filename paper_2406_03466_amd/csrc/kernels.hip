@@ -1545,6 +1545,106 @@ __global__ void k_shift_combine(ShiftCombineArgs a)
     a.grad[g] = s;
 }
 
+// ------------------------------------------------------------------------------------------------------
+// Probability path (Section 4.2): the output distribution P_theta(b) = |psi_b|^2 over all bit strings, the
+// Jensen-Shannon divergence of Eq. 3 against a target distribution P, and its derivative. With M = (P + Q)/2
+// and Q = P_theta, dJS/dQ(b) = log(Q(b)/M(b)) / 2; a bit string with Q(b) = 0 gets weight 0 (Q is at its
+// minimum there, so dQ/dtheta = 0) and 0 log 0 counts as 0. The gradient of the divergence is then the
+// gradient of the diagonal observable diag(w) at fixed w, by either rule.
+// ------------------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_probs(ProbArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * 4096ull;
+    const Cx<R> *st = reinterpret_cast<const Cx<R> *>(a.psi) + C.state_off;
+    double js = 0.0;
+    for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
+        const uint64_t o = o0 + e;
+        if (o >= dim) break;
+        const Cx<R> v = st[o];
+        const double vr = v.re, vi = v.im;
+        const double q = vr * vr + vi * vi;
+        const int64_t i = C.state_off + (int64_t)o;
+        if (a.probs) a.probs[i] = q;
+        if (a.target) {
+            const double p = a.target[i];
+            const double m = 0.5 * (p + q);
+            if (p > 0.0) js += p * log(p / m);
+            if (q > 0.0) js += q * log(q / m);
+            a.w[i] = q > 0.0 ? 0.5 * log(q / m) : 0.0;
+        }
+    }
+    if (a.partials) {
+        js = block_sum(js, red);
+        if (threadIdx.x == 0) a.partials[blk] = js;
+    }
+}
+
+// lambda = u_b diag(w) psi: the adjoint seed of the diagonal observable.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_diag_seed(DiagArgs a)
+{
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * 4096ull;
+    const Cx<R> *st = reinterpret_cast<const Cx<R> *>(a.psi) + C.state_off;
+    Cx<R> *lam = reinterpret_cast<Cx<R> *>(a.lam) + C.state_off;
+    const double *w = a.w + a.base_circs[C.base_circ].state_off;
+    const double u = a.upstream ? a.upstream[C.base_circ] : 1.0;
+    for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
+        const uint64_t o = o0 + e;
+        if (o >= dim) break;
+        const Cx<R> v = st[o];
+        const double f = u * w[o];
+        Cx<R> out;
+        out.re = (R)(f * (double)v.re);
+        out.im = (R)(f * (double)v.im);
+        lam[o] = out;
+    }
+}
+
+// Per-block partial sums of <psi|diag(w)|psi> = sum_o w[o] |psi[o]|^2 (FP64).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_diag_expect(DiagArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * 4096ull;
+    const Cx<R> *st = reinterpret_cast<const Cx<R> *>(a.psi) + C.state_off;
+    const double *w = a.w + a.base_circs[C.base_circ].state_off;
+    double s = 0.0;
+    for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
+        const uint64_t o = o0 + e;
+        if (o >= dim) break;
+        const Cx<R> v = st[o];
+        const double vr = v.re, vi = v.im;
+        s += w[o] * (vr * vr + vi * vi);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) a.partials[blk] = s;
+}
+
+// One workgroup per output: a fixed strided share per thread, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_segment_sum(SegSumArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t j = a.first_block[c] + threadIdx.x; j < a.first_block[c + 1]; j += kBlock) s += a.partials[j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) a.out[c] = a.scale * s;
+}
+
 __global__ void k_fill(double *p, int64_t n, double v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1798,6 +1898,42 @@ int launch_fuse(const FuseArgs &a, void *stream)
     if (a.n_blocks <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_fuse, dim3((unsigned)a.n_blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_probs(const ProbArgs &a, int precision, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    if (a.target && !a.w) return hipErrorInvalidValue;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision == QV_C64) hipLaunchKernelGGL((k_probs<float>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_probs<double>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_diag_seed(const DiagArgs &a, int precision, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision == QV_C64) hipLaunchKernelGGL((k_diag_seed<float>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_diag_seed<double>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_diag_expect(const DiagArgs &a, int precision, void *stream)
+{
+    if (a.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (precision == QV_C64) hipLaunchKernelGGL((k_diag_expect<float>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_diag_expect<double>), dim3((unsigned)a.n_blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_segment_sum(const SegSumArgs &a, void *stream)
+{
+    if (a.n <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_segment_sum, dim3((unsigned)a.n), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

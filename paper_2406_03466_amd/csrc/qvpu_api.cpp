@@ -294,6 +294,9 @@ struct ExecSet {
     int p_fwd_ok = 0, p_rev_ok = 0;
     int32_t p_lds_t[2] = {0, 0}, p_tab_bits[2] = {0, 0}, p_max_train[2] = {0, 0};
     DBuf d_p_fwd, d_p_rev, d_p_head, d_p_done, d_p_error;
+    // probability path: per-circuit block prefix and partial sums of diagonal-observable expectations
+    std::vector<int64_t> diag_fb;
+    DBuf d_diag_fb, d_diag_part;
 };
 
 // Device form of a batch's plans (shared by all its circuits and parameter-shift variants).
@@ -347,7 +350,12 @@ struct qv_batch_s {
     bool theta_set = false;
     bool fwd_valid = false;
 
-    hipGraphExec_t g_fwd = nullptr, g_adj = nullptr, g_ps = nullptr;
+    // probability path: block prefix of the batch's circuits, output distributions, target distributions,
+    // divergence weights dJS/dP_theta, divergence partial sums and values
+    std::vector<int64_t> pfb;
+    DBuf d_pfb, d_probs, d_target, d_w, d_js_part, d_js;
+
+    hipGraphExec_t g_fwd = nullptr, g_adj = nullptr, g_ps = nullptr, g_js_adj = nullptr, g_js_ps = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     LaunchLog log;
@@ -866,6 +874,8 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     return logged(log, s, QV_K_FINALIZE, -1, 0, [&] { return launch_finalize(fa, s); });
 }
 
+static int enqueue_reverse(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, hipStream_t s, LaunchLog *log);
+
 static int enqueue_adjoint(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, hipStream_t s, LaunchLog *log)
 {
     LambdaArgs la;
@@ -878,8 +888,15 @@ static int enqueue_adjoint(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     la.psi = bt.d_psi.p;
     la.lam = bt.d_lam.p;
     la.n_blocks = es.lam_blocks;
-    int e = logged(log, s, QV_K_LAMBDA, -1, es.lam_bytes, [&] { return launch_lambda(la, bt.prec, s); });
+    const int e = logged(log, s, QV_K_LAMBDA, -1, es.lam_bytes, [&] { return launch_lambda(la, bt.prec, s); });
     if (e) return e;
+    return enqueue_reverse(bt, es, dp, s, log);
+}
+
+// The reverse sweep from seeded psi and lambda, then the gradient reduction.
+static int enqueue_reverse(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, hipStream_t s, LaunchLog *log)
+{
+    int e = 0;
     if (bt.ctx->persistent && es.p_rev_ok) {
         e = enqueue_persistent(bt, es, dp, 1, bt.d_psi.p, bt.d_lam.p, s, log);
         if (e) return e;
@@ -1030,7 +1047,9 @@ static void drop_graphs(qv_batch_s *bt)
     if (bt->g_fwd) (void)hipGraphExecDestroy(bt->g_fwd);
     if (bt->g_adj) (void)hipGraphExecDestroy(bt->g_adj);
     if (bt->g_ps) (void)hipGraphExecDestroy(bt->g_ps);
-    bt->g_fwd = bt->g_adj = bt->g_ps = nullptr;
+    if (bt->g_js_adj) (void)hipGraphExecDestroy(bt->g_js_adj);
+    if (bt->g_js_ps) (void)hipGraphExecDestroy(bt->g_js_ps);
+    bt->g_fwd = bt->g_adj = bt->g_ps = bt->g_js_adj = bt->g_js_ps = nullptr;
     bt->ps_chunks.clear();
     bt->ps_chunk_var0.clear();
     bt->ps_ready = false;
@@ -1646,6 +1665,230 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
     bt->timed = true;
     if ((st = copy_out(bt, grad, bt->d_grad.p, sizeof(double) * (size_t)bt->n_grad, on_device)) != QV_OK) return st;
     if ((st = copy_out(bt, energies, bt->d_energies.p, sizeof(double) * bt->B, on_device)) != QV_OK) return st;
+    if (!on_device) {
+        HIPCHK(hipStreamSynchronize(s));
+        if ((st = check_persist_error(bt)) != QV_OK) return st;
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Probability path (Section 4.2): output distributions and the Jensen-Shannon divergence of Eq. 3
+// ---------------------------------------------------------------------------------------------------------
+static void diag_prefix(const std::vector<DevCirc> &circs, std::vector<int64_t> &fb)
+{
+    fb.assign(circs.size() + 1, 0);
+    for (size_t c = 0; c < circs.size(); c++) fb[c + 1] = fb[c] + ((((int64_t)1 << circs[c].n) + 4095) / 4096);
+}
+
+static qv_status alloc_doubles(DBuf &d, int64_t n, const char *what)
+{
+    const size_t bytes = sizeof(double) * (size_t)std::max<int64_t>(1, n);
+    if (d.p && d.bytes >= bytes) return QV_OK;
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    if ((double)bytes > 0.92 * (double)freeb)
+        return fail(QV_E_OOM, "%s need %.2f GiB, device has %.2f GiB free", what, bytes / 1073741824.0,
+                    freeb / 1073741824.0);
+    HIPCHK(d.alloc(bytes));
+    return QV_OK;
+}
+
+static qv_status ensure_prob_blocks(qv_batch bt)
+{
+    if (!bt->pfb.empty()) return QV_OK;
+    std::vector<int64_t> fb;
+    diag_prefix(bt->main.circs, fb);
+    HIPCHK(bt->d_pfb.upload(fb));
+    bt->pfb = std::move(fb);
+    return QV_OK;
+}
+
+static ProbArgs prob_args(const qv_batch_s &bt)
+{
+    ProbArgs a{};
+    a.circs = bt.main.d_circs.as<DevCirc>();
+    a.n_circ = bt.B;
+    a.first_block = bt.d_pfb.as<int64_t>();
+    a.n_blocks = bt.pfb[bt.B];
+    a.psi = bt.d_psi.p;
+    return a;
+}
+
+qv_status qv_batch_probabilities(qv_batch bt, double *probs, int32_t out_on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!probs) return fail(QV_E_INVALID, "probs must not be NULL");
+    if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    qv_status st;
+    if ((st = ensure_prob_blocks(bt)) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_probs, bt->main.state_amps, "output distributions")) != QV_OK) return st;
+    hipStream_t s = bt->ctx->stream();
+    HIPCHK(hipEventRecord(bt->ev0, s));
+    if ((st = forward(bt)) != QV_OK) return st;
+    ProbArgs a = prob_args(*bt);
+    a.probs = bt->d_probs.as<double>();
+    const int64_t bytes = bt->main.state_amps * (bt->amp_bytes + (int64_t)sizeof(double));
+    const int e = logged(bt->ctx->launch_events ? &bt->log : nullptr, s, QV_K_PROBS, -1, bytes,
+                         [&] { return launch_probs(a, bt->prec, s); });
+    if (e) return fail(QV_E_DEVICE, "probabilities launch failed: %s", hipGetErrorString((hipError_t)e));
+    HIPCHK(hipEventRecord(bt->ev1, s));
+    bt->timed = true;
+    bt->last.launches += 1;
+    bt->last.algorithmic_bytes += bytes;
+    if ((st = copy_out(bt, probs, bt->d_probs.p, sizeof(double) * (size_t)bt->main.state_amps, out_on_device)) != QV_OK)
+        return st;
+    if (!out_on_device) HIPCHK(hipStreamSynchronize(s));
+    return ok();
+}
+
+qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double *target, const double *upstream,
+                               double *js, double *grad, int32_t on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!target) return fail(QV_E_INVALID, "target must not be NULL");
+    if (!grad) return fail(QV_E_INVALID, "grad must not be NULL");
+    if (method != QV_ADJOINT && method != QV_PARAM_SHIFT) return fail(QV_E_INVALID, "unknown gradient method %d", (int)method);
+    if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
+    const int64_t n = bt->main.state_amps;
+    if (!on_device) {
+        for (int64_t i = 0; i < n; i++)
+            if (!(target[i] >= 0.0) || !std::isfinite(target[i]))
+                return fail(QV_E_INVALID, "target[%lld] = %g is not a finite probability", (long long)i, target[i]);
+        if (upstream)
+            for (int b = 0; b < bt->B; b++)
+                if (!std::isfinite(upstream[b])) return fail(QV_E_INVALID, "upstream[%d] is not finite", b);
+    }
+    HIPCHK(hipSetDevice(bt->ctx->device));
+    qv_status st;
+    if ((st = ensure_prob_blocks(bt)) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_target, n, "target distributions")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_w, n, "divergence weights")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_js_part, bt->pfb[bt->B], "divergence partial sums")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_js, bt->B, "divergences")) != QV_OK) return st;
+    hipStream_t s = bt->ctx->stream();
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(bt->d_target.p, target, sizeof(double) * (size_t)n, kind, s));
+    if (upstream) {
+        HIPCHK(hipMemcpyAsync(bt->d_upstream.p, upstream, sizeof(double) * bt->B, kind, s));
+    } else {
+        const int e = launch_fill(bt->d_upstream.as<double>(), bt->B, 1.0, s);
+        if (e) return fail(QV_E_DEVICE, "fill failed: %s", hipGetErrorString((hipError_t)e));
+    }
+    DevPlans &dp = *bt->dp;
+    const int64_t js_bytes = n * (bt->amp_bytes + 2 * (int64_t)sizeof(double));
+    // output distributions, divergences and their weights dJS/dP_theta from the batch's final states
+    auto divergence = [&](hipStream_t cs, LaunchLog *log) {
+        ProbArgs a = prob_args(*bt);
+        a.target = bt->d_target.as<double>();
+        a.w = bt->d_w.as<double>();
+        a.partials = bt->d_js_part.as<double>();
+        int e = logged(log, cs, QV_K_PROBS, -1, js_bytes, [&] { return launch_probs(a, bt->prec, cs); });
+        if (e) return e;
+        SegSumArgs sa{bt->d_pfb.as<int64_t>(), bt->d_js_part.as<double>(), bt->d_js.as<double>(), bt->B, 0.5};
+        return logged(log, cs, QV_K_SEGMENT_SUM, -1, 0, [&] { return launch_segment_sum(sa, cs); });
+    };
+    HIPCHK(hipEventRecord(bt->ev0, s));
+    if (method == QV_ADJOINT) {
+        if ((st = ensure_lambda(bt)) != QV_OK) return st;
+        int64_t passes = 0, bytes = 0, launches = 0;
+        if (!bt->fwd_valid) {
+            if ((st = forward(bt)) != QV_OK) return st;
+            passes += bt->last.passes;
+            bytes += bt->last.algorithmic_bytes;
+            launches += bt->last.launches;
+        }
+        st = run_graph(bt, bt->g_js_adj, [&](hipStream_t cs, LaunchLog *log) {
+            int e = divergence(cs, log);
+            if (e) return e;
+            DiagArgs d{};
+            d.circs = bt->main.d_circs.as<DevCirc>();
+            d.n_circ = bt->B;
+            d.first_block = bt->d_pfb.as<int64_t>();
+            d.n_blocks = bt->pfb[bt->B];
+            d.base_circs = bt->main.d_circs.as<DevCirc>();
+            d.w = bt->d_w.as<double>();
+            d.upstream = bt->d_upstream.as<double>();
+            d.psi = bt->d_psi.p;
+            d.lam = bt->d_lam.p;
+            e = logged(log, cs, QV_K_DIAG_SEED, -1, n * (2 * bt->amp_bytes + (int64_t)sizeof(double)),
+                       [&] { return launch_diag_seed(d, bt->prec, cs); });
+            if (e) return e;
+            return enqueue_reverse(*bt, bt->main, dp, cs, log);
+        });
+        if (st != QV_OK) return st;
+        bt->fwd_valid = false;
+        bt->last = qv_stats{};
+        bt->last.passes = passes + bt->main.passes_rev;
+        bt->last.launches = launches + 4 + (int64_t)bt->main.rev.size();
+        bt->last.algorithmic_bytes = bytes + js_bytes + bt->main.algo_bytes_rev;
+    } else {
+        if ((st = ensure_param_shift(bt)) != QV_OK) return st;
+        for (auto &c : bt->ps_chunks) {
+            if (!c->diag_fb.empty()) continue;
+            diag_prefix(c->circs, c->diag_fb);
+            HIPCHK(c->d_diag_fb.upload(c->diag_fb));
+            HIPCHK(c->d_diag_part.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, c->diag_fb.back())));
+        }
+        st = run_graph(bt, bt->g_js_ps, [&](hipStream_t cs, LaunchLog *log) {
+            int e = enqueue_matrices(*bt, cs, log);
+            if (e) return e;
+            e = enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                                bt->d_norms.as<double>(), cs, log);
+            if (e) return e;
+            if ((e = divergence(cs, log))) return e;
+            // each variant's <diag(w)> with its base circuit's weights replaces its energy in the combination
+            for (size_t i = 0; i < bt->ps_chunks.size(); i++) {
+                ExecSet &es = *bt->ps_chunks[i];
+                double *ev = bt->d_ps_energies.as<double>() + bt->ps_chunk_var0[i];
+                e = enqueue_forward(*bt, es, dp, bt->d_ps_psi.p, ev, bt->d_ps_tv.as<double>(), nullptr, cs, log);
+                if (e) return e;
+                DiagArgs d{};
+                d.circs = es.d_circs.as<DevCirc>();
+                d.n_circ = es.n_circ;
+                d.first_block = es.d_diag_fb.as<int64_t>();
+                d.n_blocks = es.diag_fb.back();
+                d.base_circs = bt->main.d_circs.as<DevCirc>();
+                d.w = bt->d_w.as<double>();
+                d.psi = bt->d_ps_psi.p;
+                d.partials = es.d_diag_part.as<double>();
+                e = logged(log, cs, QV_K_DIAG_EXPECT, -1, es.state_amps * (bt->amp_bytes + (int64_t)sizeof(double)),
+                           [&] { return launch_diag_expect(d, bt->prec, cs); });
+                if (e) return e;
+                SegSumArgs sa{es.d_diag_fb.as<int64_t>(), es.d_diag_part.as<double>(), ev, es.n_circ, 1.0};
+                e = logged(log, cs, QV_K_SEGMENT_SUM, -1, 0, [&] { return launch_segment_sum(sa, cs); });
+                if (e) return e;
+            }
+            ShiftCombineArgs sa;
+            sa.n_out = (int32_t)bt->n_grad;
+            sa.occ_begin = bt->d_occ_begin.as<int64_t>();
+            sa.occ_plus = bt->d_occ_plus.as<int32_t>();
+            sa.occ_minus = bt->d_occ_minus.as<int32_t>();
+            sa.occ_circ = bt->d_occ_circ.as<int32_t>();
+            sa.energies = bt->d_ps_energies.as<double>();
+            sa.upstream = bt->d_upstream.as<double>();
+            sa.grad = bt->d_grad.as<double>();
+            return logged(log, cs, QV_K_SHIFT_COMBINE, -1, 0, [&] { return launch_shift_combine(sa, cs); });
+        });
+        if (st != QV_OK) return st;
+        bt->fwd_valid = true;
+        bt->last = qv_stats{};
+        int64_t passes = bt->main.passes_fwd, bytes = bt->main.algo_bytes_fwd + js_bytes;
+        int64_t launches = 6 + (int64_t)bt->main.fwd.size();
+        for (auto &c : bt->ps_chunks) {
+            passes += c->passes_fwd;
+            bytes += c->algo_bytes_fwd + c->state_amps * (bt->amp_bytes + (int64_t)sizeof(double));
+            launches += 5 + (int64_t)c->fwd.size();
+        }
+        bt->last.passes = passes;
+        bt->last.launches = launches;
+        bt->last.algorithmic_bytes = bytes;
+    }
+    HIPCHK(hipEventRecord(bt->ev1, s));
+    bt->timed = true;
+    if ((st = copy_out(bt, grad, bt->d_grad.p, sizeof(double) * (size_t)bt->n_grad, on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, js, bt->d_js.p, sizeof(double) * bt->B, on_device)) != QV_OK) return st;
     if (!on_device) {
         HIPCHK(hipStreamSynchronize(s));
         if ((st = check_persist_error(bt)) != QV_OK) return st;

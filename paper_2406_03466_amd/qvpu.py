@@ -44,7 +44,7 @@ class qv_launch_rec(ctypes.Structure):
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
                 "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices", "rtile_persist",
-                "rtile_adj_persist", "fuse"]
+                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum"]
 
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),
@@ -55,8 +55,9 @@ class qv_pass_info(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
-           "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_state", "qv_batch_stats",
-           "qv_batch_destroy", "qv_batch_launch_log", "qv_plan_circuit", "qv_last_error", "qv_version"]
+           "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_probabilities",
+           "qv_batch_js_gradient", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy", "qv_batch_launch_log",
+           "qv_plan_circuit", "qv_last_error", "qv_version"]
 
 
 def load():
@@ -76,6 +77,8 @@ def load():
     lib.qv_batch_set_params.argtypes = [P, P, i32]
     lib.qv_batch_expectations.argtypes = [P, P, P, i32]
     lib.qv_batch_gradient.argtypes = [P, i32, P, P, P, i32]
+    lib.qv_batch_probabilities.argtypes = [P, P, i32]
+    lib.qv_batch_js_gradient.argtypes = [P, i32, P, P, P, P, i32]
     lib.qv_batch_state.argtypes = [P, i32, P, i32]
     lib.qv_batch_stats.argtypes = [P, ctypes.POINTER(qv_stats)]
     lib.qv_batch_destroy.argtypes = [P]
@@ -83,8 +86,9 @@ def load():
     lib.qv_plan_circuit.argtypes = [i32, ctypes.c_int64, P, i32, i32, i32, i32, i32,
                                     ctypes.POINTER(qv_pass_info), ctypes.POINTER(i32), P]
     for f in ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
-              "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_state",
-              "qv_batch_stats", "qv_batch_destroy", "qv_batch_launch_log", "qv_plan_circuit"]:
+              "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_probabilities",
+              "qv_batch_js_gradient", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy",
+              "qv_batch_launch_log", "qv_plan_circuit"]:
         getattr(lib, f).restype = st
     lib.qv_last_error.restype = ctypes.c_char_p
     lib.qv_last_error.argtypes = []
@@ -241,6 +245,36 @@ class Batch:
             return g[: self.n_grad], e
         _check(lib.qv_batch_gradient(self.h, int(method), _ptr(upstream), _ptr(grad), _ptr(energies), 1))
         return grad, energies
+
+    def n_amplitudes(self) -> int:
+        return int(sum(1 << int(n) for n in self.wl.n_qubits))
+
+    def probabilities(self, probs=None):
+        """Output distributions of every circuit, concatenated (circuit b's 2^n_b values in order). Host
+        mode returns a numpy array; device mode fills a float64 device tensor of n_amplitudes() values."""
+        if probs is None:
+            out = np.zeros(self.n_amplitudes())
+            _check(load().qv_batch_probabilities(self.h, _ptr(out), 0))
+            return out
+        _check(load().qv_batch_probabilities(self.h, _ptr(probs), 1))
+        return probs
+
+    def js_gradient(self, target, method: int = QV_ADJOINT, upstream=None, js=None, grad=None):
+        """Jensen-Shannon divergences against target distributions (layout of probabilities()) and the
+        gradient of sum_b upstream_b JS_b. Host mode returns (js[B], grad); device mode takes float64
+        device tensors for target, upstream (or None), js and grad."""
+        lib = load()
+        if grad is None:
+            t = np.ascontiguousarray(target, np.float64)
+            if t.shape != (self.n_amplitudes(),):
+                raise ValueError(f"target must hold {self.n_amplitudes()} values, got shape {t.shape}")
+            up = None if upstream is None else np.ascontiguousarray(upstream, np.float64)
+            g = np.zeros(max(1, self.n_grad))
+            j = np.zeros(self.B)
+            _check(lib.qv_batch_js_gradient(self.h, int(method), _ptr(t), _ptr(up), _ptr(j), _ptr(g), 0))
+            return j, g[: self.n_grad]
+        _check(lib.qv_batch_js_gradient(self.h, int(method), _ptr(target), _ptr(upstream), _ptr(js), _ptr(grad), 1))
+        return js, grad
 
     def state(self, circuit: int) -> np.ndarray:
         n = int(self.wl.n_qubits[circuit])

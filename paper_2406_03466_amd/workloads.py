@@ -394,6 +394,47 @@ def mcvqe(n: int = 16, n_states: Optional[int] = None, seed_index: int = 6, merg
                  True, {"cis": cis, "merged_from": merged_from, "n_hamiltonian_terms": int(len(xm) - 1)})
 
 
+def ddcl_layers(n: int, layers: int, first_param: int = 0):
+    """Data-driven circuit-learning body (Section 4.2): Bell pairs on neighbouring qubits (H on 2i, CNOT
+    2i -> 2i+1), then `layers` layers of RZ RY RZ on every qubit, the CNOT ring q -> q+1 (mod n), and RZ RY
+    RZ on every qubit again: 6n trainable angles per layer (Table 2: N_theta = 60 N_q at 10 layers)."""
+    g = []
+    for i in range(0, n - 1, 2):
+        g += [gate(H, i), gate(CNOT, i, i + 1)]
+    p = first_param
+    for _ in range(layers):
+        for half in range(2):
+            for q in range(n):
+                for kind in (RZ, RY, RZ):
+                    g.append(gate(kind, q, -1, p))
+                    p += 1
+            if half == 0 and n > 1:
+                g += [gate(CNOT, q, (q + 1) % n) for q in range(n if n > 2 else 1)]
+    return g, p - first_param
+
+
+def ddcl(n: int = 20, layers: int = 10, seed_index: int = 7, sizes=None) -> Workload:
+    """DDCL-shaped batch: one circuit per entry of `sizes` (default [n]), each the Bell-pair + layer circuit
+    with its own angles theta ~ U[0, 2pi) and its own target distribution: exponential weights on a random
+    half of the 2^n bit strings (the rest exactly 0), normalised (the paper's targets are not published).
+    No Pauli terms. Draw order per circuit: theta, the support mask, the weights."""
+    sizes = [n] if sizes is None else [int(x) for x in sizes]
+    rng = np.random.default_rng(SEED_BASE + seed_index)
+    circuits, nps, thetas, targets = [], [], [], []
+    for m in sizes:
+        g, P = ddcl_layers(m, layers)
+        thetas.append(rng.uniform(0.0, 2 * np.pi, size=P))
+        mask = rng.random(1 << m) < 0.5
+        t = rng.exponential(1.0, size=1 << m) * mask
+        targets.append(t / t.sum())
+        circuits.append(g)
+        nps.append(P)
+    empty = [(np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0)) for _ in sizes]
+    name = f"ddcl{'-'.join(map(str, sizes))}_L{layers}"
+    return _pack(name, circuits, sizes, nps, False, np.concatenate(thetas), empty, False,
+                 {"target": np.concatenate(targets)})
+
+
 def ghz(n: int) -> Workload:
     """H on qubit 0 then the CNOT ladder: (|0..0> + |1..1>)/sqrt(2). No parameters, no terms."""
     g = [gate(H, 0)] + [gate(CNOT, q, q + 1) for q in range(n - 1)]

@@ -39,10 +39,30 @@ def random_case():
             "seconds": time.time() - t0}
 
 
+DDCL20_PARAMS = [0, 1, 2, 119, 600, 601, 1197, 1199]
+
+
+def ddcl20_case():
+    """Table 2's smallest DDCL size: 20 qubits, 10 layers, 1200 parameters. The divergence, 64 sampled
+    output probabilities and 8 gradient components by the parameter-shift rule (17 oracle circuits)."""
+    from oracle import ddcl as OD
+    wl = W.ddcl(20, 10)
+    t0 = time.time()
+    t = wl.extra["target"]
+    q = OD.probabilities(wl)
+    idx = np.random.default_rng(20).choice(len(q), size=64, replace=False)
+    g = OD.js_grad_param_shift(wl, t, None, only=set(DDCL20_PARAMS))
+    return {"workload": wl.name, "what": "JS divergence, sampled probabilities, gradient components (param-shift)",
+            "js": OD.js_divergence(t, q), "prob_index": idx.tolist(), "probs": q[idx].tolist(),
+            "grad_index": DDCL20_PARAMS, "grad": [float(g[j]) for j in DDCL20_PARAMS],
+            "seconds": time.time() - t0}
+
+
 CASES = {
     "qcl20_L2": lambda: qcl_case(2),
     "qcl20_L8": lambda: qcl_case(8),
     "random1024": random_case,
+    "ddcl20": ddcl20_case,
 }
 
 if __name__ == "__main__":
