@@ -97,7 +97,8 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
     """The other workload shapes, each on its own batch (created and freed here): circuit learning with 2
     and 4 layers (adjoint vs parameter-shift gradients/s), the 16-qubit VQE parameter-shift gradient (513
     circuits), 1024 uneven random circuits, MC-VQE-shaped batches at 16-22 qubits (adjoint and
-    parameter-shift mean-energy gradients), and the 32-qubit 10-layer circuit (32 GiB complex64 state)
+    parameter-shift mean-energy gradients), DDCL-shaped circuits at 20-26 qubits (Jensen-Shannon loss
+    gradients), and the 32-qubit 10-layer circuit (32 GiB complex64 state)
     forward and adjoint, with and without fused MFMA blocks."""
     out = {}
 
@@ -151,6 +152,20 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                                         "param_shift_circuit_evals_per_s": round(wl.B * (2 * P + 1) / s_ps, 1),
                                         "terms": nh, "params": P, "per_state_per_term_circuits": 2 * nh * P}
         b.close()
+    # DDCL-shaped circuits at Table 2's sizes (10 layers, 60 N_q parameters): Jensen-Shannon loss gradient
+    for nq in ((20, 22, 24, 26) if only in (None, "ddcl") else ()):
+        wl = W.ddcl(nq, 10)
+        t = wl.extra["target"]
+        b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
+        s_ad = timed(lambda: b.js_gradient(t, qvpu.QV_ADJOINT), sync, 3)
+        rec = {"adjoint_gradient_ms": round(s_ad * 1e3, 3), "params": wl.n_grad(),
+               "param_shift_circuits": 2 * wl.n_grad() + 1}
+        if nq <= 22:
+            s_ps = timed(lambda: b.js_gradient(t, qvpu.QV_PARAM_SHIFT), sync, 1)
+            rec["param_shift_gradient_ms"] = round(s_ps * 1e3, 2)
+            rec["param_shift_circuit_evals_per_s"] = round((2 * wl.n_grad() + 1) / s_ps, 1)
+        out[f"ddcl{nq}_L10_c64"] = rec
+        b.close()
     wl = W.config5() if only in (None, "hea32") else None
     for fusion in (["off", "8"] if wl is not None else []):
         b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
@@ -172,7 +187,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ps", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workload shapes")
-    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32", "mcvqe"],
+    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32", "mcvqe", "ddcl"],
                     help="run only this one of the other workload shapes and print its figures")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
