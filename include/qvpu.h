@@ -226,8 +226,10 @@ qv_status qv_batch_probabilities(qv_batch batch, double *probs, int32_t out_on_d
  * dJS_b/dQ_b(x) = log(Q_b(x)/M(x))/2 (weight 0 where Q_b(x) = 0) turns the gradient into that of the
  * diagonal observable diag(u_b dJS_b/dQ_b) at fixed weights: QV_ADJOINT seeds lambda_b with it and sweeps
  * the gates backwards; QV_PARAM_SHIFT evaluates that observable on the +-pi/2 variants of every trainable
- * gate. js[B] (may be NULL) receives the divergences; grad as in qv_batch_gradient. target, upstream, js
- * and grad are device pointers when on_device. Buffers of sum_b 2^{n_b} doubles (target copy, weights)
+ * gate. js[B] (may be NULL) receives the divergences; grad as in qv_batch_gradient, or NULL for the
+ * divergences alone (one forward pass; method is then ignored, and the final states stay for a following
+ * QV_ADJOINT call, which does not repeat the forward pass). target, upstream, js and grad are device
+ * pointers when on_device. Buffers of sum_b 2^{n_b} doubles (target copy, weights)
  * are allocated on first use and kept with the batch. */
 qv_status qv_batch_js_gradient(qv_batch batch, qv_grad_method method, const double *target, const double *upstream,
                                double *js, double *grad, int32_t on_device);

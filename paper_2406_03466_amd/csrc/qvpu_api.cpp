@@ -1748,7 +1748,7 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
 {
     if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
     if (!target) return fail(QV_E_INVALID, "target must not be NULL");
-    if (!grad) return fail(QV_E_INVALID, "grad must not be NULL");
+    if (!grad && !js) return fail(QV_E_INVALID, "js and grad must not both be NULL");
     if (method != QV_ADJOINT && method != QV_PARAM_SHIFT) return fail(QV_E_INVALID, "unknown gradient method %d", (int)method);
     if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
     const int64_t n = bt->main.state_amps;
@@ -1790,7 +1790,14 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
         return logged(log, cs, QV_K_SEGMENT_SUM, -1, 0, [&] { return launch_segment_sum(sa, cs); });
     };
     HIPCHK(hipEventRecord(bt->ev0, s));
-    if (method == QV_ADJOINT) {
+    if (!grad) {
+        // divergences only: one forward pass, whose final states stay for a following gradient call
+        if ((st = forward(bt)) != QV_OK) return st;
+        const int e = divergence(s, bt->ctx->launch_events ? &bt->log : nullptr);
+        if (e) return fail(QV_E_DEVICE, "divergence launch failed: %s", hipGetErrorString((hipError_t)e));
+        bt->last.launches += 2;
+        bt->last.algorithmic_bytes += js_bytes;
+    } else if (method == QV_ADJOINT) {
         if ((st = ensure_lambda(bt)) != QV_OK) return st;
         int64_t passes = 0, bytes = 0, launches = 0;
         if (!bt->fwd_valid) {
@@ -1887,7 +1894,8 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
     }
     HIPCHK(hipEventRecord(bt->ev1, s));
     bt->timed = true;
-    if ((st = copy_out(bt, grad, bt->d_grad.p, sizeof(double) * (size_t)bt->n_grad, on_device)) != QV_OK) return st;
+    if (grad && (st = copy_out(bt, grad, bt->d_grad.p, sizeof(double) * (size_t)bt->n_grad, on_device)) != QV_OK)
+        return st;
     if ((st = copy_out(bt, js, bt->d_js.p, sizeof(double) * bt->B, on_device)) != QV_OK) return st;
     if (!on_device) {
         HIPCHK(hipStreamSynchronize(s));

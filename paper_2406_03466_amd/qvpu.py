@@ -262,9 +262,9 @@ class Batch:
     def js_gradient(self, target, method: int = QV_ADJOINT, upstream=None, js=None, grad=None):
         """Jensen-Shannon divergences against target distributions (layout of probabilities()) and the
         gradient of sum_b upstream_b JS_b. Host mode returns (js[B], grad); device mode takes float64
-        device tensors for target, upstream (or None), js and grad."""
+        device tensors for target, upstream (or None), js and grad (grad None: divergences only)."""
         lib = load()
-        if grad is None:
+        if grad is None and js is None:
             t = np.ascontiguousarray(target, np.float64)
             if t.shape != (self.n_amplitudes(),):
                 raise ValueError(f"target must hold {self.n_amplitudes()} values, got shape {t.shape}")

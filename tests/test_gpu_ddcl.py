@@ -156,3 +156,23 @@ def test_ddcl20_table2_size(qv, prec, method):
     gi = np.array(gold["grad_index"])
     check(g[gi], np.array(gold["grad"]), prec, 1.0, "gradient components", tol128=1e-11)
     assert abs(g[1199]) <= (1e-12 if prec == 1 else 1e-7)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_js_autograd(qv, prec):
+    """torch.autograd through the divergence: forward computes the divergences only, backward reuses the
+    forward states for one adjoint sweep seeded with dL/dJS_b."""
+    import torch
+    from paper_2406_03466_amd.autograd import js_divergence
+    say(f"ddcl autograd prec={prec}")
+    wl = W.ddcl(8, 2, sizes=[8, 6])
+    t = wl.extra["target"]
+    u = np.array([0.4, 2.0])
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    dev = torch.device("cuda:0")
+    theta = torch.tensor(wl.theta, device=dev, requires_grad=True)
+    js = js_divergence(theta, b, torch.tensor(t, device=dev))
+    (js * torch.tensor(u, device=dev)).sum().backward()
+    torch.cuda.synchronize()
+    check(js.detach().cpu().numpy(), OD.js_values(wl, t), prec, 1.0, "divergences")
+    check(theta.grad.cpu().numpy(), OD.js_grad_param_shift(wl, t, u), prec, float(np.abs(u).sum()), "gradient")
