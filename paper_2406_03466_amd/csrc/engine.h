@@ -173,6 +173,8 @@ struct LevelArgs {
     void *psi;
     void *lam;
     double *partials;
+    int32_t chunk;        // register-tiled levels: consecutive tiles per workgroup (set by the launcher)
+    int32_t pad;
 };
 
 // One persistent launch runs every level of a direction: workgroups claim items (level blocks in level

@@ -1095,20 +1095,21 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, int64_t blk, cons
     return false;
 }
 
-// A level launch: workgroups take chunks of tile_chunk<ADJ>() consecutive tiles (grid-stride over chunks);
-// within a chunk, a tile whose successor belongs to the same (circuit, pass) prefetches it. Forward passes
-// run two workgroups per CU and balance better with shorter chunks; the adjoint (one per CU) gains more
-// from longer prefetch chains (measured on the 20-qubit circuit-learning levels).
+// A level launch: workgroups take chunks of a.chunk consecutive tiles (grid-stride over chunks); within a
+// chunk, a tile whose successor belongs to the same (circuit, pass) prefetches it. Forward passes run two
+// workgroups per CU and balance better with shorter chunks (4); the adjoint (one per CU) gains more from
+// longer prefetch chains (8; measured on the 20-qubit circuit-learning levels). A level with too few
+// tiles to give every resident workgroup a full chunk gets shorter chunks, down to one tile.
 template <bool ADJ>
 constexpr int tile_chunk() { return ADJ ? 8 : 4; }
 
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void rtile_tiles(const LevelArgs &a)
 {
-    constexpr int kTileChunk = tile_chunk<ADJ>();
-    const int64_t nchunks = (a.n_blocks + kTileChunk - 1) / kTileChunk;
+    const int64_t ch = a.chunk;
+    const int64_t nchunks = (a.n_blocks + ch - 1) / ch;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const int64_t b0 = c * kTileChunk, b1 = b0 + kTileChunk < a.n_blocks ? b0 + kTileChunk : a.n_blocks;
+        const int64_t b0 = c * ch, b1 = b0 + ch < a.n_blocks ? b0 + ch : a.n_blocks;
         bool pre = false;
         for (int64_t blk = b0; blk < b1; blk++) {
             const int si = find_block(a.segs, a.n_segs, blk);
@@ -1757,16 +1758,35 @@ int launch_zero_u64(unsigned long long *p, int64_t n, void *stream)
     return hipGetLastError();
 }
 
-int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream)
+// Compute units of the current device (cached per device).
+static int device_cus()
 {
-    if (a.n_blocks <= 0) return hipSuccess;
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
+int launch_rlevel(const LevelArgs &a_in, int precision, int adjoint, void *stream)
+{
+    if (a_in.n_blocks <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int amp = precision == QV_C64 ? 8 : 16;
-    const size_t lds = tile_lds_bytes(a.lds_t, a.tab_bits, amp, adjoint) +
-                       (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)a.max_train : 0);
+    const size_t lds = tile_lds_bytes(a_in.lds_t, a_in.tab_bits, amp, adjoint) +
+                       (adjoint ? sizeof(double) * (kRtileThreads / 64) * (size_t)a_in.max_train : 0);
     if (lds > (size_t)kLdsLimit) return hipErrorInvalidValue;
-    // one workgroup per chunk of tiles
-    const int chunk = adjoint ? tile_chunk<true>() : tile_chunk<false>();
+    // one workgroup per chunk of tiles; chunks shrink until every resident workgroup (two per CU forward,
+    // one adjoint) has one
+    LevelArgs a = a_in;
+    const int64_t resident = (int64_t)device_cus() * (adjoint ? 1 : 2);
+    int64_t chunk = adjoint ? tile_chunk<true>() : tile_chunk<false>();
+    while (chunk > 1 && (a.n_blocks + chunk - 1) / chunk < resident) chunk >>= 1;
+    a.chunk = (int32_t)chunk;
     dim3 grid((unsigned)((a.n_blocks + chunk - 1) / chunk)), block(kRtileThreads);
     if (precision == QV_C64) {
         if (adjoint) hipLaunchKernelGGL((k_rtile_adj<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
