@@ -101,3 +101,27 @@ def test_js_gradient_matches_finite_differences():
     np.testing.assert_allclose(g, fd, atol=2e-8)
     sub = OD.js_grad_param_shift(wl, t, u, only={1, 30})
     assert sub[1] == g[1] and sub[30] == g[30] and np.count_nonzero(sub) <= 2
+
+
+@pytest.mark.parametrize("theta,target_index,want_js,want_g", [
+    (0.0, 2, 0.0, 0.0),                    # target reached exactly: JS = 0, flat
+    (0.0, 3, np.log(2.0), 0.0),            # disjoint supports: JS = log 2, flat at theta = 0
+    (np.pi / 2, 2, None, None),            # general point: closed form below
+])
+def test_degenerate_distributions(theta, target_index, want_js, want_g):
+    """X on qubit 1, then RY(theta) on qubit 0: Q(2) = cos^2(theta/2), Q(3) = sin^2(theta/2), zero
+    elsewhere; target a point mass. JS and its derivative in closed form (0 log 0 = 0)."""
+    wl = W.single("deg", 2, [W.gate(W.X, 1), W.gate(W.RY, 0, -1, 0)], [theta])
+    t = np.zeros(4)
+    t[target_index] = 1.0
+    c, s = np.cos(theta / 2) ** 2, np.sin(theta / 2) ** 2
+    q = np.array([0.0, 0.0, c, s])
+    if want_js is None:
+        # P = delta_2: JS = 1/2 [log(2/(1+c)) + c log(2c/(1+c)) + s log 2]
+        want_js = 0.5 * (np.log(2 / (1 + c)) + c * np.log(2 * c / (1 + c)) + s * np.log(2.0))
+        # d/dtheta with dc = -sin(theta)/2, ds = +sin(theta)/2 (the c/(1+c) terms cancel)
+        dc, ds = -np.sin(theta) / 2, np.sin(theta) / 2
+        want_g = 0.5 * (dc * np.log(2 * c / (1 + c)) + ds * np.log(2.0))
+    np.testing.assert_allclose(OD.probabilities(wl), q, atol=1e-15)
+    assert OD.js_values(wl, t)[0] == pytest.approx(want_js, abs=1e-15)
+    assert OD.js_grad_param_shift(wl, t)[0] == pytest.approx(want_g, abs=1e-15)

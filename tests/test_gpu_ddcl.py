@@ -176,3 +176,38 @@ def test_js_autograd(qv, prec):
     torch.cuda.synchronize()
     check(js.detach().cpu().numpy(), OD.js_values(wl, t), prec, 1.0, "divergences")
     check(theta.grad.cpu().numpy(), OD.js_grad_param_shift(wl, t, u), prec, float(np.abs(u).sum()), "gradient")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("theta,target_index", [(0.0, 2), (0.0, 3), (np.pi / 2, 2), (np.pi, 2)])
+def test_degenerate_distributions(qv, prec, method, theta, target_index):
+    """Point-mass targets and output distributions with zeros (0 log 0, zero weights): X on qubit 1 then
+    RY(theta) on qubit 0, against the oracle (pinned to the closed form on the CPU)."""
+    say(f"ddcl degenerate prec={prec} method={method} theta={theta} target={target_index}")
+    wl = W.single("deg", 2, [W.gate(W.X, 1), W.gate(W.RY, 0, -1, 0)], [theta])
+    t = np.zeros(4)
+    t[target_index] = 1.0
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    js, g = b.js_gradient(t, method)
+    check(js, OD.js_values(wl, t), prec, 1.0, "divergence")
+    check(g, OD.js_grad_param_shift(wl, t), prec, 1.0, "gradient")
+    assert np.isfinite(js).all() and np.isfinite(g).all()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("method", [0, 1])
+def test_js_gradient_shared_parameters(qv, prec, method):
+    """Circuits sharing one parameter vector (data-fed copies): the divergence gradients of all circuits
+    add into one vector."""
+    say(f"js shared params prec={prec} method={method}")
+    wl = W.qcl(n=7, layers=2, samples=3, seed_index=9)
+    rng = np.random.default_rng(5)
+    t = rng.exponential(size=wl.B << 7) * (rng.random(wl.B << 7) < 0.6)
+    for b in range(wl.B):
+        t[b << 7:(b + 1) << 7] /= t[b << 7:(b + 1) << 7].sum()
+    u = np.array([1.0, -0.5, 0.25])
+    bt = qv.Batch(ctx_for(qv), wl, prec)
+    js, g = bt.js_gradient(t, method, u)
+    check(js, OD.js_values(wl, t), prec, 1.0, "divergences")
+    check(g, OD.js_grad_param_shift(wl, t, u), prec, float(np.abs(u).sum()), "gradient")
