@@ -164,8 +164,27 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
             s_ps = timed(lambda: b.js_gradient(t, qvpu.QV_PARAM_SHIFT), sync, 1)
             rec["param_shift_gradient_ms"] = round(s_ps * 1e3, 2)
             rec["param_shift_circuit_evals_per_s"] = round((2 * wl.n_grad() + 1) / s_ps, 1)
-        out[f"ddcl{nq}_L10_c64"] = rec
+            rec["param_shift_measured"] = "full gradient"
         b.close()
+        if nq > 22:
+            # the same circuit with only its first K angles trainable (the rest fixed at their values):
+            # 2K + 1 circuits timed, the full gradient's 2 N_theta + 1 extrapolated per circuit
+            K = 64
+            g = wl.gates.copy()
+            keep = g["param"] < K
+            g["angle"][~keep] = wl.theta[g["param"][~keep]]
+            g["param"][~keep] = -1
+            sub = W.Workload(wl.name + f"[{K} params]", wl.n_qubits, wl.gate_offsets, g, np.array([K], np.int32),
+                             False, wl.theta[:K].copy(), wl.term_offsets, wl.xmask, wl.zmask, wl.coeff, False,
+                             dict(wl.extra))
+            b = qvpu.Batch(ctx(), sub, qvpu.QV_C64)
+            s_ps = timed(lambda: b.js_gradient(t, qvpu.QV_PARAM_SHIFT), sync, 1)
+            per = s_ps / (2 * K + 1)
+            rec["param_shift_gradient_ms"] = round(per * (2 * wl.n_grad() + 1) * 1e3, 1)
+            rec["param_shift_circuit_evals_per_s"] = round(1.0 / per, 1)
+            rec["param_shift_measured"] = f"extrapolated: {2 * K + 1} circuits timed ({s_ps * 1e3:.1f} ms)"
+            b.close()
+        out[f"ddcl{nq}_L10_c64"] = rec
     wl = W.config5() if only in (None, "hea32") else None
     for fusion in (["off", "8"] if wl is not None else []):
         b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
