@@ -10,7 +10,9 @@ It computes, by the plain definitions, what the GPU library computes:
   by central finite differences, and by the adjoint method (Jones and Gacon, 2020; not in the paper).
 
 The arithmetic lives in ``qv_oracle.c`` (plain C, complex128, OpenMP only across independent circuits
-or independent amplitude pairs). This module only builds and calls it.
+or independent amplitude pairs). This module only builds and calls it. The probability path of Section
+4.2 (output distributions, the Jensen-Shannon divergence of Eq. 3 and its parameter-shift gradient) is in
+``oracle/ddcl.py``, in numpy on top of this module's final states.
 """
 from __future__ import annotations
 
