@@ -124,6 +124,20 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                                        "speedup": round(s_ps / s_ad, 1),
                                        "param_shift_circuits": wl.B * (2 * wl.n_grad() + 1)}
         b.close()
+    # the benchmark workload in complex128 (FP64 throughout; register tiles of 2^12 amplitudes)
+    if only in (None, "qcl"):
+        wl = W.config3(8)
+        b = qvpu.Batch(ctx(fusion="off"), wl, qvpu.QV_C128)
+        e, _ = b.expectations(want_terms=False)
+        up = 2.0 * (e - wl.extra["y"]) / wl.B
+
+        def grad128():
+            b.expectations(want_terms=False)
+            b.gradient(qvpu.QV_ADJOINT, upstream=up)
+
+        s_ad = timed(grad128, sync, 3)
+        out["qcl20_L8_S64_c128"] = {"adjoint_gradients_per_s": round(1.0 / s_ad, 3), "ms": round(s_ad * 1e3, 3)}
+        b.close()
     wl = W.config2()
     for prec, name in ([(qvpu.QV_C64, "c64"), (qvpu.QV_C128, "c128")] if only in (None, "hea16") else []):
         b = qvpu.Batch(ctx(), wl, prec)
