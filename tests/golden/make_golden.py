@@ -58,11 +58,25 @@ def ddcl20_case():
             "seconds": time.time() - t0}
 
 
+def mcvqe22_case():
+    """Table 1's largest MC-VQE size: 22 CIS states of 22 qubits, 106 shared parameters, 128 terms and a
+    constant. Energies and the mean-energy gradient (upstream 1/22) by the oracle's adjoint."""
+    wl = W.mcvqe(22)
+    t0 = time.time()
+    e, _, mi, used = oracle.expectations(wl)
+    up = np.full(wl.B, 1.0 / wl.B)
+    g = oracle.grad_adjoint(wl, up)
+    return {"workload": wl.name, "what": "energies, mean-energy gradient by oracle adjoint",
+            "energies": e.tolist(), "upstream": up.tolist(), "grad": g.tolist(), "max_imag": mi,
+            "threads": used, "seconds": time.time() - t0}
+
+
 CASES = {
     "qcl20_L2": lambda: qcl_case(2),
     "qcl20_L8": lambda: qcl_case(8),
     "random1024": random_case,
     "ddcl20": ddcl20_case,
+    "mcvqe22": mcvqe22_case,
 }
 
 if __name__ == "__main__":

@@ -85,3 +85,26 @@ def test_mcvqe_zero_angles_give_cis_energies(qv):
     b = qv.Batch(ctx_for(qv), wl, 1)
     e, _ = b.expectations(want_terms=False)
     check(e, e_ref, 1, 1.0, "CIS energies")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_mcvqe22_table1_largest(qv, prec):
+    """Table 1's largest size (22 CIS states of 22 qubits, 106 parameters, 128 terms and a constant)
+    against the oracle's stored energies and mean-energy gradient. In complex128 a gradient component is a
+    sum over 22 x 2^22 products accumulated in different orders, so it is held to 1e-11 (energies 1e-12)."""
+    import os
+    say(f"mcvqe n=22 prec={prec}")
+    with open(os.path.join(os.path.dirname(__file__), "golden", "mcvqe22.json")) as f:
+        gold = json.load(f)
+    wl = W.mcvqe(22)
+    s = float(np.abs(wl.coeff).sum())
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    e, _ = b.expectations(want_terms=False)
+    check(e, np.array(gold["energies"]), prec, s, "energies")
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
+    ref = np.array(gold["grad"])
+    if prec == 1:
+        err = np.abs(g - ref)
+        assert err.max() <= 1e-11, f"gradient: max err {err.max():.3e}"
+    else:
+        check(g, ref, prec, s, "gradient")
