@@ -58,6 +58,28 @@ def ddcl20_case():
             "seconds": time.time() - t0}
 
 
+DDCL26_PARAMS = [0, 1559]
+
+
+def ddcl26_case():
+    """Table 2's largest DDCL size: 26 qubits, 10 layers, 1560 parameters. The divergence, 64 sampled
+    probabilities and 2 gradient components (the first angle and the last, which cannot change the
+    distribution) by the parameter-shift rule: 5 oracle circuits of 2^26 amplitudes."""
+    from oracle import ddcl as OD
+    wl = W.ddcl(26, 10)
+    t0 = time.time()
+    t = wl.extra["target"]
+    q = OD.probabilities(wl)
+    idx = np.random.default_rng(26).choice(len(q), size=64, replace=False)
+    js = OD.js_divergence(t, q)
+    del q
+    g = OD.js_grad_param_shift(wl, t, None, only=set(DDCL26_PARAMS))
+    return {"workload": wl.name, "what": "JS divergence, sampled probabilities, gradient components (param-shift)",
+            "js": js, "prob_index": idx.tolist(), "probs": [float(v) for v in OD.probabilities(wl)[idx]],
+            "grad_index": DDCL26_PARAMS, "grad": [float(g[j]) for j in DDCL26_PARAMS],
+            "seconds": time.time() - t0}
+
+
 def mcvqe22_case():
     """Table 1's largest MC-VQE size: 22 CIS states of 22 qubits, 106 shared parameters, 128 terms and a
     constant. Energies and the mean-energy gradient (upstream 1/22) by the oracle's adjoint."""
@@ -77,6 +99,7 @@ CASES = {
     "random1024": random_case,
     "ddcl20": ddcl20_case,
     "mcvqe22": mcvqe22_case,
+    "ddcl26": ddcl26_case,
 }
 
 if __name__ == "__main__":

@@ -211,3 +211,26 @@ def test_js_gradient_shared_parameters(qv, prec, method):
     js, g = bt.js_gradient(t, method, u)
     check(js, OD.js_values(wl, t), prec, 1.0, "divergences")
     check(g, OD.js_grad_param_shift(wl, t, u), prec, float(np.abs(u).sum()), "gradient")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ddcl26_table2_largest(qv, prec):
+    """Table 2's largest size (26 qubits, 10 layers, 1560 parameters), adjoint: the divergence, 64 sampled
+    probabilities and 2 gradient components against the oracle's stored values (complex128 components
+    held to 1e-11: sums over 2^26 products in different orders)."""
+    say(f"ddcl26 prec={prec}")
+    with open(os.path.join(HERE, "golden", "ddcl26.json")) as f:
+        gold = json.load(f)
+    wl = W.ddcl(26, 10)
+    t = wl.extra["target"]
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    q = b.probabilities()
+    idx = np.array(gold["prob_index"])
+    ref = np.array(gold["probs"])
+    err = np.abs(q[idx] - ref)
+    assert (err <= (1e-12 if prec == 1 else 1e-5 * np.maximum(ref, 2.0 ** -26))).all(), err.max()
+    del q
+    js, g = b.js_gradient(t, 0)
+    check(js, [gold["js"]], prec, 1.0, "divergence", tol128=1e-11)
+    gi = np.array(gold["grad_index"])
+    check(g[gi], np.array(gold["grad"]), prec, 1.0, "gradient components", tol128=1e-11)
