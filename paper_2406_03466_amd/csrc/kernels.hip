@@ -1408,9 +1408,10 @@ __global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
     const uint64_t i0 = (uint64_t)chunk << G.chunk_log2;
     if (x == 0) {
         const uint64_t dim = 1ull << C.n;
-        for (uint32_t e = threadIdx.x; e < per; e += kBlock) {
+        const uint32_t lim = (uint32_t)(dim - i0 < (uint64_t)per ? dim - i0 : (uint64_t)per);
+#pragma unroll 4
+        for (uint32_t e = threadIdx.x; e < lim; e += kBlock) {
             const uint64_t b = i0 + e;
-            if (b >= dim) break;
             const Cx<R> v = st[b];
             const double w = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
 #pragma unroll
@@ -1420,9 +1421,10 @@ __global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
     } else {
         const int h = 63 - __clzll(x);
         const uint64_t npairs = 1ull << (C.n - 1);
-        for (uint32_t e = threadIdx.x; e < per; e += kBlock) {
+        const uint32_t lim = (uint32_t)(npairs - i0 < (uint64_t)per ? npairs - i0 : (uint64_t)per);
+#pragma unroll 4
+        for (uint32_t e = threadIdx.x; e < lim; e += kBlock) {
             const uint64_t i = i0 + e;
-            if (i >= npairs) break;
             const uint64_t b = insert0_64(i, h);
             const Cx<R> a0 = st[b], a1 = st[b ^ x];
             // w = conj(psi[b ^ x]) psi[b]
