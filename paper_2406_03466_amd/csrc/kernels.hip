@@ -1491,8 +1491,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
     for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
         const uint64_t o = o0 + e;
         if (o >= dim) break;
-        // diagonal terms (x-mask 0) scale psi[o] itself: their signed coefficients are summed first
+        // diagonal terms (x-mask 0) scale psi[o] itself: their signed coefficients are summed first; the
+        // host orders the other terms by x-mask, so terms sharing one read psi[o ^ x] once
         double d = 0.0, sr = 0.0, si = 0.0;
+        uint64_t px = 0;
+        double vr = 0.0, vi = 0.0;
         for (int64_t t = tb; t < te; t++) {
             const DevObsTerm term = ldu(a.obs + t);
             if (term.xmask == 0) {
@@ -1500,8 +1503,13 @@ __global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
                 continue;
             }
             const uint64_t b = o ^ term.xmask;
-            const Cx<R> v = st[b];
-            double vr = v.re, vi = v.im, pr, pi;
+            if (term.xmask != px) {
+                const Cx<R> v = st[b];
+                vr = v.re;
+                vi = v.im;
+                px = term.xmask;
+            }
+            double pr, pi;
             switch (term.ny) {
             case 0: pr = vr; pi = vi; break;
             case 1: pr = -vi; pi = vr; break;

@@ -641,7 +641,11 @@ static void build_lambda(ExecSet &es, const ObsView &ov, const std::vector<int> 
         const int b = obs_of[c];
         const int64_t t0 = ov.obs_shared ? ov.toff[0] : ov.toff[b];
         const int64_t t1 = ov.obs_shared ? ov.toff[1] : ov.toff[b + 1];
-        for (int64_t t = t0; t < t1; t++) {
+        // terms ordered by x-mask (stable), so that k_lambda reads psi[o ^ x] once per distinct mask
+        std::vector<int64_t> order;
+        for (int64_t t = t0; t < t1; t++) order.push_back(t);
+        std::stable_sort(order.begin(), order.end(), [&](int64_t u, int64_t v) { return ov.xm[u] < ov.xm[v]; });
+        for (int64_t t : order) {
             DevObsTerm o;
             o.xmask = ov.xm[t];
             o.zmask = ov.zm[t];
