@@ -136,9 +136,15 @@ typedef struct qv_batch_s *qv_batch;
  *                      "lds" (LDS tile passes, one gate at a time in LDS) or "stride" (one global-memory
  *                      pass per gate);
  *   "tile_qubits"    : int 6..14 or "auto" (default "auto": the autotuner's choice);
- *   "launch"         : "levels" (one launch per pass level, default). "persistent" (all levels of a
- *                      sweep in one launch, resident workgroups taking tiles from a queue in level order)
- *                      is disabled in this version and returns QV_E_UNSUPPORTED;
+ *   "launch"         : "levels" (one launch per pass level, default) or "persistent" (all levels of a
+ *                      sweep in one launch: resident workgroups take tiles from a queue in level order and
+ *                      wait until their circuit's earlier passes are complete; a wait that runs out makes
+ *                      every later item skip its work and the call return QV_E_DEVICE). Sweeps whose passes
+ *                      are not all register-tiled, or whose tiles do not fit one persistent workgroup's
+ *                      LDS, run one launch per level;
+ *   "wait_ms"        : 0..600000, longest dependency wait of a persistent launch (default 4000);
+ *   "wait_extra"     : int >= 0 (default 0), added to every dependency count of a persistent launch so that
+ *                      those waits cannot be met: for testing the time-out path only;
  *   "fusion"         : "off" (default), "on" (runs of >= 6 gates) or a minimum run length: within a
  *                      register segment, consecutive gates acting only on its 4 register qubits are
  *                      multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);

@@ -194,8 +194,9 @@ struct PersistArgs {
     int64_t n_items;
     unsigned long long *head;    // queue head, zero before the launch
     unsigned long long *done;    // finished tiles per circuit, zero before the launch
-    int32_t *error;              // set to 1 if a wait hits its spin limit
-    int64_t spin_limit;          // sleep iterations before a wait gives up
+    int32_t *error;              // set to 1 if a wait runs out; later items then skip their work
+    int64_t wait_ticks;          // longest wait, in ticks of the device's constant-rate wall clock
+    int64_t wait_extra;          // added to every nonzero dependency count (0; a test sets it to force time-outs)
 };
 
 // Gate matrices of a batch: for every gate record, its 2x2 complex matrix at the current parameters.

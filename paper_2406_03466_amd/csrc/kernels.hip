@@ -1136,21 +1136,39 @@ __global__ __launch_bounds__(NT) void k_rtile_adj(LevelArgs a)
     rtile_tiles<R, true, RB, NT>(a);
 }
 
+// A value every lane of the workgroup holds (read back from LDS after a barrier), made wave-uniform for the
+// compiler, so that control flow depending on it is uniform.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 // Persistent form: workgroups stay resident and claim items from a queue. Items are the blocks of all
 // levels in level order, so every item an item waits for was claimed earlier by a running workgroup and
 // every wait ends. A finished tile is published with a device-scope release fence before its circuit's
-// counter is incremented; a waiting workgroup acquires after it has seen the count. Waits are bounded:
-// past spin_limit sleeps the workgroup records an error and goes on (the host reports it).
+// counter is incremented; a waiting workgroup acquires after it has seen the count.
+//
+// The claim loop keeps every thread of a workgroup on the same path: the next item is claimed by thread 0
+// in the same region that publishes the finished one, fenced by barriers on both sides, and the loop test
+// reads the claimed item as a wave-uniform value. (With the claim at the top of the loop and the
+// publication at its bottom, each under its own `threadIdx.x == 0` test, the compiler joins the two regions
+// across the loop's back edge and turns the loop into two nested loops whose inner one lets wave 0's other
+// lanes return to the top barrier without lane 0, re-read the old item and run it again, forever.)
+//
+// A wait is bounded by wait_ticks of the constant-rate wall clock. A wait that runs out sets *error; from
+// then on every workgroup skips the work of the items it claims (it still counts them finished, so no
+// other wait blocks on them) and the host reports the launch's results as invalid.
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void persistent_body(const PersistArgs &pa)
 {
     __shared__ long long item_s;
-    for (;;) {
-        if (threadIdx.x == 0) item_s = (long long)atomicAdd(pa.head, 1ull);
-        __syncthreads();
-        const int64_t item = item_s;
-        __syncthreads();
-        if (item >= pa.n_items) break;
+    __shared__ int run_s;
+    if (threadIdx.x == 0) item_s = (long long)atomicAdd(pa.head, 1ull);
+    __syncthreads();
+    int64_t item = uniform_i64(item_s);
+    while (item < pa.n_items) {
         int lo = 0, hi = pa.n_levels - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -1162,21 +1180,34 @@ __device__ __forceinline__ void persistent_body(const PersistArgs &pa)
         a.n_segs = lv.n_segs;
         const int64_t blk = item - lv.first_item;
         const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
-        if (threadIdx.x == 0 && sg.wait > 0) {
-            int64_t spins = 0;
-            while ((int64_t)__hip_atomic_load(pa.done + sg.circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < sg.wait) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > pa.spin_limit) { atomicOr(pa.error, 1); break; }
+        if (threadIdx.x == 0) {
+            int run = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+            if (run && sg.wait > 0) {
+                const int64_t need = sg.wait + pa.wait_extra;
+                const int64_t t0 = wall_clock64();
+                while ((int64_t)__hip_atomic_load(pa.done + sg.circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       need) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (wall_clock64() - t0 > pa.wait_ticks) {
+                        atomicOr(pa.error, 1);
+                        run = 0;
+                        break;
+                    }
+                }
             }
             __threadfence();
+            run_s = run;
         }
         __syncthreads();
-        rtile_body<R, ADJ, RB, NT>(a, blk, sg, false, -1);
+        if (uniform_i64(run_s)) rtile_body<R, ADJ, RB, NT>(a, blk, sg, false, -1);
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();
             atomicAdd(pa.done + sg.circ, 1ull);
+            item_s = (long long)atomicAdd(pa.head, 1ull);
         }
+        __syncthreads();
+        item = uniform_i64(item_s);
     }
 }
 

@@ -118,6 +118,8 @@ struct qv_ctx_s {
     int contig = 0;             // qubits 0..contig-1 always local (0: 4 for complex64, 3 for complex128)
     int autotune = 1;           // 0 off, 1 cached (use a stored choice), 2 search (time candidates once)
     int persistent = 0;         // 1: one persistent work-queue launch per direction instead of one per level
+    int wait_ms = 4000;         // persistent launches: longest dependency wait
+    int wait_extra = 0;         // persistent launches: added to every dependency count (tests of the time-out)
     int fuse_min = 0;           // >0: fuse runs of at least this many register-local gates into MFMA blocks
     int fold_cnots = 1;         // 1: CNOT runs at register-segment boundaries fold into the LDS addressing
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
@@ -795,6 +797,15 @@ static int enqueue_matrices(const qv_batch_s &bt, hipStream_t s, LaunchLog *log)
     return logged(log, s, QV_K_FUSE, -1, 0, [&] { return launch_fuse(fa, s); });
 }
 
+// Longest dependency wait of a persistent launch in ticks of the device's constant-rate wall clock (default
+// 4 s: a pass over the largest state that fits takes well under a second).
+static int64_t wait_ticks(int device, int ms)
+{
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) khz = 100000;
+    return (int64_t)khz * ms;
+}
+
 // One persistent launch for all levels of a direction (see k_rtile_*_persist).
 static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, int dir, void *psi, void *lam,
                               hipStream_t s, LaunchLog *log)
@@ -816,7 +827,8 @@ static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans 
     pa.head = es.d_p_head.as<unsigned long long>();
     pa.done = es.d_p_done.as<unsigned long long>();
     pa.error = es.d_p_error.as<int32_t>();
-    pa.spin_limit = (int64_t)1 << 21;  // ~0.1 s of 128-clock sleeps
+    pa.wait_ticks = wait_ticks(bt.ctx->device, bt.ctx->wait_ms);
+    pa.wait_extra = bt.ctx->wait_extra;
     int64_t bytes = 0;
     double flops = 0.0;
     for (const Level &lv : lvs) { bytes += lv.bytes; flops += lv.flops; }
@@ -967,10 +979,16 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             c->launch_events = (v == "true" || v == "1");
         } else if (k == "launch") {
             if (v == "levels") c->persistent = 0;
-            else if (v == "persistent")
-                // switched off: its first device run did not finish and the cause is not yet known
-                return fail(QV_E_UNSUPPORTED, "launch \"persistent\" is disabled in this version; use \"levels\"");
+            else if (v == "persistent") c->persistent = 1;
             else return fail(QV_E_INVALID, "launch must be \"levels\" or \"persistent\"");
+        } else if (k == "wait_ms") {
+            const int w = atoi(v.c_str());
+            if (w < 0 || w > 600000) return fail(QV_E_INVALID, "wait_ms must be in [0, 600000]");
+            c->wait_ms = w;
+        } else if (k == "wait_extra") {
+            const int w = atoi(v.c_str());
+            if (w < 0) return fail(QV_E_INVALID, "wait_extra must be >= 0");
+            c->wait_extra = w;
         } else if (k == "autotune") {
             if (v == "off") c->autotune = 0;
             else if (v == "cached") c->autotune = 1;
@@ -1437,7 +1455,7 @@ static qv_status forward(qv_batch bt)
     return QV_OK;
 }
 
-// A persistent launch whose wait hit its spin limit leaves a flag behind; report it once.
+// A persistent launch whose wait ran out leaves a flag behind; report it once.
 static qv_status check_persist_error(qv_batch bt)
 {
     std::vector<ExecSet *> sets{&bt->main};

@@ -136,14 +136,16 @@ def test_null_pointers_rejected():
     assert lib.qv_ctx_destroy(None) == qvpu.QV_E_INVALID
 
 
-@pytest.mark.parametrize("opts,code", [('{"launch": "persistent"}', "QV_E_UNSUPPORTED"),
+@pytest.mark.parametrize("opts,code", [('{"launch": "sometimes"}', "QV_E_INVALID"),
+                                       ('{"wait_ms": -1}', "QV_E_INVALID"),
+                                       ('{"wait_extra": -2}', "QV_E_INVALID"),
                                        ('{"fusion": 99}', "QV_E_INVALID"),
                                        ('{"fusion": "sometimes"}', "QV_E_INVALID"),
                                        ('{"tile_qubits": 20}', "QV_E_INVALID"),
                                        ('{"no_such_key": 1}', "QV_E_INVALID")])
 def test_context_options_checked_before_device(opts, code):
     """Context options are parsed before any device call, so a bad option is reported as such even on a
-    host without a GPU; the switched-off persistent launch mode says so."""
+    host without a GPU."""
     with pytest.raises(qvpu.QvError) as ei:
         qvpu.Context(0, None, opts)
     assert code in str(ei.value)
