@@ -244,3 +244,111 @@ def test_config_counts():
         assert c3.B == 64 and c3.n_grad() == P and int(c3.gate_offsets[1]) == G
     c5 = W.large_hea(32, 10)
     assert c5.n_grad() == 320 and int(c5.gate_offsets[-1]) == 950 and len(c5.xmask) == 31
+
+
+# ---- batch slicing (catch a wrong parameter base, term range or output offset for circuit b) ---------
+
+def _concat_batch(singles, params_shared, obs_shared):
+    """Packs single-circuit workloads into one batch by hand: circuit b's gates, parameters and terms
+    follow those of circuits 0..b-1 (or one parameter vector / one observable for all, when shared)."""
+    goff, toff, nq, npar = [0], [0], [], []
+    gates, theta, xm, zm, cf = [], [], [], [], []
+    for k, s in enumerate(singles):
+        nq.append(int(s.n_qubits[0]))
+        npar.append(int(s.n_params[0]))
+        gates.extend(s.gates.tolist())
+        goff.append(goff[-1] + len(s.gates))
+        if not params_shared or k == 0:
+            theta.extend(s.theta.tolist())
+        if not obs_shared or k == 0:
+            xm.extend(s.xmask.tolist())
+            zm.extend(s.zmask.tolist())
+            cf.extend(s.coeff.tolist())
+            toff.append(toff[-1] + len(s.xmask))
+    return W.Workload("concat", np.array(nq, np.int32), np.array(goff, np.int64), np.array(gates, W.GATE_DTYPE),
+                      np.array(npar, np.int32), params_shared, np.array(theta, np.float64),
+                      np.array(toff, np.int64), np.array(xm, np.uint64), np.array(zm, np.uint64),
+                      np.array(cf, np.float64), obs_shared)
+
+
+def _single_circuits(seed, shared_theta=None, shared_terms=None):
+    """Six circuits of 2..7 qubits with 0..30 gates and 0..5 terms (one without parameters, one without
+    terms), each with its own parameters (or a common vector) and terms (or a common observable)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, (n, G, T) in enumerate([(5, 30, 4), (2, 7, 3), (7, 25, 5), (3, 0, 2), (6, 18, 0), (4, 22, 3)]):
+        gates, p = [], 0
+        for _ in range(G):
+            kind = int(rng.choice([W.H, W.RX, W.RY, W.RZ, W.CNOT, W.CZ, W.S]))
+            if kind in (W.CNOT, W.CZ):
+                a, b = rng.choice(n, size=2, replace=False)
+                gates.append(W.gate(kind, int(a), int(b)))
+            elif kind in (W.RX, W.RY, W.RZ):
+                if shared_theta is not None:
+                    gates.append(W.gate(kind, int(rng.integers(n)), -1, int(rng.integers(len(shared_theta)))))
+                else:
+                    gates.append(W.gate(kind, int(rng.integers(n)), -1, p))
+                    p += 1
+            else:
+                gates.append(W.gate(kind, int(rng.integers(n))))
+        if k == 0 and shared_theta is None:   # a fixed-angle rotation among the trainable ones
+            gates.append(W.gate(W.RY, 1, -1, -1, 0.7))
+        theta = shared_theta if shared_theta is not None else rng.uniform(0, 2 * np.pi, p)
+        if shared_theta is not None:
+            p = len(shared_theta)
+        letters = rng.integers(0, 4, size=(T, 7))[:, :n]
+        terms = (*W.pauli_from_letters(letters), rng.normal(size=T)) if shared_terms is None else shared_terms
+        s = W.single(f"s{k}", n, gates, theta, terms)
+        s.n_params[0] = p
+        out.append(s)
+    return out
+
+
+def _oracle_outputs(wl, up):
+    e, tv, _, _ = oracle.expectations(wl)
+    return e, tv, oracle.grad_param_shift(wl, up), oracle.grad_fd(wl, 1e-4, up), oracle.grad_adjoint(wl, up)
+
+
+def test_batch_slicing_own_parameters_and_terms():
+    """Every oracle entry point on a batch of circuits with their own parameters and observables equals
+    the same circuits run one at a time, concatenated in circuit order."""
+    singles = _single_circuits(71)
+    up = np.array([0.5, -1.25, 2.0, 0.75, -0.3, 1.5])
+    e, tv, gps, gfd, gad = _oracle_outputs(_concat_batch(singles, False, False), up)
+    parts = [_oracle_outputs(s, up[k:k + 1]) for k, s in enumerate(singles)]
+    np.testing.assert_array_equal(e, np.concatenate([p[0] for p in parts]))
+    np.testing.assert_array_equal(tv, np.concatenate([p[1] for p in parts]))
+    for i in (2, 3, 4):
+        np.testing.assert_array_equal(np.concatenate([p[i] for p in parts]),
+                                      [gps, gfd, gad][i - 2])
+    assert len(gad) == sum(int(s.n_params[0]) for s in singles) and np.max(np.abs(gad)) > 1e-2
+
+
+def test_batch_slicing_shared_parameters_own_terms():
+    """One parameter vector for all circuits, an observable per circuit: energies and term values per
+    circuit, and every gradient equal to the weighted sum of the single circuits' gradients."""
+    theta = np.random.default_rng(72).uniform(0, 2 * np.pi, 5)
+    singles = _single_circuits(73, shared_theta=theta)
+    up = np.array([1.0, -0.5, 0.25, 2.0, 0.125, -1.5])
+    e, tv, gps, gfd, gad = _oracle_outputs(_concat_batch(singles, True, False), up)
+    parts = [_oracle_outputs(s, up[k:k + 1]) for k, s in enumerate(singles)]
+    np.testing.assert_array_equal(e, np.concatenate([p[0] for p in parts]))
+    np.testing.assert_array_equal(tv, np.concatenate([p[1] for p in parts]))
+    for i, g in zip((2, 3, 4), (gps, gfd, gad)):
+        assert len(g) == 5
+        np.testing.assert_allclose(g, np.sum([p[i] for p in parts], axis=0), rtol=0, atol=1e-14)
+
+
+def test_batch_slicing_own_parameters_shared_observable():
+    """Parameters per circuit, one observable for all (term values repeat it per circuit)."""
+    rng = np.random.default_rng(74)
+    letters = rng.integers(0, 4, size=(3, 2))
+    terms = (*W.pauli_from_letters(letters), rng.normal(size=3))
+    singles = _single_circuits(75, shared_terms=terms)
+    up = np.linspace(-1.0, 2.0, 6)
+    e, tv, gps, gfd, gad = _oracle_outputs(_concat_batch(singles, False, True), up)
+    parts = [_oracle_outputs(s, up[k:k + 1]) for k, s in enumerate(singles)]
+    np.testing.assert_array_equal(e, np.concatenate([p[0] for p in parts]))
+    np.testing.assert_array_equal(tv, np.concatenate([p[1] for p in parts]))
+    for i, g in zip((2, 3, 4), (gps, gfd, gad)):
+        np.testing.assert_array_equal(g, np.concatenate([p[i] for p in parts]))
