@@ -32,6 +32,7 @@
 #endif
 
 typedef double complex cplx;
+typedef long double complex lcplx;  /* accumulators of long sums */
 
 /* Gate record layout, 24 bytes: kind, q0, q1, param (-1 = fixed angle), angle. */
 typedef struct {
@@ -156,20 +157,23 @@ static void apply_pauli(const cplx *psi, cplx *out, int n, uint64_t x, uint64_t 
     }
 }
 
-/* <psi|P|psi> summed over all 2^n basis states; the imaginary part is returned through imag_out. */
+/* <psi|P|psi> summed over all 2^n basis states; the imaginary part is returned through imag_out.
+ * Products and the running sum are kept in the host's extended precision (long double), so that the
+ * rounding of a sum over millions of amplitudes stays far below the tolerance the results are checked
+ * to; the result is rounded to double once. */
 static double expect_pauli(const cplx *psi, int n, uint64_t x, uint64_t z, double *imag_out)
 {
     const int64_t dim = (int64_t)1 << n;
     const int ny = __builtin_popcountll(x & z) & 3;
-    const cplx iy[4] = {1, I, -1, -I};
-    cplx acc = 0;
+    const lcplx iy[4] = {1, I, -1, -I};
+    lcplx acc = 0;
     for (int64_t b = 0; b < dim; b++) {
-        cplx ph = iy[ny];
+        lcplx ph = iy[ny];
         if (__builtin_popcountll((uint64_t)b & z) & 1) ph = -ph;
-        acc += conj(psi[(uint64_t)b ^ x]) * ph * psi[b];
+        acc += conjl((lcplx)psi[(uint64_t)b ^ x]) * ph * (lcplx)psi[b];
     }
-    if (imag_out) *imag_out = cimag(acc);
-    return creal(acc);
+    if (imag_out) *imag_out = (double)cimagl(acc);
+    return (double)creall(acc);
 }
 
 /* Energy E = sum_t c_t <P_t> for one state. term_values may be NULL. */
@@ -424,9 +428,9 @@ int orc_batch_grad_adjoint(int32_t B, const int32_t *n_qubits, const int64_t *go
                 orc_gate gen = {gk, g[k].q0, -1, -1, 0.0};
                 memcpy(tmp, psi, sizeof(cplx) * (size_t)dim);
                 apply_gate(tmp, n, &gen, 0.0, 0);
-                cplx ip = 0;
-                for (int64_t i = 0; i < dim; i++) ip += conj(lam[i]) * tmp[i];
-                row[g[k].param] += cimag(ip);
+                lcplx ip = 0;  /* extended precision, as in expect_pauli */
+                for (int64_t i = 0; i < dim; i++) ip += conjl((lcplx)lam[i]) * (lcplx)tmp[i];
+                row[g[k].param] += (double)cimagl(ip);
             }
             apply_gate(psi, n, &g[k], a, 1);
             apply_gate(lam, n, &g[k], a, 1);
