@@ -3,12 +3,23 @@ every circuit, backward returns dL/dtheta from one adjoint reverse sweep (qv_bat
 QV_ADJOINT) seeded with the upstream gradient dL/dE_b. JSDivergenceFn: forward returns the Jensen-Shannon
 divergences JS_b(theta) of Eq. 3 against target distributions, backward one adjoint sweep seeded with
 dL/dJS_b times the divergence weights (qv_batch_js_gradient). Tensors stay on the device; torch's current
-stream orders the work."""
+stream orders the work.
+
+Both keep the parameters of their forward call: if the batch received other parameters in between (the
+same batch evaluated at several points before one backward), backward sets the saved ones again, and the
+gradient call re-runs the forward sweep at them before its reverse sweep."""
 from __future__ import annotations
 
 import torch
 
 from . import qvpu
+
+
+def _restore_params(ctx, batch, th):
+    """Sets the forward call's parameters again if the batch has received others since."""
+    if batch.param_version != ctx.version:
+        batch.set_params(th)
+        ctx.version = batch.param_version
 
 
 class ExpectationFn(torch.autograd.Function):
@@ -22,15 +33,18 @@ class ExpectationFn(torch.autograd.Function):
         energies = torch.empty(batch.B, dtype=torch.float64, device=theta.device)
         batch.expectations(energies, None)
         ctx.batch = batch
-        ctx.n_theta = th.numel()
+        ctx.version = batch.param_version
+        ctx.save_for_backward(th.clone())
         return energies
 
     @staticmethod
     def backward(ctx, grad_energies: torch.Tensor):
         batch = ctx.batch
+        (th,) = ctx.saved_tensors
         up = grad_energies.detach().to(torch.float64).contiguous()
         grad = torch.empty(batch.n_grad, dtype=torch.float64, device=up.device)
         batch.ctx.set_stream(torch.cuda.current_stream(up.device).cuda_stream)
+        _restore_params(ctx, batch, th)
         batch.gradient(qvpu.QV_ADJOINT, upstream=up, grad=grad)
         return grad, None
 
@@ -53,16 +67,18 @@ class JSDivergenceFn(torch.autograd.Function):
         js = torch.empty(batch.B, dtype=torch.float64, device=theta.device)
         batch.js_gradient(tg, qvpu.QV_ADJOINT, None, js, None)
         ctx.batch = batch
-        ctx.save_for_backward(tg)
+        ctx.version = batch.param_version
+        ctx.save_for_backward(tg, th.clone())
         return js
 
     @staticmethod
     def backward(ctx, grad_js: torch.Tensor):
         batch = ctx.batch
-        (tg,) = ctx.saved_tensors
+        (tg, th) = ctx.saved_tensors
         up = grad_js.detach().to(torch.float64).contiguous()
         grad = torch.empty(batch.n_grad, dtype=torch.float64, device=up.device)
         batch.ctx.set_stream(torch.cuda.current_stream(up.device).cuda_stream)
+        _restore_params(ctx, batch, th)
         batch.js_gradient(tg, qvpu.QV_ADJOINT, up, None, grad)
         return grad, None, None
 

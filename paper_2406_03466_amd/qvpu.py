@@ -210,11 +210,14 @@ class Batch:
         self.n_grad = wl.n_grad()
         self.n_tv = wl.B * int(wl.term_offsets[1] - wl.term_offsets[0]) if wl.obs_shared else \
             int(wl.term_offsets[-1] - wl.term_offsets[0])
+        self.param_version = 0
         if len(wl.theta) or self.n_grad == 0:
             self.set_params(np.asarray(wl.theta, np.float64))
 
     def set_params(self, theta):
-        """theta: host float64 array or a float64 device tensor."""
+        """theta: host float64 array or a float64 device tensor. Every call advances param_version, so a
+        caller holding an earlier version knows the batch has moved to other parameters."""
+        self.param_version += 1
         if isinstance(theta, np.ndarray):
             th = np.ascontiguousarray(theta, np.float64)
             if th.size == 0:

@@ -93,8 +93,25 @@ def mcvqe22_case():
             "threads": used, "seconds": time.time() - t0}
 
 
+def hea_ladder_case(n):
+    """The 32-qubit workload's shape (10 hardware-efficient layers, trainable RY, fixed RZ, the open ZZ
+    chain) at a size the oracle runs: energy, term values and the gradient of all 10 n RY angles by the
+    oracle's adjoint."""
+    wl = W.large_hea(n, 10)
+    t0 = time.time()
+    e, tv, mi, used = oracle.expectations(wl)
+    g = oracle.grad_adjoint(wl)
+    return {"workload": wl.name, "what": "energy, ZZ term values, gradient by oracle adjoint",
+            "energies": e.tolist(), "term_values": tv.tolist(), "grad": g.tolist(), "max_imag": mi,
+            "threads": used, "seconds": time.time() - t0}
+
+
 CASES = {
     "qcl20_L2": lambda: qcl_case(2),
+    "qcl20_L4": lambda: qcl_case(4),
+    "hea20_L10": lambda: hea_ladder_case(20),
+    "hea22_L10": lambda: hea_ladder_case(22),
+    "hea24_L10": lambda: hea_ladder_case(24),
     "qcl20_L8": lambda: qcl_case(8),
     "random1024": random_case,
     "ddcl20": ddcl20_case,

@@ -1,8 +1,7 @@
 """GPU parity for the probability path of Section 4.2 (output distributions, the Jensen-Shannon divergence
 of Eq. 3 and its gradient by the adjoint sweep and by the parameter-shift rule) against the CPU oracle.
 
-Tolerances: complex128 1e-12 absolute (gradients of the 20-qubit case 1e-11, as for the other full-size
-complex128 gradient: sums of 2^20 products accumulated in different orders). complex64: a probability
+Tolerances: complex128 1e-12 absolute. complex64: a probability
 within 1e-5 * max(Q_ref, 2^-n) (FP32 amplitudes carry a relative error of a few 1e-6 of the state's norm,
 so a probability's error is at the 2^-n scale) and the distribution within 1e-5 in L1; a divergence
 within 1e-5 * max(JS_ref, 1); a gradient component within 1e-5 * max(|g_ref|, sum_b |u_b|) (the loss is at
@@ -59,10 +58,11 @@ def check_probs(q, ref, wl, prec):
         assert e.sum() <= 1e-5, f"circuit {b}: L1 err {e.sum():.3e}"
 
 
-def check(x, ref, prec, scale, what, tol128=1e-12):
+def check(x, ref, prec, scale, what):
     x, ref = np.asarray(x), np.asarray(ref)
     err = np.abs(x - ref)
-    bad = err > (tol128 if prec == 1 else 1e-5 * np.maximum(np.abs(ref), scale))
+    say(f"  {what}: max err {err.max():.3e}")
+    bad = err > (1e-12 if prec == 1 else 1e-5 * np.maximum(np.abs(ref), scale))
     assert not bad.any(), f"{what}: max err {err.max():.3e} at {int(np.argmax(err))}"
 
 
@@ -154,7 +154,7 @@ def test_ddcl20_table2_size(qv, prec, method):
     js, g = b.js_gradient(t, method)
     check(js, [gold["js"]], prec, 1.0, "divergence")
     gi = np.array(gold["grad_index"])
-    check(g[gi], np.array(gold["grad"]), prec, 1.0, "gradient components", tol128=1e-11)
+    check(g[gi], np.array(gold["grad"]), prec, 1.0, "gradient components")
     assert abs(g[1199]) <= (1e-12 if prec == 1 else 1e-7)
 
 
@@ -216,8 +216,7 @@ def test_js_gradient_shared_parameters(qv, prec, method):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_ddcl26_table2_largest(qv, prec):
     """Table 2's largest size (26 qubits, 10 layers, 1560 parameters), adjoint: the divergence, 64 sampled
-    probabilities and 2 gradient components against the oracle's stored values (complex128 components
-    held to 1e-11: sums over 2^26 products in different orders)."""
+    probabilities and 2 gradient components against the oracle's stored values."""
     say(f"ddcl26 prec={prec}")
     with open(os.path.join(HERE, "golden", "ddcl26.json")) as f:
         gold = json.load(f)
@@ -231,6 +230,6 @@ def test_ddcl26_table2_largest(qv, prec):
     assert (err <= (1e-12 if prec == 1 else 1e-5 * np.maximum(ref, 2.0 ** -26))).all(), err.max()
     del q
     js, g = b.js_gradient(t, 0)
-    check(js, [gold["js"]], prec, 1.0, "divergence", tol128=1e-11)
+    check(js, [gold["js"]], prec, 1.0, "divergence")
     gi = np.array(gold["grad_index"])
-    check(g[gi], np.array(gold["grad"]), prec, 1.0, "gradient components", tol128=1e-11)
+    check(g[gi], np.array(gold["grad"]), prec, 1.0, "gradient components")

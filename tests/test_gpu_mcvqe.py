@@ -90,8 +90,7 @@ def test_mcvqe_zero_angles_give_cis_energies(qv):
 @pytest.mark.parametrize("prec", [1, 0])
 def test_mcvqe22_table1_largest(qv, prec):
     """Table 1's largest size (22 CIS states of 22 qubits, 106 parameters, 128 terms and a constant)
-    against the oracle's stored energies and mean-energy gradient. In complex128 a gradient component is a
-    sum over 22 x 2^22 products accumulated in different orders, so it is held to 1e-11 (energies 1e-12)."""
+    against the oracle's stored energies and mean-energy gradient."""
     import os
     say(f"mcvqe n=22 prec={prec}")
     with open(os.path.join(os.path.dirname(__file__), "golden", "mcvqe22.json")) as f:
@@ -103,8 +102,5 @@ def test_mcvqe22_table1_largest(qv, prec):
     check(e, np.array(gold["energies"]), prec, s, "energies")
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
     ref = np.array(gold["grad"])
-    if prec == 1:
-        err = np.abs(g - ref)
-        assert err.max() <= 1e-11, f"gradient: max err {err.max():.3e}"
-    else:
-        check(g, ref, prec, s, "gradient")
+    check(g, ref, prec, s, "gradient")
+    say(f"  max |dE| {np.abs(e - np.array(gold['energies'])).max():.2e}  max |dg| {np.abs(g - ref).max():.2e}")

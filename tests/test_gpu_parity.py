@@ -54,6 +54,7 @@ def check(x, ref, prec, scale, what):
     else:
         bad = err > c64_tol(ref, scale)
     assert not bad.any(), f"{what}: max err {err.max():.3e} at {int(np.argmax(err))}"
+    return float(err.max()) if err.size else 0.0
 
 
 def obs_scale(wl):
@@ -214,6 +215,32 @@ def test_qcl_autograd_small(qv, prec):
     check(theta.grad.cpu().numpy(), g_ref, prec, float(np.sum(np.abs(up))), "grad")
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autograd_same_batch_two_points(qv, prec):
+    """One batch evaluated at two parameter vectors before a single backward (as in a loss that compares
+    two points): each backward runs at its own forward's parameters, not at the ones the batch received
+    last. Checked against the oracle's adjoint gradient at each point."""
+    import torch
+    from paper_2406_03466_amd.autograd import expectation
+    say(f"autograd two points prec={prec}")
+    wl = W.qcl(n=10, layers=2, samples=6, seed_index=8)
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    th1 = torch.tensor(wl.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    th2_host = np.random.default_rng(3).uniform(0, 2 * np.pi, wl.theta.shape)
+    th2 = torch.tensor(th2_host, dtype=torch.float64, device="cuda", requires_grad=True)
+    u1 = np.linspace(-1.0, 1.0, wl.B)
+    u2 = np.linspace(0.5, -0.25, wl.B)
+    f1 = expectation(th1, b)
+    f2 = expectation(th2, b)
+    loss = (f1 * torch.tensor(u1, device="cuda")).sum() + (f2 * torch.tensor(u2, device="cuda")).sum()
+    loss.backward()
+    for th, th_host, u, f in ((th1, wl.theta, u1, f1), (th2, th2_host, u2, f2)):
+        wl_at = W.with_theta(wl, th_host)
+        e_ref, _, _, _ = oracle.expectations(wl_at)
+        check(f.detach().cpu().numpy(), e_ref, prec, 1.0, "energies")
+        check(th.grad.cpu().numpy(), oracle.grad_adjoint(wl_at, u), prec, float(np.sum(np.abs(u))), "grad")
+
+
 def _golden(name):
     p = os.path.join(HERE, "golden", name + ".json")
     if not os.path.exists(p):
@@ -221,20 +248,27 @@ def _golden(name):
     return json.load(open(p))
 
 
-@pytest.mark.parametrize("layers", [2, 8])
-def test_qcl20_full_size(qv, layers):
+# the launch configuration bench.py times (autotuned tile, fused blocks of >= 8 gates, eager launches)
+BENCH_OPTS = {"fusion": "8", "autotune": "search", "graph": False, "launch_events": True}
+
+
+@pytest.mark.parametrize("layers,opts", [(2, {}), (4, {}), (8, {}), (2, BENCH_OPTS), (4, BENCH_OPTS),
+                                         (8, BENCH_OPTS), (8, dict(BENCH_OPTS, launch="persistent"))])
+def test_qcl20_full_size(qv, layers, opts, tmp_path, monkeypatch):
     """20 qubits, 64 samples, complex64: every energy and every gradient component of the MSE loss against
-    the oracle's stored values, in the launch configuration the benchmark times."""
-    say(f"qcl20 L={layers}")
+    the oracle's stored values, with default options and in the launch configuration the benchmark times."""
+    monkeypatch.setenv("QV_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    say(f"qcl20 L={layers} opts={opts}")
     gold = _golden(f"qcl20_L{layers}")
     wl = W.config3(layers)
-    b = qv.Batch(ctx_for(qv), wl, 0)
+    b = qv.Batch(ctx_for(qv, **opts), wl, 0)
     e, _ = b.expectations(want_terms=False)
-    check(e, np.array(gold["energies"]), 0, 1.0, "energies")
+    ee = check(e, np.array(gold["energies"]), 0, 1.0, "energies")
     up = 2.0 * (e - wl.extra["y"]) / wl.B
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
-    check(g, np.array(gold["grad"]), 0, float(np.sum(np.abs(gold["upstream"]))), "grad")
+    ge = check(g, np.array(gold["grad"]), 0, float(np.sum(np.abs(gold["upstream"]))), "grad")
     assert np.max(np.abs(up - np.array(gold["upstream"]))) < 1e-5
+    say(f"  max |dE| {ee:.2e}  max |dg| {ge:.2e}  stats {b.stats()}")
 
 
 def test_random1024_full_size(qv):
@@ -456,15 +490,58 @@ def test_adjoint_stops_at_first_trainable_gate(qv, prec):
 
 def test_qcl20_full_size_complex128(qv):
     """20 qubits, 64 samples, 2 layers in complex128 (register tiles of 2^12 amplitudes, 8 per thread):
-    every energy to 1e-12 and every gradient component to 1e-11 against the oracle's stored values. A
-    gradient component here is a sum of 64 x 2^20 products that the oracle accumulates one amplitude after
-    another (worst-case rounding 2^20 x 1.1e-16 relative), so the two FP64 results differ by ~1e-12."""
+    every energy and every gradient component to 1e-12 against the oracle's stored values."""
     say("qcl20 L=2 c128")
     gold = _golden("qcl20_L2")
     wl = W.config3(2)
     b = qv.Batch(ctx_for(qv), wl, 1)
     e, _ = b.expectations(want_terms=False)
-    check(e, np.array(gold["energies"]), 1, 1.0, "energies")
+    ee = check(e, np.array(gold["energies"]), 1, 1.0, "energies")
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=np.array(gold["upstream"]))
-    err = np.abs(g - np.array(gold["grad"]))
-    assert err.max() <= 1e-11, f"grad: max err {err.max():.3e} at {int(np.argmax(err))}"
+    ge = check(g, np.array(gold["grad"]), 1, 1.0, "grad")
+    say(f"  max |dE| {ee:.2e}  max |dg| {ge:.2e}")
+
+
+@pytest.mark.parametrize("n", [20, 22, 24])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_hea_ladder_full_depth(qv, n, prec):
+    """The 32-qubit workload's shape (10 hardware-efficient layers, trainable RY, fixed RZ, open ZZ chain)
+    at 20, 22 and 24 qubits against the oracle's stored energy, term values and full gradient; complex64
+    with fused blocks of >= 8 gates (the option the 32-qubit figures use), complex128 unfused."""
+    say(f"hea ladder n={n} prec={prec}")
+    gold = _golden(f"hea{n}_L10")
+    wl = W.large_hea(n, 10)
+    opts = {"fusion": "8", "tile_qubits": 13} if prec == 0 else {}
+    b = qv.Batch(ctx_for(qv, **opts), wl, prec)
+    e, tv = b.expectations()
+    s = float(n - 1)
+    ee = check(e, np.array(gold["energies"]), prec, s, "energy")
+    te = check(tv, np.array(gold["term_values"]), prec, 1.0, "ZZ terms")
+    g, _ = b.gradient(qv.QV_ADJOINT)
+    ge = check(g, np.array(gold["grad"]), prec, s, "grad")
+    if prec == 0:
+        assert sum(p["n_fused"] for p in qv.plan_circuit(n, wl.circuit(0), 13, 0, 0, fuse_min=8)) > 0
+    say(f"  max |dE| {ee:.2e}  max |dterm| {te:.2e}  max |dg| {ge:.2e}")
+    b.close()
+
+
+def test_hea32_L10_fused_matches_unfused(qv):
+    """32 qubits (a 32 GiB complex64 state), 10 layers: the energy, the 31 ZZ terms and the 320-component
+    gradient with fused MFMA blocks of >= 8 gates agree with the unfused path to the complex64 bound (the
+    oracle cannot hold this state; the 20-24-qubit ladder pins the same circuit shape against it)."""
+    say("hea32 L10 fused vs unfused")
+    wl = W.config5()
+    out = {}
+    for fusion in ("off", "8"):
+        b = qv.Batch(ctx_for(qv, fusion=fusion, tile_qubits=13), wl, 0)
+        e, tv = b.expectations()
+        g, _ = b.gradient(qv.QV_ADJOINT)
+        out[fusion] = (e, tv, g)
+        say(f"  fusion {fusion}: E {e[0]:.9f}")
+        b.close()
+    (e0, tv0, g0), (e1, tv1, g1) = out["off"], out["8"]
+    # both sides carry complex64 rounding, so each is held to the bound against the other
+    ee = check(e1, e0, 0, 31.0, "energy")
+    te = check(tv1, tv0, 0, 1.0, "ZZ terms")
+    ge = check(g1, g0, 0, 31.0, "grad")
+    say(f"  max |dE| {ee:.2e}  max |dterm| {te:.2e}  max |dg| {ge:.2e}")
