@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak (256 CUs at 2.4 GHz)
 TILE_KERNELS = ("rtile", "rtile_adj", "rtile_persist", "rtile_adj_persist", "tile", "tile_adj")
+SEED_PROFILE = 240603466 + 11
 
 
 from paper_2406_03466_amd.profile_summary import kernel_source_hash  # noqa: E402
@@ -64,22 +65,93 @@ def summarize_launches(recs):
     return per
 
 
-def cpu_baseline(wl_full, max_seconds: float = 20.0):
-    """The oracle (plain complex128 CPU simulator) on a bounded sample: adjoint gradients of the first k
-    samples of the same workload, scaled to full gradients per second."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl_full, reps: int = 3):
+    """The oracle (plain complex128 CPU simulator) on a bounded sample, timed twice: with one thread (the
+    adjoint gradient of one sample) and with all host cores the box grants (one sample per thread, OpenMP
+    over circuits); each `reps` times, mean and standard deviation, scaled to full gradients per second."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
-    k = threads
-    sub = wl_full.subset(range(k))
-    e, _, _, _ = oracle.expectations(sub, nthreads=threads)
-    up = 2.0 * (e - sub.extra["y"]) / wl_full.B
-    t0 = time.time()
-    oracle.grad_adjoint(sub, up, nthreads=threads)
-    dt = time.time() - t0
-    used = oracle.max_threads(threads)
-    return {"value": (k / wl_full.B) / dt, "unit": "gradients/s", "cores": used, "kind": "oracle",
-            "sample": f"oracle adjoint gradient of {k} of the {wl_full.B} samples (complex128, {used} threads), "
-                      f"{dt:.1f} s, scaled by {k}/{wl_full.B}"}
+    out = {}
+    for label, nth in (("one_thread", 1), ("all_cores", threads)):
+        k = nth
+        sub = wl_full.subset(range(k))
+        e, _, _, _ = oracle.expectations(sub, nthreads=nth)
+        up = 2.0 * (e - sub.extra["y"]) / wl_full.B
+        ts = []
+        for _ in range(reps):
+            t0 = time.time()
+            oracle.grad_adjoint(sub, up, nthreads=nth)
+            ts.append(time.time() - t0)
+        used = oracle.max_threads(nth)
+        rates = [(k / wl_full.B) / t for t in ts]
+        out[label] = {"gradients_per_s": float(np.mean(rates)), "sd": float(np.std(rates)), "threads": used,
+                      "seconds_per_rep": [round(t, 3) for t in ts],
+                      "sample": f"oracle adjoint gradient of {k} of the {wl_full.B} samples, scaled by {k}/{wl_full.B}"}
+    a = out["all_cores"]
+    return {"value": a["gradients_per_s"], "sd": a["sd"], "unit": "gradients/s", "cores": a["threads"],
+            "kind": "oracle",
+            "sample": f"oracle adjoint gradient (complex128) of {a['threads']} of the {wl_full.B} samples on "
+                      f"{a['threads']} threads, mean of {reps}, scaled by {a['threads']}/{wl_full.B}",
+            "one_thread": out["one_thread"], "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def copy_ceiling(torch, stream, reps: int = 10) -> dict:
+    """A plain 1 GiB device-to-device copy (torch's copy kernel) timed with HIP events: the HBM rate a
+    streaming kernel can reach on this GPU, beside the published 8 TB/s."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    nbytes = 2 * src.numel() * 8
+    del src, dst
+    return {"bytes_per_copy": nbytes, "ms": round(ms, 4), "gbs": round(nbytes / 1e9 / (ms / 1e3), 1),
+            "frac_of_peak": round(nbytes / 1e9 / (ms / 1e3) / HBM_PEAK_GBS, 4)}
+
+
+def stride_profile(qvpu, W, stream, sync, n: int) -> dict:
+    """The stride engine alone on one n-qubit complex64 state: RY and RZ on every qubit (2n one-qubit
+    gates, each one global-memory pass reading and writing the whole state), then the ZZ-chain
+    expectation. Per-launch HIP events give each kernel's average time and algorithmic GB/s."""
+    gates = [W.gate(W.RY, q, -1, q) for q in range(n)] + [W.gate(W.RZ, q, -1, n + q) for q in range(n)]
+    theta = np.random.default_rng(SEED_PROFILE).uniform(0, 2 * np.pi, 2 * n)
+    zm = np.array([(1 << i) | (1 << (i + 1)) for i in range(n - 1)], np.uint64)
+    wl = W.single(f"ryrz{n}", n, gates, theta, (np.zeros(n - 1, np.uint64), zm, np.ones(n - 1)))
+    ctx = qvpu.Context(0, stream.cuda_stream, json.dumps({"engine": "stride", "graph": False,
+                                                           "launch_events": True}))
+    b = qvpu.Batch(ctx, wl, qvpu.QV_C64)
+    b.expectations()
+    sync()
+    b.launch_log()
+    for _ in range(3):
+        b.expectations()
+    sync()
+    per = summarize_launches(b.launch_log())
+    b.close()
+    out = {"workload": f"{n} qubits complex64 ({(8 << n) / 2**30:.2f} GiB), {2 * n} one-qubit gates, "
+                       f"{n - 1} ZZ terms; engine stride"}
+    for k, v in per.items():
+        out[k] = {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4),
+                  "algorithmic_bytes_per_launch": int(v["avg_bytes"]), "gbs": round(v["gbs"], 1),
+                  "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def timed(fn, stream_sync, reps: int = 1) -> float:
@@ -138,20 +210,30 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
         s_ad = timed(grad128, sync, 3)
         out["qcl20_L8_S64_c128"] = {"adjoint_gradients_per_s": round(1.0 / s_ad, 3), "ms": round(s_ad * 1e3, 3)}
         b.close()
+    # the 16-qubit VQE parameter-shift gradient (513 circuits) and 1024 uneven random circuits, each with
+    # one launch per pass level and with every sweep in one persistent launch
     wl = W.config2()
     for prec, name in ([(qvpu.QV_C64, "c64"), (qvpu.QV_C128, "c128")] if only in (None, "hea16") else []):
-        b = qvpu.Batch(ctx(), wl, prec)
-        s = timed(lambda: b.gradient(qvpu.QV_PARAM_SHIFT), sync, 3)
-        out[f"hea16_L8_T100_param_shift_{name}"] = {"circuit_evals_per_s": round(513 / s, 1),
-                                                     "gradient_ms": round(s * 1e3, 3), "circuits": 513}
-        b.close()
+        rec = {"circuits": 513}
+        for launch in ("levels", "persistent"):
+            b = qvpu.Batch(ctx(launch=launch), wl, prec)
+            s = timed(lambda: b.gradient(qvpu.QV_PARAM_SHIFT), sync, 3)
+            key = "" if launch == "levels" else "_persistent"
+            rec["circuit_evals_per_s" + key] = round(513 / s, 1)
+            rec["gradient_ms" + key] = round(s * 1e3, 3)
+            b.close()
+        out[f"hea16_L8_T100_param_shift_{name}"] = rec
     if only in (None, "random1024"):
         wl = W.config4()
-        b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
-        s = timed(lambda: b.expectations(), sync, 3)
-        out["random1024_expectations_c64"] = {"circuit_evals_per_s": round(wl.B / s, 1),
-                                              "ms": round(s * 1e3, 3), "circuits": wl.B}
-        b.close()
+        rec = {"circuits": wl.B}
+        for launch in ("levels", "persistent"):
+            b = qvpu.Batch(ctx(launch=launch), wl, qvpu.QV_C64)
+            s = timed(lambda: b.expectations(), sync, 3)
+            key = "" if launch == "levels" else "_persistent"
+            rec["circuit_evals_per_s" + key] = round(wl.B / s, 1)
+            rec["ms" + key] = round(s * 1e3, 3)
+            b.close()
+        out["random1024_expectations_c64"] = rec
     # MC-VQE-shaped batches at Table 1's sizes: one circuit per CIS state, mean-energy gradient
     for nq in ((16, 18, 20, 22) if only in (None, "mcvqe") else ()):
         wl = W.mcvqe(nq)
@@ -220,8 +302,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ps", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workload shapes")
-    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32", "mcvqe", "ddcl"],
+    ap.add_argument("--only", choices=["qcl", "hea16", "random1024", "hea32", "mcvqe", "ddcl", "stride"],
                     help="run only this one of the other workload shapes and print its figures")
+    ap.add_argument("--qubits", type=int, default=26, help="state size of --only stride")
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
@@ -251,6 +334,11 @@ def main():
     from paper_2406_03466_amd.autograd import expectation
     if args.only:
         st = torch.cuda.current_stream(torch.device("cuda:0"))
+        if args.only == "stride":
+            out = stride_profile(qvpu, W, st, torch.cuda.synchronize, args.qubits)
+            out["copy_ceiling"] = copy_ceiling(torch, st)
+            print(json.dumps(out), flush=True)
+            return
         print(json.dumps(other_workloads(qvpu, W, st, torch.cuda.synchronize, args.only)), flush=True)
         return
 
@@ -286,11 +374,15 @@ def main():
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     batch.launch_log()  # drop the warm-up records
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t_start.record(stream)
-    for _ in range(args.steps):
+    marks[0].record(stream)
+    for i in range(args.steps):
         step()
+        marks[i + 1].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
+    step_ms = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
     recs = batch.launch_log()
     tuned = batch.stats()
     if args.levels:
@@ -323,6 +415,15 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel_sym,
                     "launches": d["launches"], "avg_launch_ms": round(d["avg_ms"], 4),
                     "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
+    # fused 4-qubit blocks of the forward passes run on MFMA (a 32 x 32 real product per 16 amplitudes,
+    # 128 flops per amplitude per block); their flops are reported apart from the gates' algorithmic flops
+    fuse_min = {"off": 0, "on": 6}.get(args.fusion, None)
+    fuse_min = int(args.fusion) if fuse_min is None else fuse_min
+    n_fused = 0
+    if fuse_min and args.engine == "tiled":
+        n_fused = sum(p["n_fused"] for p in qvpu.plan_circuit(20, wl.circuit(0), tuned["tile_qubits"], qvpu.QV_C64,
+                                                               0, fuse_min=fuse_min))
+    fused = {"blocks_per_circuit": n_fused, "mfma_flops_per_forward": n_fused * 128.0 * (1 << 20) * wl.B}
     # forward-only circuit evals/s (the 64 circuits of one forward pass)
     fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("matrices", "fuse", "init", "tile", "rtile",
                                                           "rtile_persist", "stride", "expect",
@@ -381,6 +482,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_sd": round(float(np.std(step_ms)), 4),
+        "gradient_s_mean_sd": [round(float(np.mean(step_ms)) / 1e3, 6), round(float(np.std(step_ms)) / 1e3, 6)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -395,14 +498,17 @@ def main():
                    "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch,
                    "fusion": args.fusion},
         "roofline": roofline,
+        "fused_blocks": fused,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1),
                         "tflops": round(v["tflops"], 2)} for k, v in per.items()},
         "kernel_source_hash": kernel_source_hash(),
     }
     out.update(extra)
+    out["copy_ceiling"] = copy_ceiling(torch, stream)
     if not args.no_extras:
         out["other_workloads"] = other_workloads(qvpu, W, stream, torch.cuda.synchronize)
+        out["other_workloads"]["stride26_c64"] = stride_profile(qvpu, W, stream, torch.cuda.synchronize, 26)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

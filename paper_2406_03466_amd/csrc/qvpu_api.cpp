@@ -177,14 +177,17 @@ struct Level {
     int32_t tab_bits; // largest (tile qubits - contiguous low qubits) of the level's passes
 };
 
-// Algorithmic flops per amplitude of a gate: a dense complex 2x2 product costs two complex multiplies and
-// one complex add per output amplitude (14), a diagonal phase one complex multiply (6); X, Y, Z, CNOT and
-// CZ are permutations and sign flips (0). Fused-block markers add nothing (their gates are counted).
+// Algorithmic flops per amplitude of a gate, by what the gate's matrix needs, averaged over the two
+// amplitudes of a pair: RX and RY mix a pair with real weights (two real-times-complex products and one
+// complex add per output, 6); RZ multiplies both amplitudes by a phase (one complex multiply, 6); T
+// multiplies one of the two (3); H adds and subtracts the pair and scales by a real (4); X, Y, Z, S, CNOT
+// and CZ only move amplitudes or flip signs (0). Fused-block markers add nothing (their gates are counted).
 static double op_flops(int kind)
 {
     switch (kind) {
-    case QV_H: case QV_RX: case QV_RY: return 14.0;
-    case QV_S: case QV_T: case QV_RZ: return 6.0;
+    case QV_RX: case QV_RY: case QV_RZ: return 6.0;
+    case QV_H: return 4.0;
+    case QV_T: return 3.0;
     default: return 0.0;
     }
 }
