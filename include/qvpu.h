@@ -110,7 +110,8 @@ typedef enum {
     QV_K_PROBS = 16,             /* output distributions |psi|^2; with a target, divergence partials and weights */
     QV_K_DIAG_SEED = 17,         /* adjoint seed lambda = u diag(w) psi of the divergence weights */
     QV_K_DIAG_EXPECT = 18,       /* <psi|diag(w)|psi> partial sums (parameter-shift variants) */
-    QV_K_SEGMENT_SUM = 19        /* per-circuit sums of partials in a fixed order */
+    QV_K_SEGMENT_SUM = 19,       /* per-circuit sums of partials in a fixed order */
+    QV_K_SAMPLE = 20             /* shots from the output distributions and their bit-string counts */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -166,6 +167,8 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
 /* Points the context at another hipStream_t (NULL: the device's default stream). */
 qv_status qv_ctx_set_stream(qv_ctx ctx, void *hip_stream);
 
+/* Releases the caller's context. Batches created on it keep it alive: the context is freed when it has
+ * been destroyed and its last batch too, so batches and their context may be destroyed in either order. */
 qv_status qv_ctx_destroy(qv_ctx ctx);
 
 /* Submits a batch of circuits and its observable (Section 3.2: a vector of circuits executed on one
@@ -240,6 +243,27 @@ qv_status qv_batch_probabilities(qv_batch batch, double *probs, int32_t out_on_d
 qv_status qv_batch_js_gradient(qv_batch batch, qv_grad_method method, const double *target, const double *upstream,
                                double *js, double *grad, int32_t on_device);
 
+/* Shots and bit-string counts (Section 3.1: a circuit's execution result is the table of observed bit
+ * strings and how often each occurred; Section 4.2: the circuit-learning application consumes these
+ * counts). Runs the forward pass at the current parameters, forms each circuit's output distribution
+ * Q_b(x) = |psi_b[x]|^2 (FP64, as qv_batch_probabilities) and its running sum C_b(x) = Q_b(0) + ... + Q_b(x)
+ * in bit-string order (FP64, fixed summation order: blocks of 4096 bit strings summed left to right, then
+ * block offsets), and draws `shots` shots per circuit by inverse transform sampling: shot j of circuit b
+ * takes u = uniforms[b * shots + j] and is the first x with C_b(x) > u * C_b(2^{n_b} - 1). The uniforms
+ * are the caller's (any generator; host values must lie in [0, 1), device values outside it are clamped
+ * into it), so a draw is reproducible and can be checked against another implementation of the same rule.
+ * Outputs, each a device pointer when on_device, else host:
+ *   samples[B * shots]        (may be NULL) the bit string of every shot, in uniform order;
+ *   bitstrings, counts[B * shots] circuit b's distinct drawn bit strings in increasing order, from index
+ *                             b * shots on, and how many shots drew each (entries past n_distinct[b] are
+ *                             unspecified);
+ *   n_distinct[B]             how many distinct bit strings circuit b drew.
+ * bitstrings, counts and n_distinct are all given or all NULL; samples or they must be given.
+ * 1 <= shots <= 2^31 - 1. Buffers (the running sums, a 32-bit count per amplitude, the shot arrays) are
+ * allocated on first use and kept with the batch. QV_E_INVALID for bad arguments (nothing runs). */
+qv_status qv_batch_sample(qv_batch batch, int64_t shots, const double *uniforms, int64_t *samples,
+                          uint64_t *bitstrings, int64_t *counts, int64_t *n_distinct, int32_t on_device);
+
 /* Copies the final state of circuit b after the last forward pass: 2^n complex numbers, interleaved
  * (re, im), float for QV_C64 and double for QV_C128. */
 qv_status qv_batch_state(qv_batch batch, int32_t circuit, void *out, int32_t out_on_device);
@@ -253,6 +277,8 @@ qv_status qv_batch_stats(qv_batch batch, qv_stats *out);
  * with max_records = 0 to query the count). */
 qv_status qv_batch_launch_log(qv_batch batch, qv_launch_rec *out, int32_t max_records, int32_t *n_records);
 
+/* Waits for the batch's work on its context's stream, frees its device memory and graphs, and drops its
+ * reference to the context. */
 qv_status qv_batch_destroy(qv_batch batch);
 
 /* Message of the last failure on the calling thread ("" if none); valid until the next call. */

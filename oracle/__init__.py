@@ -12,7 +12,8 @@ It computes, by the plain definitions, what the GPU library computes:
 The arithmetic lives in ``qv_oracle.c`` (plain C, complex128, OpenMP only across independent circuits
 or independent amplitude pairs). This module only builds and calls it. The probability path of Section
 4.2 (output distributions, the Jensen-Shannon divergence of Eq. 3 and its parameter-shift gradient) is in
-``oracle/ddcl.py``, in numpy on top of this module's final states.
+``oracle/ddcl.py``, and shots drawn from the output distributions with their bit-string counts (Section
+3.1) in ``oracle/sampling.py``, both in numpy on top of this module's final states.
 """
 from __future__ import annotations
 

@@ -329,6 +329,36 @@ struct SegSumArgs {
     double scale;
 };
 
+// Shots from the output distributions. The distribution of circuit c (probs, pool layout) is split into the
+// probability path's blocks of kSampleBlock amplitudes (first_block as for ProbArgs). C(x), the running sum
+// of the distribution in bit-string order, is held as a block offset (sum of the earlier blocks) plus a
+// prefix within the block; a shot with uniform u is the first x with C(x) > u * C(last).
+constexpr int kSampleBlock = 4096;
+
+struct SampleArgs {
+    const DevCirc *circs;
+    int32_t n_circ;
+    const int64_t *first_block;  // [n_circ + 1]
+    int64_t n_blocks;
+    const double *probs;         // [pool amplitudes] the distributions
+    double *local;               // [pool amplitudes] prefix sums within each block
+    double *bsum;                // [n_blocks] block totals
+    double *boff;                // [n_blocks] sums of the circuit's earlier blocks
+    double *total;               // [n_circ] C(last)
+    int64_t shots;               // per circuit
+    const double *uniforms;      // [n_circ * shots]
+    int64_t *samples;            // [n_circ * shots] bit string of every shot
+    uint32_t *hist;              // [pool amplitudes] shots per bit string (zero before the draw)
+    int64_t *nnz;                // [n_blocks] distinct sampled bit strings per block
+    int64_t *noff;               // [n_blocks] of the circuit's earlier blocks
+    int64_t *n_distinct;         // [n_circ]
+    uint64_t *bits;              // [n_circ * shots] circuit c's distinct bit strings from c * shots on
+    int64_t *counts;             // [n_circ * shots] their counts
+};
+
+int launch_sample(const SampleArgs &a, void *stream);
+int launch_zero_hist(uint32_t *p, int64_t n, void *stream);
+
 int launch_probs(const ProbArgs &a, int precision, void *stream);
 int launch_diag_seed(const DiagArgs &a, int precision, void *stream);
 int launch_diag_expect(const DiagArgs &a, int precision, void *stream);
@@ -352,5 +382,6 @@ struct FuseArgs {
 };
 int launch_fuse(const FuseArgs &a, void *stream);
 int prepare_kernels();  // raises the dynamic-LDS limits; call once per device
+
 
 }  // namespace qv

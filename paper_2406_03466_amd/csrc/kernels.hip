@@ -1694,6 +1694,185 @@ __global__ void k_fill(double *p, int64_t n, double v)
 }
 
 // ------------------------------------------------------------------------------------------------------
+// Shots and bit-string counts (Section 3.1: a circuit's execution yields a table of observed bit strings
+// and their counts; Section 4.2 works on those counts). Every sum below runs in a fixed order, so the
+// draws are reproducible: a thread owns kSampleBlock / kBlock consecutive entries of a block and sums them
+// left to right, thread 0 scans the thread totals, and the block's prefixes are the thread's running sum
+// plus its offset.
+// ------------------------------------------------------------------------------------------------------
+constexpr int kSamplePer = kSampleBlock / kBlock;  // 16 entries per thread
+
+// Exclusive prefix of the kBlock values tot[] in thread order, in place; returns the block total.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T *tot)
+{
+    __syncthreads();
+    __shared__ T total_s;
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int t = 0; t < kBlock; t++) {
+            const T v = tot[t];
+            tot[t] = run;
+            run += v;
+        }
+        total_s = run;
+    }
+    __syncthreads();
+    return total_s;
+}
+
+// Per block: prefix sums of the distribution within the block (local) and the block total (bsum).
+__global__ __launch_bounds__(kBlock) void k_cdf_local(SampleArgs a)
+{
+    __shared__ double q[kSampleBlock];
+    __shared__ double tot[kBlock];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * kSampleBlock;
+    const uint32_t lim = (uint32_t)(dim - o0 < (uint64_t)kSampleBlock ? dim - o0 : (uint64_t)kSampleBlock);
+    const double *pr = a.probs + C.state_off + o0;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)kSampleBlock; e += kBlock) q[e] = e < lim ? pr[e] : 0.0;
+    __syncthreads();
+    const int t0 = threadIdx.x * kSamplePer;
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSamplePer; k++) {
+        run += q[t0 + k];
+        q[t0 + k] = run;
+    }
+    tot[threadIdx.x] = run;
+    const double total = block_exclusive_scan(tot);
+    const double off = tot[threadIdx.x];
+    double *lo = a.local + C.state_off + o0;
+#pragma unroll
+    for (int k = 0; k < kSamplePer; k++)
+        if ((uint32_t)(t0 + k) < lim) lo[t0 + k] = off + q[t0 + k];
+    if (threadIdx.x == 0) a.bsum[blk] = total;
+}
+
+// One workgroup per circuit: exclusive prefix of its block totals (boff) and the circuit's total.
+template <typename T>
+__device__ __forceinline__ T segment_exclusive_scan(const T *in, T *out, int64_t b0, int64_t b1)
+{
+    __shared__ T tot[kBlock];
+    const int64_t nb = b1 - b0;
+    const int64_t per = (nb + kBlock - 1) / kBlock;
+    const int64_t j0 = b0 + (int64_t)threadIdx.x * per;
+    const int64_t j1 = j0 + per < b1 ? j0 + per : b1;
+    T run = 0;
+    for (int64_t j = j0; j < j1; j++) run += in[j];
+    tot[threadIdx.x] = run;
+    const T total = block_exclusive_scan(tot);
+    T acc = tot[threadIdx.x];
+    for (int64_t j = j0; j < j1; j++) {
+        const T v = in[j];
+        out[j] = acc;
+        acc += v;
+    }
+    return total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cdf_blocks(SampleArgs a)
+{
+    const int c = blockIdx.x;
+    const double t = segment_exclusive_scan<double>(a.bsum, a.boff, a.first_block[c], a.first_block[c + 1]);
+    if (threadIdx.x == 0) a.total[c] = t;
+}
+
+// One thread per shot: the first bit string x with C(x) > u * C(last), by binary search over the circuit's
+// blocks and then within the block; the shot is counted in the histogram.
+__global__ __launch_bounds__(kBlock) void k_draw(SampleArgs a)
+{
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (int64_t)a.n_circ * a.shots) return;
+    const int c = (int)(s / a.shots);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    double u = a.uniforms[s];
+    u = u >= 0.0 ? u : 0.0;
+    u = u < 1.0 ? u : 0x1.fffffffffffffp-1;
+    const double target = u * a.total[c];
+    int64_t lo = a.first_block[c], hi = a.first_block[c + 1] - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.boff[mid] + a.bsum[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    const uint64_t o0 = (uint64_t)(lo - a.first_block[c]) * kSampleBlock;
+    const double off = a.boff[lo];
+    const double *loc = a.local + C.state_off + o0;
+    int64_t e0 = 0, e1 = (int64_t)(dim - o0 < (uint64_t)kSampleBlock ? dim - o0 : (uint64_t)kSampleBlock) - 1;
+    while (e0 < e1) {
+        const int64_t mid = (e0 + e1) >> 1;
+        if (off + loc[mid] > target) e1 = mid;
+        else e0 = mid + 1;
+    }
+    const uint64_t x = o0 + (uint64_t)e0;
+    if (a.samples) a.samples[s] = (int64_t)x;
+    atomicAdd(a.hist + C.state_off + x, 1u);
+}
+
+// Per block: how many bit strings were drawn at least once.
+__global__ __launch_bounds__(kBlock) void k_hist_nnz(SampleArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * kSampleBlock;
+    double n = 0.0;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)kSampleBlock; e += kBlock)
+        if (o0 + e < dim && a.hist[C.state_off + o0 + e] != 0u) n += 1.0;
+    n = block_sum(n, red);
+    if (threadIdx.x == 0) a.nnz[blk] = (int64_t)n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hist_offsets(SampleArgs a)
+{
+    const int c = blockIdx.x;
+    const int64_t t = segment_exclusive_scan<int64_t>(a.nnz, a.noff, a.first_block[c], a.first_block[c + 1]);
+    if (threadIdx.x == 0) a.n_distinct[c] = t;
+}
+
+// Per block: its drawn bit strings and counts, in increasing order, after those of earlier blocks.
+__global__ __launch_bounds__(kBlock) void k_hist_emit(SampleArgs a)
+{
+    __shared__ int64_t tot[kBlock];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const int c = find_prefix(a.first_block, a.n_circ, blk);
+    const DevCirc C = a.circs[c];
+    const uint64_t dim = 1ull << C.n;
+    const uint64_t o0 = (uint64_t)(blk - a.first_block[c]) * kSampleBlock;
+    const int t0 = threadIdx.x * kSamplePer;
+    const uint32_t *h = a.hist + C.state_off + o0;
+    int64_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kSamplePer; k++)
+        if (o0 + (uint64_t)(t0 + k) < dim && h[t0 + k] != 0u) cnt++;
+    tot[threadIdx.x] = cnt;
+    block_exclusive_scan(tot);
+    int64_t pos = (int64_t)c * a.shots + a.noff[blk] + tot[threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < kSamplePer; k++) {
+        const uint64_t x = o0 + (uint64_t)(t0 + k);
+        if (x < dim && h[t0 + k] != 0u) {
+            a.bits[pos] = x;
+            a.counts[pos] = (int64_t)h[t0 + k];
+            pos++;
+        }
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------------------------
 // LDS of a tile launch: the tile (twice for the adjoint), the table of 2^tab_bits run offsets, and a
@@ -2003,6 +2182,33 @@ int launch_fill(double *p, int64_t n, double v, void *stream)
     if (n <= 0) return hipSuccess;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+
+// Shots and counts: block prefixes, block offsets, the draw, then the compaction of the histogram. The
+// histogram (one 32-bit count per amplitude of the pool) is cleared by a kernel, not a memset, so the
+// sequence can sit in a captured graph.
+int launch_sample(const SampleArgs &a, void *stream)
+{
+    if (a.n_blocks <= 0 || a.n_circ <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const unsigned nb = (unsigned)a.n_blocks;
+    hipLaunchKernelGGL(k_cdf_local, dim3(nb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_cdf_blocks, dim3((unsigned)a.n_circ), dim3(kBlock), 0, s, a);
+    const int64_t nshots = (int64_t)a.n_circ * a.shots;
+    hipLaunchKernelGGL(k_draw, dim3((unsigned)((nshots + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_hist_nnz, dim3(nb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_hist_offsets, dim3((unsigned)a.n_circ), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_hist_emit, dim3(nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_zero_hist(uint32_t *p, int64_t n, void *stream)
+{
+    if (n <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

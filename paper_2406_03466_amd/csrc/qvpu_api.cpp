@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,7 +107,17 @@ static bool parse_options(const char *js, std::map<std::string, std::string> &ou
 // ---------------------------------------------------------------------------------------------------------
 // Context and batch objects
 // ---------------------------------------------------------------------------------------------------------
+// Makes `device` current and clears the runtime's last-error slot, so that the launch checks of this call
+// (which read that slot) report only this call's launches, not an earlier failure another call ignored.
+static hipError_t enter_device(int device)
+{
+    const hipError_t e = hipSetDevice(device);
+    (void)hipGetLastError();
+    return e;
+}
+
 struct qv_ctx_s {
+    std::atomic<int> refs{1};   // the caller's reference plus one per live batch
     int device = 0;
     hipStream_t user_stream = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -359,6 +370,7 @@ struct qv_batch_s {
     // divergence weights dJS/dP_theta, divergence partial sums and values
     std::vector<int64_t> pfb;
     DBuf d_pfb, d_probs, d_target, d_w, d_js_part, d_js;
+    DBuf d_slocal, d_bsum, d_boff, d_stotal, d_uni, d_samples, d_hist, d_nnz, d_noff, d_ndist, d_bits, d_counts;
 
     hipGraphExec_t g_fwd = nullptr, g_adj = nullptr, g_ps = nullptr, g_js_adj = nullptr, g_js_ps = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1019,7 +1031,7 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(QV_E_INVALID, "device %d out of range (%d devices)", device, ndev);
     c->device = device;
-    HIPCHK(hipSetDevice(device));
+    HIPCHK(enter_device(device));
     int e = prepare_kernels();
     if (e) return fail(QV_E_DEVICE, "kernel setup failed: %s", hipGetErrorString((hipError_t)e));
     c->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1035,12 +1047,19 @@ qv_status qv_ctx_set_stream(qv_ctx ctx, void *hip_stream)
     return ok();
 }
 
+// Drops one reference; the last one frees the context (its capture stream).
+static void ctx_release(qv_ctx ctx)
+{
+    if (ctx->refs.fetch_sub(1) != 1) return;
+    if (hipSetDevice(ctx->device) == hipSuccess && ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    (void)hipGetLastError();  // a failure here must not be reported by the next call's launch checks
+    delete ctx;
+}
+
 qv_status qv_ctx_destroy(qv_ctx ctx)
 {
     if (!ctx) return fail(QV_E_INVALID, "ctx must not be NULL");
-    (void)hipSetDevice(ctx->device);
-    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    delete ctx;
+    ctx_release(ctx);
     return ok();
 }
 
@@ -1231,7 +1250,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     *out = nullptr;
     qv_status st = validate(B, nq, goff, gates, np, params_shared, toff, xm, zm, cf, obs_shared, prec);
     if (st != QV_OK) return st;
-    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(enter_device(ctx->device));
     auto bt = std::make_unique<qv_batch_s>();
     bt->ctx = ctx;
     bt->B = B;
@@ -1278,6 +1297,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     HIPCHK(hipEventCreate(&bt->ev0));
     HIPCHK(hipEventCreate(&bt->ev1));
     if (bt->n_theta == 0) bt->theta_set = true;
+    ctx->refs.fetch_add(1);  // the context stays alive until this batch is destroyed
     *out = bt.release();
     return ok();
 }
@@ -1290,7 +1310,7 @@ qv_status qv_batch_set_params(qv_batch bt, const double *theta, int32_t on_devic
     if (!on_device)
         for (int64_t i = 0; i < bt->n_theta; i++)
             if (!std::isfinite(theta[i])) return fail(QV_E_INVALID, "theta[%lld] is not finite", (long long)i);
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     hipStream_t s = bt->ctx->stream();
     HIPCHK(hipMemcpyAsync(bt->d_theta.p, theta, sizeof(double) * (size_t)bt->n_theta,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
@@ -1486,7 +1506,7 @@ qv_status qv_batch_expectations(qv_batch bt, double *energies, double *term_valu
 {
     if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
     if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     HIPCHK(hipEventRecord(bt->ev0, bt->ctx->stream()));
     qv_status st = forward(bt);
     if (st != QV_OK) return st;
@@ -1500,6 +1520,7 @@ qv_status qv_batch_expectations(qv_batch bt, double *energies, double *term_valu
     }
     return ok();
 }
+
 
 static qv_status ensure_lambda(qv_batch bt)
 {
@@ -1614,7 +1635,7 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
     if (!grad) return fail(QV_E_INVALID, "grad must not be NULL");
     if (method != QV_ADJOINT && method != QV_PARAM_SHIFT) return fail(QV_E_INVALID, "unknown gradient method %d", (int)method);
     if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     hipStream_t s = bt->ctx->stream();
     if (upstream) {
         if (!on_device)
@@ -1706,9 +1727,8 @@ static void diag_prefix(const std::vector<DevCirc> &circs, std::vector<int64_t> 
     for (size_t c = 0; c < circs.size(); c++) fb[c + 1] = fb[c] + ((((int64_t)1 << circs[c].n) + 4095) / 4096);
 }
 
-static qv_status alloc_doubles(DBuf &d, int64_t n, const char *what)
+static qv_status alloc_bytes(DBuf &d, size_t bytes, const char *what)
 {
-    const size_t bytes = sizeof(double) * (size_t)std::max<int64_t>(1, n);
     if (d.p && d.bytes >= bytes) return QV_OK;
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
@@ -1717,6 +1737,11 @@ static qv_status alloc_doubles(DBuf &d, int64_t n, const char *what)
                     freeb / 1073741824.0);
     HIPCHK(d.alloc(bytes));
     return QV_OK;
+}
+
+static qv_status alloc_doubles(DBuf &d, int64_t n, const char *what)
+{
+    return alloc_bytes(d, sizeof(double) * (size_t)std::max<int64_t>(1, n), what);
 }
 
 static qv_status ensure_prob_blocks(qv_batch bt)
@@ -1745,7 +1770,7 @@ qv_status qv_batch_probabilities(qv_batch bt, double *probs, int32_t out_on_devi
     if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
     if (!probs) return fail(QV_E_INVALID, "probs must not be NULL");
     if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     qv_status st;
     if ((st = ensure_prob_blocks(bt)) != QV_OK) return st;
     if ((st = alloc_doubles(bt->d_probs, bt->main.state_amps, "output distributions")) != QV_OK) return st;
@@ -1768,6 +1793,89 @@ qv_status qv_batch_probabilities(qv_batch bt, double *probs, int32_t out_on_devi
     return ok();
 }
 
+qv_status qv_batch_sample(qv_batch bt, int64_t shots, const double *uniforms, int64_t *samples,
+                          uint64_t *bitstrings, int64_t *counts, int64_t *n_distinct, int32_t on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!uniforms) return fail(QV_E_INVALID, "uniforms must not be NULL");
+    if (shots < 1 || shots > (int64_t)INT32_MAX) return fail(QV_E_INVALID, "shots must be in [1, 2^31 - 1]");
+    const bool want_counts = bitstrings || counts || n_distinct;
+    if (want_counts && !(bitstrings && counts && n_distinct))
+        return fail(QV_E_INVALID, "bitstrings, counts and n_distinct must be given together");
+    if (!want_counts && !samples) return fail(QV_E_INVALID, "nothing to return: give samples or the counts");
+    const int64_t nshots = (int64_t)bt->B * shots;
+    if (nshots > ((int64_t)1 << 40)) return fail(QV_E_INVALID, "too many shots in total");
+    if (!on_device)
+        for (int64_t i = 0; i < nshots; i++)
+            if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0))
+                return fail(QV_E_INVALID, "uniforms[%lld] = %g is not in [0, 1)", (long long)i, uniforms[i]);
+    if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
+    HIPCHK(enter_device(bt->ctx->device));
+    qv_status st;
+    if ((st = ensure_prob_blocks(bt)) != QV_OK) return st;
+    const int64_t amps = bt->main.state_amps, nb = bt->pfb[bt->B];
+    if ((st = alloc_doubles(bt->d_probs, amps, "output distributions")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_slocal, amps, "running sums")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_bsum, nb, "block sums")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_boff, nb, "block offsets")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_stotal, bt->B, "distribution totals")) != QV_OK) return st;
+    if ((st = alloc_doubles(bt->d_uni, nshots, "uniforms")) != QV_OK) return st;
+    if ((st = alloc_bytes(bt->d_samples, sizeof(int64_t) * (size_t)nshots, "samples")) != QV_OK) return st;
+    if ((st = alloc_bytes(bt->d_hist, sizeof(uint32_t) * (size_t)std::max<int64_t>(1, amps), "counts per bit string")) != QV_OK)
+        return st;
+    if ((st = alloc_bytes(bt->d_nnz, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nb), "block counts")) != QV_OK) return st;
+    if ((st = alloc_bytes(bt->d_noff, sizeof(int64_t) * (size_t)std::max<int64_t>(1, nb), "block count offsets")) != QV_OK)
+        return st;
+    if ((st = alloc_bytes(bt->d_ndist, sizeof(int64_t) * (size_t)bt->B, "distinct counts")) != QV_OK) return st;
+    if ((st = alloc_bytes(bt->d_bits, sizeof(uint64_t) * (size_t)nshots, "drawn bit strings")) != QV_OK) return st;
+    if ((st = alloc_bytes(bt->d_counts, sizeof(int64_t) * (size_t)nshots, "drawn counts")) != QV_OK) return st;
+    hipStream_t s = bt->ctx->stream();
+    HIPCHK(hipMemcpyAsync(bt->d_uni.p, uniforms, sizeof(double) * (size_t)nshots,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(bt->ev0, s));
+    if ((st = forward(bt)) != QV_OK) return st;
+    ProbArgs pa = prob_args(*bt);
+    pa.probs = bt->d_probs.as<double>();
+    LaunchLog *log = bt->ctx->launch_events ? &bt->log : nullptr;
+    int e = logged(log, s, QV_K_PROBS, -1, amps * (bt->amp_bytes + (int64_t)sizeof(double)),
+                   [&] { return launch_probs(pa, bt->prec, s); });
+    if (e) return fail(QV_E_DEVICE, "probabilities launch failed: %s", hipGetErrorString((hipError_t)e));
+    SampleArgs sa{};
+    sa.circs = bt->main.d_circs.as<DevCirc>();
+    sa.n_circ = bt->B;
+    sa.first_block = bt->d_pfb.as<int64_t>();
+    sa.n_blocks = nb;
+    sa.probs = bt->d_probs.as<double>();
+    sa.local = bt->d_slocal.as<double>();
+    sa.bsum = bt->d_bsum.as<double>();
+    sa.boff = bt->d_boff.as<double>();
+    sa.total = bt->d_stotal.as<double>();
+    sa.shots = shots;
+    sa.uniforms = bt->d_uni.as<double>();
+    sa.samples = bt->d_samples.as<int64_t>();
+    sa.hist = bt->d_hist.as<uint32_t>();
+    sa.nnz = bt->d_nnz.as<int64_t>();
+    sa.noff = bt->d_noff.as<int64_t>();
+    sa.n_distinct = bt->d_ndist.as<int64_t>();
+    sa.bits = bt->d_bits.as<uint64_t>();
+    sa.counts = bt->d_counts.as<int64_t>();
+    // probabilities read, running sums written and read back, the histogram cleared, counted and scanned
+    const int64_t bytes = amps * (3 * (int64_t)sizeof(double) + 3 * (int64_t)sizeof(uint32_t)) + nshots * 40;
+    e = logged(log, s, QV_K_SAMPLE, -1, bytes, [&] {
+        const int z = launch_zero_hist(sa.hist, amps, s);
+        return z ? z : launch_sample(sa, s);
+    });
+    if (e) return fail(QV_E_DEVICE, "sampling launch failed: %s", hipGetErrorString((hipError_t)e));
+    HIPCHK(hipEventRecord(bt->ev1, s));
+    bt->timed = true;
+    if ((st = copy_out(bt, samples, bt->d_samples.p, sizeof(int64_t) * (size_t)nshots, on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, bitstrings, bt->d_bits.p, sizeof(uint64_t) * (size_t)nshots, on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, counts, bt->d_counts.p, sizeof(int64_t) * (size_t)nshots, on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, n_distinct, bt->d_ndist.p, sizeof(int64_t) * (size_t)bt->B, on_device)) != QV_OK) return st;
+    if (!on_device) HIPCHK(hipStreamSynchronize(s));
+    return ok();
+}
+
 qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double *target, const double *upstream,
                                double *js, double *grad, int32_t on_device)
 {
@@ -1785,7 +1893,7 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
             for (int b = 0; b < bt->B; b++)
                 if (!std::isfinite(upstream[b])) return fail(QV_E_INVALID, "upstream[%d] is not finite", b);
     }
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     qv_status st;
     if ((st = ensure_prob_blocks(bt)) != QV_OK) return st;
     if ((st = alloc_doubles(bt->d_target, n, "target distributions")) != QV_OK) return st;
@@ -1935,7 +2043,7 @@ qv_status qv_batch_state(qv_batch bt, int32_t circuit, void *out, int32_t out_on
     if (!out) return fail(QV_E_INVALID, "out must not be NULL");
     if (circuit < 0 || circuit >= bt->B) return fail(QV_E_INVALID, "circuit %d out of range [0, %d)", circuit, bt->B);
     if (!bt->fwd_valid) return fail(QV_E_STATE, "no forward state: call qv_batch_expectations first");
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     const DevCirc &c = bt->main.circs[circuit];
     const size_t bytes = ((size_t)1 << c.n) * bt->amp_bytes;
     HIPCHK(hipMemcpyAsync(out, (char *)bt->d_psi.p + (size_t)c.state_off * bt->amp_bytes, bytes,
@@ -1947,7 +2055,7 @@ qv_status qv_batch_state(qv_batch bt, int32_t circuit, void *out, int32_t out_on
 qv_status qv_batch_stats(qv_batch bt, qv_stats *out)
 {
     if (!bt || !out) return fail(QV_E_INVALID, "batch and out must not be NULL");
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     if (bt->timed) {
         HIPCHK(hipEventSynchronize(bt->ev1));
         float ms = 0.f;
@@ -1976,12 +2084,15 @@ qv_status qv_batch_stats(qv_batch bt, qv_stats *out)
 qv_status qv_batch_destroy(qv_batch bt)
 {
     if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
-    (void)hipSetDevice(bt->ctx->device);
-    (void)hipStreamSynchronize(bt->ctx->stream());
+    qv_ctx ctx = bt->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream());
     drop_graphs(bt);
     if (bt->ev0) (void)hipEventDestroy(bt->ev0);
     if (bt->ev1) (void)hipEventDestroy(bt->ev1);
     delete bt;
+    (void)hipGetLastError();  // failures while tearing down are not reported by a later call
+    ctx_release(ctx);
     return ok();
 }
 
@@ -1991,7 +2102,7 @@ qv_status qv_batch_launch_log(qv_batch bt, qv_launch_rec *out, int32_t max_recor
 {
     if (!bt || !n_records) return fail(QV_E_INVALID, "batch and n_records must not be NULL");
     if (max_records > 0 && !out) return fail(QV_E_INVALID, "out must not be NULL when max_records > 0");
-    HIPCHK(hipSetDevice(bt->ctx->device));
+    HIPCHK(enter_device(bt->ctx->device));
     const int32_t n = (int32_t)bt->log.recs.size();
     *n_records = n;
     if (n == 0) return ok();

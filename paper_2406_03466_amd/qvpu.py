@@ -44,7 +44,7 @@ class qv_launch_rec(ctypes.Structure):
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
                 "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices", "rtile_persist",
-                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum"]
+                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum", "sample"]
 
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),
@@ -56,8 +56,8 @@ _lib = None
 
 EXPORTS = ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
            "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_probabilities",
-           "qv_batch_js_gradient", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy", "qv_batch_launch_log",
-           "qv_plan_circuit", "qv_last_error", "qv_version"]
+           "qv_batch_js_gradient", "qv_batch_sample", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy",
+           "qv_batch_launch_log", "qv_plan_circuit", "qv_last_error", "qv_version"]
 
 
 def load():
@@ -79,6 +79,7 @@ def load():
     lib.qv_batch_gradient.argtypes = [P, i32, P, P, P, i32]
     lib.qv_batch_probabilities.argtypes = [P, P, i32]
     lib.qv_batch_js_gradient.argtypes = [P, i32, P, P, P, P, i32]
+    lib.qv_batch_sample.argtypes = [P, ctypes.c_int64, P, P, P, P, P, i32]
     lib.qv_batch_state.argtypes = [P, i32, P, i32]
     lib.qv_batch_stats.argtypes = [P, ctypes.POINTER(qv_stats)]
     lib.qv_batch_destroy.argtypes = [P]
@@ -87,7 +88,7 @@ def load():
                                     ctypes.POINTER(qv_pass_info), ctypes.POINTER(i32), P]
     for f in ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
               "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_probabilities",
-              "qv_batch_js_gradient", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy",
+              "qv_batch_js_gradient", "qv_batch_sample", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy",
               "qv_batch_launch_log", "qv_plan_circuit"]:
         getattr(lib, f).restype = st
     lib.qv_last_error.restype = ctypes.c_char_p
@@ -278,6 +279,29 @@ class Batch:
             return j, g[: self.n_grad]
         _check(lib.qv_batch_js_gradient(self.h, int(method), _ptr(target), _ptr(upstream), _ptr(js), _ptr(grad), 1))
         return js, grad
+
+    def sample(self, shots: int, uniforms, samples=None, bitstrings=None, counts=None, n_distinct=None,
+               want_samples: bool = True):
+        """qv_batch_sample. Host mode (uniforms a numpy array of B * shots values in [0, 1)): returns
+        (samples[B * shots] or None, [(bitstrings, counts) per circuit]). Device mode: uniforms and the
+        outputs are device tensors (int64 samples or None, uint64-as-int64 bitstrings, int64 counts and
+        n_distinct), filled in stream order."""
+        lib = load()
+        if isinstance(uniforms, np.ndarray):
+            u = np.ascontiguousarray(uniforms, np.float64)
+            if u.shape != (self.B * shots,):
+                raise ValueError(f"uniforms must hold {self.B * shots} values, got shape {u.shape}")
+            smp = np.zeros(self.B * shots, np.int64) if want_samples else None
+            bits = np.zeros(self.B * shots, np.uint64)
+            cnt = np.zeros(self.B * shots, np.int64)
+            nd = np.zeros(self.B, np.int64)
+            _check(lib.qv_batch_sample(self.h, int(shots), _ptr(u), _ptr(smp), _ptr(bits), _ptr(cnt), _ptr(nd), 0))
+            per = [(bits[b * shots: b * shots + nd[b]].copy(), cnt[b * shots: b * shots + nd[b]].copy())
+                   for b in range(self.B)]
+            return smp, per
+        _check(lib.qv_batch_sample(self.h, int(shots), _ptr(uniforms), _ptr(samples), _ptr(bitstrings),
+                                   _ptr(counts), _ptr(n_distinct), 1))
+        return samples, bitstrings, counts, n_distinct
 
     def state(self, circuit: int) -> np.ndarray:
         n = int(self.wl.n_qubits[circuit])

@@ -241,6 +241,42 @@ def test_autograd_same_batch_two_points(qv, prec):
         check(th.grad.cpu().numpy(), oracle.grad_adjoint(wl_at, u), prec, float(np.sum(np.abs(u))), "grad")
 
 
+def test_context_destroyed_before_its_batch(qv):
+    """A batch keeps its context alive: destroying the context first (as a garbage collector may do with
+    objects in a reference cycle) leaves the batch usable, and destroying the batch afterwards frees both."""
+    say("context destroyed first")
+    wl = W.config1()
+    e_ref, _, _, _ = oracle.expectations(wl)
+    ctx = ctx_for(qv)
+    b = qv.Batch(ctx, wl, 1)
+    ctx.close()
+    e, _ = b.expectations()
+    check(e, e_ref, 1, 1.0, "energies after the context was destroyed")
+    b.close()
+    b2 = qv.Batch(ctx_for(qv), wl, 1)
+    check(b2.expectations()[0], e_ref, 1, 1.0, "energies on a new context")
+
+
+def test_earlier_runtime_error_not_reported(qv):
+    """A failed HIP call made by someone else on this thread (here hipSetDevice with a device that does
+    not exist) leaves the runtime's last-error slot set; the library's next call clears it on entry and
+    succeeds instead of reporting that error as its own launch failure."""
+    import ctypes
+    say("stale runtime error")
+    lib = qv.load()
+    set_device = lib.hipSetDevice      # the HIP runtime the library itself uses (found through its handle)
+    set_device.argtypes = [ctypes.c_int]
+    set_device.restype = ctypes.c_int
+    wl = W.config1()
+    e_ref, _, _, _ = oracle.expectations(wl)
+    for graph in (True, False):
+        b = qv.Batch(ctx_for(qv, graph=graph), wl, 1)
+        assert set_device(4096) != 0
+        e, _ = b.expectations()
+        check(e, e_ref, 1, 1.0, f"energies (graph {graph})")
+        b.close()
+
+
 def _golden(name):
     p = os.path.join(HERE, "golden", name + ".json")
     if not os.path.exists(p):
