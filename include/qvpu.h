@@ -208,6 +208,19 @@ qv_status qv_batch_set_params(qv_batch batch, const double *theta, int32_t theta
  * The final states stay on the device for a following adjoint gradient. */
 qv_status qv_batch_expectations(qv_batch batch, double *energies, double *term_values, int32_t out_on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same computation and outputs as qv_batch_expectations, with no
+ * hipMalloc, hipFree or other allocating call. The expectation partial sums live in a static device array
+ * of the library (8 MiB, at most 2^20 partial sums, held by every device the library runs on until the
+ * process ends); a batch needing more (about 2^20 / ceil(2^n / 2^14) x-mask groups of up to 8 terms per
+ * n-qubit circuit) gets QV_E_INVALID and nothing runs. Every call on one device shares that array, so
+ * calls that overlap on one device (several streams or threads) race; calls in one stream do not. The
+ * work is launched eagerly on the context's stream (no graph), and the batch must already have its launch
+ * configuration: a batch whose autotuner has still to choose tiles (context option "autotune" "search",
+ * or a stored choice that differs) gets QV_E_STATE until one qv_batch_expectations call has run. Outputs
+ * as for qv_batch_expectations (host outputs synchronise). */
+qv_status qv_batch_expectations_static(qv_batch batch, double *energies, double *term_values, int32_t out_on_device);
+
 /* Gradient of L = sum_b w_b E_b with w = upstream[B] (NULL: all ones). grad receives n_params[0] values
  * when parameters are shared (summed over circuits), else sum n_params values (circuit b's own slice).
  * QV_ADJOINT runs the forward pass, seeds lambda_b = w_b H psi_b and sweeps the gates backwards,

@@ -383,5 +383,10 @@ struct FuseArgs {
 int launch_fuse(const FuseArgs &a, void *stream);
 int prepare_kernels();  // raises the dynamic-LDS limits; call once per device
 
+// Static scratch of the non-allocating expectation call (a file-scope device array, one per device).
+constexpr int64_t kStaticScratchDoubles = (int64_t)1 << 20;  // 8 MiB
+constexpr int kMaxStaticDevices = 64;
+int static_scratch_setup(int device);  // looks up the array's address on `device`, which must be current
+double *static_scratch(int device);    // that address, or NULL before static_scratch_setup
 
 }  // namespace qv

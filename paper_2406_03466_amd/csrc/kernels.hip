@@ -12,6 +12,8 @@
 //     Im <lambda| G |psi> for every trainable gate exp(-i a G / 2).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "engine.h"
 
 namespace qv {
@@ -1976,6 +1978,34 @@ int launch_zero_u64(unsigned long long *p, int64_t n, void *stream)
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
+}
+
+// Scratch of qv_batch_expectations_static: the expectation partial sums of one call, at most
+// kStaticScratchDoubles of them. Every device the library runs on holds its own copy until the process
+// ends. The host-side name `scratch` is not a device address: host code uses the address looked up per
+// device by static_scratch_setup, never the name itself.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+static double *g_scratch_addr[kMaxStaticDevices];
+static std::mutex g_scratch_mu;
+
+int static_scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_addr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
+double *static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxStaticDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_addr[device];
 }
 
 // Compute units of the current device (cached per device).

@@ -852,8 +852,9 @@ static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans 
 }
 
 static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp, void *psi, double *energies,
-                           double *tv, double *norms, hipStream_t s, LaunchLog *log)
+                           double *tv, double *norms, hipStream_t s, LaunchLog *log, double *partials = nullptr)
 {
+    if (!partials) partials = es.d_exp_partials.as<double>();
     int e = logged(log, s, QV_K_INIT, -1, es.init_bytes, [&] {
         return launch_init_states(psi, es.d_circs.as<DevCirc>(), es.d_init_fb.as<int64_t>(), es.n_circ,
                                   es.init_blocks, bt.prec, s);
@@ -888,7 +889,7 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     ea.terms = es.d_terms.as<DevTerm>();
     ea.circs = es.d_circs.as<DevCirc>();
     ea.psi = psi;
-    ea.partials = es.d_exp_partials.as<double>();
+    ea.partials = partials;
     e = logged(log, s, QV_K_EXPECT, -1, es.exp_bytes, [&] { return launch_expectation(ea, bt.prec, s); });
     if (e) return e;
     FinalizeArgs fa;
@@ -898,7 +899,7 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     fa.term_refs = es.d_term_refs.as<PartialRef>();
     fa.coeff = es.d_coeff.as<double>();
     fa.norm_refs = norms ? es.d_norm_refs.as<PartialRef>() : nullptr;
-    fa.partials = es.d_exp_partials.as<double>();
+    fa.partials = partials;
     fa.term_values = tv;
     fa.energies = energies;
     fa.norms = norms;
@@ -1034,6 +1035,8 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
     HIPCHK(enter_device(device));
     int e = prepare_kernels();
     if (e) return fail(QV_E_DEVICE, "kernel setup failed: %s", hipGetErrorString((hipError_t)e));
+    if ((e = static_scratch_setup(device)) != 0)
+        return fail(QV_E_DEVICE, "static scratch lookup failed: %s", hipGetErrorString((hipError_t)e));
     c->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     *out = c.release();
@@ -1423,6 +1426,20 @@ static qv_status time_forward(qv_batch bt, double &ms)
     return QV_OK;
 }
 
+// True when autotune() would leave the launch configuration as it is (no re-planning, no allocation).
+static bool tune_settled(qv_batch bt)
+{
+    if (bt->tuned) return true;
+    qv_ctx ctx = bt->ctx;
+    if (ctx->autotune == 0 || ctx->engine == 2 || ctx->tile_qubits || ctx->contig) return true;
+    int nmax = 0;
+    for (int b = 0; b < bt->B; b++) nmax = std::max(nmax, bt->nq[b]);
+    if (nmax <= (bt->prec == QV_C64 ? 13 : 12)) return true;
+    int T = 0, contig = 0;
+    if (tune_lookup(tune_key(bt), T, contig)) return T == bt->tile_qubits && contig == bt->contig;
+    return ctx->autotune != 2;
+}
+
 static qv_status autotune(qv_batch bt)
 {
     bt->tuned = 1;
@@ -1521,6 +1538,50 @@ qv_status qv_batch_expectations(qv_batch bt, double *energies, double *term_valu
     return ok();
 }
 
+
+// The non-allocating form of qv_batch_expectations: the same kernels, launched eagerly (no graph), with
+// the expectation partial sums in the static scratch array instead of the batch's buffer. Every call on a
+// device shares that device's array (calls that overlap on one device race); the partial sums are written
+// in full before they are read, so nothing needs clearing.
+qv_status qv_batch_expectations_static(qv_batch bt, double *energies, double *term_values, int32_t out_on_device)
+{
+    if (!bt) return fail(QV_E_INVALID, "batch must not be NULL");
+    if (!bt->theta_set) return fail(QV_E_STATE, "qv_batch_set_params must be called first");
+    ExecSet &es = bt->main;
+    if (es.exp_partials > kStaticScratchDoubles)
+        return fail(QV_E_INVALID, "the batch's expectations need %lld partial sums, more than the %lld of the static "
+                                  "scratch; use qv_batch_expectations", (long long)es.exp_partials,
+                    (long long)kStaticScratchDoubles);
+    if (!tune_settled(bt))
+        return fail(QV_E_STATE, "the autotuner has still to choose this batch's tiles (which allocates): call "
+                                "qv_batch_expectations once first, or use \"autotune\": \"off\" or fixed tile sizes");
+    bt->tuned = 1;
+    double *scr = static_scratch(bt->ctx->device);
+    if (!scr) return fail(QV_E_STATE, "the static scratch of device %d is not set up", bt->ctx->device);
+    HIPCHK(enter_device(bt->ctx->device));
+    hipStream_t s = bt->ctx->stream();
+    HIPCHK(hipEventRecord(bt->ev0, s));
+    int e = enqueue_matrices(*bt, s, nullptr);
+    if (!e)
+        e = enqueue_forward(*bt, es, *bt->dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                            bt->d_norms.as<double>(), s, nullptr, scr);
+    if (e) return fail(QV_E_DEVICE, "launch failed: %s", hipGetErrorString((hipError_t)e));
+    HIPCHK(hipEventRecord(bt->ev1, s));
+    bt->timed = true;
+    bt->fwd_valid = true;
+    bt->last = qv_stats{};
+    bt->last.passes = es.passes_fwd;
+    bt->last.launches = 3 + (int64_t)es.fwd.size();
+    bt->last.algorithmic_bytes = es.algo_bytes_fwd;
+    qv_status st;
+    if ((st = copy_out(bt, energies, bt->d_energies.p, sizeof(double) * bt->B, out_on_device)) != QV_OK) return st;
+    if ((st = copy_out(bt, term_values, bt->d_tv.p, sizeof(double) * (size_t)bt->n_tv, out_on_device)) != QV_OK) return st;
+    if (!out_on_device) {
+        HIPCHK(hipStreamSynchronize(s));
+        if ((st = check_persist_error(bt)) != QV_OK) return st;
+    }
+    return ok();
+}
 
 static qv_status ensure_lambda(qv_batch bt)
 {

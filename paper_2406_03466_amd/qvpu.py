@@ -55,7 +55,7 @@ class qv_pass_info(ctypes.Structure):
 _lib = None
 
 EXPORTS = ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
-           "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_probabilities",
+           "qv_batch_set_params", "qv_batch_expectations", "qv_batch_expectations_static", "qv_batch_gradient", "qv_batch_probabilities",
            "qv_batch_js_gradient", "qv_batch_sample", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy",
            "qv_batch_launch_log", "qv_plan_circuit", "qv_last_error", "qv_version"]
 
@@ -76,6 +76,7 @@ def load():
     lib.qv_validate_batch.argtypes = [i32, P, P, P, P, i32, P, P, P, P, i32, i32]
     lib.qv_batch_set_params.argtypes = [P, P, i32]
     lib.qv_batch_expectations.argtypes = [P, P, P, i32]
+    lib.qv_batch_expectations_static.argtypes = [P, P, P, i32]
     lib.qv_batch_gradient.argtypes = [P, i32, P, P, P, i32]
     lib.qv_batch_probabilities.argtypes = [P, P, i32]
     lib.qv_batch_js_gradient.argtypes = [P, i32, P, P, P, P, i32]
@@ -87,7 +88,7 @@ def load():
     lib.qv_plan_circuit.argtypes = [i32, ctypes.c_int64, P, i32, i32, i32, i32, i32,
                                     ctypes.POINTER(qv_pass_info), ctypes.POINTER(i32), P]
     for f in ["qv_ctx_create", "qv_ctx_set_stream", "qv_ctx_destroy", "qv_batch_create", "qv_validate_batch",
-              "qv_batch_set_params", "qv_batch_expectations", "qv_batch_gradient", "qv_batch_probabilities",
+              "qv_batch_set_params", "qv_batch_expectations", "qv_batch_expectations_static", "qv_batch_gradient", "qv_batch_probabilities",
               "qv_batch_js_gradient", "qv_batch_sample", "qv_batch_state", "qv_batch_stats", "qv_batch_destroy",
               "qv_batch_launch_log", "qv_plan_circuit"]:
         getattr(lib, f).restype = st
@@ -237,6 +238,17 @@ class Batch:
             _check(lib.qv_batch_expectations(self.h, _ptr(e), _ptr(tv), 0))
             return e, (tv[: self.n_tv] if tv is not None else None)
         _check(lib.qv_batch_expectations(self.h, _ptr(energies), _ptr(term_values), 1))
+        return energies, term_values
+
+    def expectations_static(self, energies=None, term_values=None, want_terms: bool = True):
+        """qv_batch_expectations_static (no device allocation; see the header); as expectations()."""
+        lib = load()
+        if energies is None:
+            e = np.zeros(self.B)
+            tv = np.zeros(max(1, self.n_tv)) if want_terms else None
+            _check(lib.qv_batch_expectations_static(self.h, _ptr(e), _ptr(tv), 0))
+            return e, (tv[: self.n_tv] if tv is not None else None)
+        _check(lib.qv_batch_expectations_static(self.h, _ptr(energies), _ptr(term_values), 1))
         return energies, term_values
 
     def gradient(self, method: int = QV_ADJOINT, upstream=None, grad=None, energies=None):
