@@ -279,6 +279,8 @@ struct ShiftCombineArgs {
 int launch_level(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_stride_level(const LevelArgs &a, int precision, int adjoint, void *stream);
 int launch_rlevel(const LevelArgs &a, int precision, int adjoint, void *stream);
+// The same level through a generated kernel of its pass (fn: a hipFunction_t; its LDS is static).
+int launch_rlevel_gen(const LevelArgs &a, int adjoint, void *fn, void *stream);
 int launch_persistent(const PersistArgs &a, int precision, int adjoint, void *stream);
 int persistent_blocks(int precision, int adjoint, int lds_t, int tab_bits, int max_train, int *blocks);
 // 1 when one persistent launch can hold the largest tile of the given passes in LDS.
