@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak (256 CUs at 2.4 GHz)
-TILE_KERNELS = ("rtile", "rtile_adj", "rtile_persist", "rtile_adj_persist", "tile", "tile_adj")
+TILE_KERNELS = ("rtile", "rtile_adj", "rtile_persist", "rtile_adj_persist", "tile", "tile_adj", "rtile_gen",
+                "rtile_adj_gen")
 SEED_PROFILE = 240603466 + 11
 
 
@@ -309,8 +310,11 @@ def main():
     ap.add_argument("--engine", default="tiled", choices=["tiled", "lds", "stride"])
     ap.add_argument("--contig", type=int, default=0)
     ap.add_argument("--launch", default="levels", choices=["levels", "persistent"])
-    ap.add_argument("--fusion", default="8",
-                    help='fused 4-qubit MFMA blocks in forward passes: "off", "on" or a minimum run length')
+    ap.add_argument("--fusion", default="auto",
+                    help='fused 4-qubit MFMA blocks in forward passes: "off", "on", "auto" (the autotuner picks '
+                         'the minimum run) or a minimum run length')
+    ap.add_argument("--specialize", default="auto", choices=["off", "adjoint", "on", "auto"],
+                    help="register-tiled levels run kernels generated for their pass (adjoint sweeps, or both)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     ap.add_argument("--levels", action="store_true", help="print per-launch times of one step")
@@ -347,7 +351,7 @@ def main():
     wl = W.config3(args.layers)
     stream = torch.cuda.current_stream(dev)
     opts = {"graph": False, "launch_events": True, "engine": args.engine, "launch": args.launch,
-            "fusion": args.fusion}
+            "fusion": args.fusion, "specialize": args.specialize}
     if args.tile_qubits:
         opts["tile_qubits"] = args.tile_qubits
     if args.contig:
@@ -399,7 +403,9 @@ def main():
     kernel_sym = {"tile_adj": "k_tile<float,true>", "tile": "k_tile<float,false>",
                   "rtile_adj": "k_rtile_adj<float,4,512>", "rtile": "k_rtile_fwd<float,4,512>",
                   "rtile_adj_persist": "k_rtile_adj_persist<float,4,512>",
-                  "rtile_persist": "k_rtile_fwd_persist<float,4,512>"}.get(dom, dom)
+                  "rtile_persist": "k_rtile_fwd_persist<float,4,512>",
+                  "rtile_adj_gen": "qv_gen_pass (generated adjoint tile pass, complex64)",
+                  "rtile_gen": "qv_gen_pass (generated forward tile pass, complex64)"}.get(dom, dom)
     workload_tag = f"qcl20_L{args.layers}"
     traffic = pmc_traffic(dom, workload_tag)
     if dom in TILE_KERNELS:
@@ -417,8 +423,7 @@ def main():
                     "algorithmic_bytes_per_launch": int(d["avg_bytes"])}
     # fused 4-qubit blocks of the forward passes run on MFMA (a 32 x 32 real product per 16 amplitudes,
     # 128 flops per amplitude per block); their flops are reported apart from the gates' algorithmic flops
-    fuse_min = {"off": 0, "on": 6}.get(args.fusion, None)
-    fuse_min = int(args.fusion) if fuse_min is None else fuse_min
+    fuse_min = tuned["fuse_min_run"]   # the run length the batch uses (chosen by the autotuner under "auto")
     n_fused = 0
     if fuse_min and args.engine == "tiled":
         n_fused = sum(p["n_fused"] for p in qvpu.plan_circuit(20, wl.circuit(0), tuned["tile_qubits"], qvpu.QV_C64,
@@ -426,14 +431,15 @@ def main():
     fused = {"blocks_per_circuit": n_fused, "mfma_flops_per_forward": n_fused * 128.0 * (1 << 20) * wl.B}
     # forward-only circuit evals/s (the 64 circuits of one forward pass)
     fwd_ms = sum(r["ms"] for r in recs if r["kernel"] in ("matrices", "fuse", "init", "tile", "rtile",
-                                                          "rtile_persist", "stride", "expect",
+                                                          "rtile_persist", "rtile_gen", "stride", "expect",
                                                           "finalize")) / args.steps
     circuit_evals_per_s = wl.B / (fwd_ms / 1e3)
 
     extra = {}
     if not args.no_ps:
         # parameter-shift gradient through the same batched tiled engine, measured in full
-        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False, "fusion": args.fusion}))
+        ctx_ps = qvpu.Context(0, stream.cuda_stream, json.dumps({"graph": False, "fusion": args.fusion,
+                                                                 "specialize": args.specialize}))
         b_ps = qvpu.Batch(ctx_ps, wl, qvpu.QV_C64)
         with torch.no_grad():
             f = expectation(theta.detach(), batch)
@@ -495,8 +501,9 @@ def main():
                    "qubits": 20, "layers": args.layers, "samples": 64, "params": wl.n_grad(),
                    "precision": "c64", "engine": args.engine, "tile_qubits": tuned["tile_qubits"],
                    "contig_qubits": tuned["contig_qubits"], "passes": tuned["passes_per_circuit_max"],
+                   "fuse_min_run": tuned["fuse_min_run"],
                    "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch,
-                   "fusion": args.fusion},
+                   "fusion": args.fusion, "specialize": args.specialize},
         "roofline": roofline,
         "fused_blocks": fused,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),

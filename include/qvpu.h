@@ -86,7 +86,7 @@ typedef struct {
     int32_t tile_qubits;       /* tile size of the batch's plans (after autotuning) */
     int32_t contig_qubits;     /* qubits 0..contig_qubits-1 are in every tile */
     int32_t passes_per_circuit_max; /* longest plan */
-    int32_t pad;
+    int32_t fuse_min_run;           /* fused blocks: shortest run of gates made into one block (0: none) */
 } qv_stats;
 
 /* Kernels named in launch records. */
@@ -111,7 +111,9 @@ typedef enum {
     QV_K_DIAG_SEED = 17,         /* adjoint seed lambda = u diag(w) psi of the divergence weights */
     QV_K_DIAG_EXPECT = 18,       /* <psi|diag(w)|psi> partial sums (parameter-shift variants) */
     QV_K_SEGMENT_SUM = 19,       /* per-circuit sums of partials in a fixed order */
-    QV_K_SAMPLE = 20             /* shots from the output distributions and their bit-string counts */
+    QV_K_SAMPLE = 20,            /* shots from the output distributions and their bit-string counts */
+    QV_K_RTILE_GEN = 21,         /* register-tiled pass, forward, kernel generated for the pass */
+    QV_K_RTILE_ADJ_GEN = 22      /* register-tiled pass, adjoint, kernel generated for the pass */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the
@@ -146,17 +148,32 @@ typedef struct qv_batch_s *qv_batch;
  *   "wait_ms"        : 0..600000, longest dependency wait of a persistent launch (default 4000);
  *   "wait_extra"     : int >= 0 (default 0), added to every dependency count of a persistent launch so that
  *                      those waits cannot be met: for testing the time-out path only;
- *   "fusion"         : "off" (default), "on" (runs of >= 6 gates) or a minimum run length: within a
- *                      register segment, consecutive gates acting only on its 4 register qubits are
- *                      multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);
+ *   "fusion"         : "off" (default), "on" (runs of >= 6 gates), a minimum run length, or "auto"
+ *                      (the autotuner times runs of >= 4, 6, 8 and no fused blocks; 8 until it has run):
+ *                      within a register segment, consecutive gates acting only on its 4 register qubits
+ *                      are multiplied into one 16x16 block (complex64: applied on MFMA in forward passes);
  *   "fold_cnots"     : "on" (default) or "off": runs of CNOTs at either end of a register segment
  *                      permute the tile's amplitudes, so they are folded into the segment's LDS load and
  *                      store addresses instead of running as ops (same results, no arithmetic);
+ *   "specialize"     : "off" (default), "adjoint", "on" or "auto": every register-tiled level whose
+ *                      circuits all run one plan pass runs a kernel generated for that pass (its ops as
+ *                      straight-line code, compiled with hipRTC on the first call that needs it; code
+ *                      objects are kept in the directory named by QV_GEN_CACHE, default
+ *                      $HOME/.cache/qvpu_gen), in reverse (adjoint) sweeps only, in both directions, or
+ *                      ("auto") in the reverse levels where it measured faster: the first adjoint call
+ *                      then times one reverse sweep with each kind of kernel. Same results as the general
+ *                      kernels, up to floating-point contraction; QV_E_DEVICE if the compilation fails;
+ *   "adjoint_inner"  : "f32" (default) or "f64" (needs "specialize" "adjoint", "on" or "auto"): in complex64
+ *                      adjoint sweeps a thread's Im <lambda| G |psi> products are summed in FP32 before the
+ *                      FP64 wave, tile and circuit sums ("f32"), or every product of two FP32 amplitude
+ *                      components is formed exactly in FP64 and summed in FP64 from there ("f64");
  *   "autotune"       : "off", "cached" (default: reuse a choice stored by an earlier search) or
  *                      "search" (on the first forward call, time one forward pass for each candidate tile
- *                      size and contiguous-run length and keep the fastest; stored in the text file named
- *                      by QV_TUNE_CACHE, default $HOME/.cache/qvpu_tune.txt). "tile_qubits" or
- *                      "contig_qubits" given explicitly disable it;
+ *                      size, contiguous-run length and, under "fusion": "auto", fused-block minimum run,
+ *                      and keep the fastest; stored as tile qubits, contiguous qubits, block width (4) and
+ *                      minimum run in the text file named by QV_TUNE_CACHE, default
+ *                      $HOME/.cache/qvpu_tune.txt). "tile_qubits" or "contig_qubits" given explicitly
+ *                      take those out of the search;
  *   "graph"          : true (default) to capture each call's launches in a hipGraph and replay it;
  *   "contig_qubits"  : 1..6: qubits 0..k-1 are in every tile, so tiles move in runs of 2^k amplitudes
  *                      (default 4 for complex64, 3 for complex128: 128-byte runs);

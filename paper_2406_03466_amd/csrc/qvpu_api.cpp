@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "jit.h"
 #include "planner.h"
 #include "qvpu.h"
 
@@ -107,6 +108,12 @@ static bool parse_options(const char *js, std::map<std::string, std::string> &ou
 // ---------------------------------------------------------------------------------------------------------
 // Context and batch objects
 // ---------------------------------------------------------------------------------------------------------
+constexpr int kSpecializeTimed = 4;                // "specialize" bit: choose per level by timing
+constexpr int kTimingSweeps = 4;                   // reverse sweeps timed, alternating general / generated
+constexpr int kFuseAuto = -1;                      // "fusion": "auto": the autotuner picks the minimum run
+constexpr int kFuseCandidates[] = {0, 4, 6, 8};    // minimum run lengths it times (0: no fused blocks)
+constexpr int kFuseDefault = 8;                    // its choice before (or without) a search
+
 // Makes `device` current and clears the runtime's last-error slot, so that the launch checks of this call
 // (which read that slot) report only this call's launches, not an earlier failure another call ignored.
 static hipError_t enter_device(int device)
@@ -133,6 +140,10 @@ struct qv_ctx_s {
     int wait_extra = 0;         // persistent launches: added to every dependency count (tests of the time-out)
     int fuse_min = 0;           // >0: fuse runs of at least this many register-local gates into MFMA blocks
     int fold_cnots = 1;         // 1: CNOT runs at register-segment boundaries fold into the LDS addressing
+    int specialize = 0;         // register-tiled levels of one pass run a kernel generated for that pass:
+                                // bit 0 in forward sweeps, bit 1 in reverse (adjoint) sweeps, and with
+                                // kSpecializeTimed only where timing shows it faster than the general one
+    int inner_f64 = 0;          // 1: generated complex64 adjoint passes form their inner products in FP64
     hipStream_t stream() const { return user_stream; }  // NULL is the device's default stream
 };
 
@@ -186,6 +197,7 @@ struct Level {
     double flops;     // algorithmic floating-point operations of the launch (op_flops per amplitude)
     int32_t max_train;
     int32_t tab_bits; // largest (tile qubits - contiguous low qubits) of the level's passes
+    void *gen = nullptr;  // register-tiled level of a single pass: the kernel generated for it, if any
 };
 
 // Algorithmic flops per amplitude of a gate, by what the gate's matrix needs, averaged over the two
@@ -295,6 +307,8 @@ struct ExecSet {
     std::vector<int64_t> gref_begin;
     std::vector<PartialRef> grefs;
     int64_t algo_bytes_fwd = 0, algo_bytes_rev = 0, passes_fwd = 0, passes_rev = 0;
+    bool gen_ready[2] = {false, false};  // generated kernels looked up for the forward / reverse levels
+    bool gen_timed = false;              // reverse levels: generated or general kernel chosen by timing
     int64_t init_bytes = 0, exp_bytes = 0, lam_bytes = 0;
 
     // device copies
@@ -318,6 +332,9 @@ struct ExecSet {
 // Device form of a batch's plans (shared by all its circuits and parameter-shift variants).
 struct DevPlans {
     DBuf passes, ops, rsegs, fused_ops;
+    std::vector<DevPass> h_passes;      // host copies (for generating specialised kernels)
+    std::vector<DevOp> h_ops;
+    std::vector<DevSeg> h_rsegs;
     std::vector<int> pass_base;
     std::vector<int64_t> op_count;      // ops per plan (fused-block markers included)
     std::vector<int64_t> fused_base;    // per plan: first entry in fused_ops
@@ -347,6 +364,7 @@ struct qv_batch_s {
     int contig = 0;
     std::unique_ptr<DevPlans> dp;
     int tuned = 0;                     // 1 once the autotuner (or its cache) has chosen the configuration
+    int fuse_min = 0;                  // minimum run length of fused blocks in this batch's plans (0: none)
 
     ExecSet main;
     // parameter-shift chunks
@@ -459,6 +477,8 @@ static int64_t tiles_of(const DevCirc &c, const Plan &pl, int p)
 static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std::vector<int> &pass_base, int wave,
                          int amp_bytes)
 {
+    es.gen_ready[0] = es.gen_ready[1] = false;
+    es.gen_timed = false;
     es.segs.clear(); es.fwd.clear(); es.rev.clear();
     es.partial_count = 0;
     es.algo_bytes_fwd = es.algo_bytes_rev = es.passes_fwd = es.passes_rev = 0;
@@ -776,6 +796,7 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
 static int launch_kind(const Level &lv, const LevelArgs &a, int prec, int adjoint, hipStream_t s)
 {
     if (lv.kind == LK_STRIDE) return launch_stride_level(a, prec, adjoint, s);
+    if (lv.kind == LK_RTILE && lv.gen) return launch_rlevel_gen(a, adjoint, lv.gen, s);
     if (lv.kind == LK_RTILE) return launch_rlevel(a, prec, adjoint, s);
     return launch_level(a, prec, adjoint, s);
 }
@@ -783,8 +804,49 @@ static int launch_kind(const Level &lv, const LevelArgs &a, int prec, int adjoin
 static int log_id(const Level &lv, int adjoint)
 {
     if (lv.kind == LK_STRIDE) return adjoint ? QV_K_STRIDE_ADJ : QV_K_STRIDE;
+    if (lv.kind == LK_RTILE && lv.gen) return adjoint ? QV_K_RTILE_ADJ_GEN : QV_K_RTILE_GEN;
     if (lv.kind == LK_RTILE) return adjoint ? QV_K_RTILE_ADJ : QV_K_RTILE;
     return adjoint ? QV_K_TILE_ADJ : QV_K_TILE;
+}
+
+// Kernels generated for the register-tiled levels of one direction of an execution set: a level whose
+// segments all run one plan pass gets a kernel with that pass's ops as straight-line code (compiled once
+// per distinct pass, cached). Runs before any graph capture; the autotuner's timing runs leave it out.
+static qv_status ensure_generated(qv_batch_s *bt, ExecSet &es, int dir)
+{
+    if (!(bt->ctx->specialize >> dir & 1) || es.gen_ready[dir]) return QV_OK;
+    std::vector<Level> &lvs = dir ? es.rev : es.fwd;
+    const DevPlans &dp = *bt->dp;
+    std::vector<std::string> srcs;
+    std::vector<size_t> level_of;
+    for (size_t L = 0; L < lvs.size(); L++) {
+        Level &lv = lvs[L];
+        lv.gen = nullptr;
+        if (lv.kind != LK_RTILE || lv.n_segs <= 0) continue;
+        const int pass = es.segs[(size_t)lv.seg_off].pass;
+        bool one = true;
+        for (int i = 1; i < lv.n_segs && one; i++) one = es.segs[(size_t)lv.seg_off + i].pass == pass;
+        if (!one) continue;
+        GenPassDesc d;
+        d.pass = dp.h_passes[(size_t)pass];
+        d.segs.assign(dp.h_rsegs.begin() + d.pass.seg_begin, dp.h_rsegs.begin() + d.pass.seg_begin + d.pass.n_seg);
+        d.ops.assign(dp.h_ops.begin() + d.pass.op_begin, dp.h_ops.begin() + d.pass.op_begin + d.pass.n_ops);
+        d.precision = bt->prec;
+        d.adjoint = dir;
+        d.lds_t = lv.lds_t;
+        d.tab_bits = lv.tab_bits;
+        d.max_train = lv.max_train;
+        d.inner_f64 = bt->ctx->inner_f64;
+        srcs.push_back(gen_pass_source(d));
+        level_of.push_back(L);
+    }
+    std::vector<void *> fns;
+    std::string err;
+    const int e = gen_kernels(srcs, fns, err);
+    if (e) return fail(QV_E_DEVICE, "%s", err.empty() ? hipGetErrorString((hipError_t)e) : err.c_str());
+    for (size_t i = 0; i < level_of.size(); i++) lvs[level_of[i]].gen = fns[i];
+    es.gen_ready[dir] = true;
+    return QV_OK;
 }
 
 static int enqueue_matrices(const qv_batch_s &bt, hipStream_t s, LaunchLog *log)
@@ -950,6 +1012,51 @@ static int enqueue_reverse(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     return logged(log, s, QV_K_GRAD_REDUCE, -1, 0, [&] { return launch_grad_reduce(ga, s); });
 }
 
+// "specialize": "auto": reverse sweeps alternately with the general kernels and with the generated ones
+// (two of each, every one after its own forward pass, eager, with per-launch events), then every reverse
+// level keeps the kernel with the lower of its two times. Once per execution set; it leaves no valid final
+// states behind.
+static qv_status time_generated_reverse(qv_batch_s *bt, ExecSet &es)
+{
+    if (!(bt->ctx->specialize & kSpecializeTimed) || es.gen_timed || bt->ctx->persistent) return QV_OK;
+    es.gen_timed = true;
+    std::vector<void *> gens;
+    bool any = false;
+    for (const Level &lv : es.rev) {
+        gens.push_back(lv.gen);
+        any |= lv.gen != nullptr;
+    }
+    if (!any) return QV_OK;
+    const DevPlans &dp = *bt->dp;
+    hipStream_t s = bt->ctx->stream();
+    std::vector<double> ms[2];
+    ms[0].assign(es.rev.size(), 1e300);
+    ms[1].assign(es.rev.size(), 1e300);
+    for (int run = 0; run < kTimingSweeps; run++) {
+        const int variant = run & 1;
+        for (size_t L = 0; L < es.rev.size(); L++) es.rev[L].gen = variant ? gens[L] : nullptr;
+        LaunchLog log;
+        int e = enqueue_matrices(*bt, s, nullptr);
+        if (!e)
+            e = enqueue_forward(*bt, es, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                                bt->d_norms.as<double>(), s, nullptr);
+        if (!e) e = enqueue_adjoint(*bt, es, dp, s, &log);
+        if (e) return fail(QV_E_DEVICE, "timing launch failed: %s", hipGetErrorString((hipError_t)e));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < log.recs.size(); i++) {
+            const qv_launch_rec &r = log.recs[i];
+            if (r.level < 0 || (size_t)r.level >= es.rev.size()) continue;
+            if (r.kernel != QV_K_RTILE_ADJ && r.kernel != QV_K_RTILE_ADJ_GEN) continue;
+            float f = 0.f;
+            HIPCHK(hipEventElapsedTime(&f, log.ev[i].first, log.ev[i].second));
+            ms[variant][(size_t)r.level] = std::min(ms[variant][(size_t)r.level], (double)f);
+        }
+    }
+    for (size_t L = 0; L < es.rev.size(); L++) es.rev[L].gen = (gens[L] && ms[1][L] < ms[0][L]) ? gens[L] : nullptr;
+    bt->fwd_valid = false;
+    return QV_OK;
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // C interface
 // ---------------------------------------------------------------------------------------------------------
@@ -1013,11 +1120,23 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
         } else if (k == "fusion") {
             if (v == "off" || v == "0") c->fuse_min = 0;
             else if (v == "on") c->fuse_min = 6;
+            else if (v == "auto") c->fuse_min = kFuseAuto;
             else {
                 const int fm = atoi(v.c_str());
-                if (fm < 1 || fm > 64) return fail(QV_E_INVALID, "fusion must be \"off\", \"on\" or a minimum run length 1..64");
+                if (fm < 1 || fm > 64)
+                    return fail(QV_E_INVALID, "fusion must be \"off\", \"on\", \"auto\" or a minimum run length 1..64");
                 c->fuse_min = fm;
             }
+        } else if (k == "specialize") {
+            if (v == "on" || v == "1" || v == "true") c->specialize = 3;
+            else if (v == "adjoint") c->specialize = 2;
+            else if (v == "auto") c->specialize = 2 | kSpecializeTimed;
+            else if (v == "off" || v == "0" || v == "false") c->specialize = 0;
+            else return fail(QV_E_INVALID, "specialize must be \"on\", \"adjoint\", \"auto\" or \"off\"");
+        } else if (k == "adjoint_inner") {
+            if (v == "f64") c->inner_f64 = 1;
+            else if (v == "f32") c->inner_f64 = 0;
+            else return fail(QV_E_INVALID, "adjoint_inner must be \"f32\" or \"f64\"");
         } else if (k == "fold_cnots") {
             if (v == "on" || v == "1" || v == "true") c->fold_cnots = 1;
             else if (v == "off" || v == "0" || v == "false") c->fold_cnots = 0;
@@ -1028,6 +1147,9 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             return fail(QV_E_INVALID, "unknown option \"%s\"", k.c_str());
         }
     }
+    if (c->inner_f64 && !(c->specialize & 2))
+        return fail(QV_E_INVALID, "\"adjoint_inner\": \"f64\" applies to generated adjoint passes: give \"specialize\": "
+                                  "\"on\" or \"adjoint\"");
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(QV_E_INVALID, "device %d out of range (%d devices)", device, ndev);
@@ -1150,7 +1272,7 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
         }
         const int lowc = bt->contig;
         const int rb = ctx->engine == 0 ? (prec == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
-        const int fm = (ctx->engine == 0) ? ctx->fuse_min : 0;
+        const int fm = (ctx->engine == 0) ? bt->fuse_min : 0;
         bt->plans.push_back(ctx->engine == 2 ? plan_stride(pin)
                                               : plan_tiled(pin, bt->tile_qubits, lowc, rb, fm, ctx->fold_cnots));
     }
@@ -1178,6 +1300,9 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
     HIPRET(dp->passes.upload(passes));
     HIPRET(dp->ops.upload(ops));
     HIPRET(dp->rsegs.upload(rsegs));
+    dp->h_passes = passes;
+    dp->h_ops = ops;
+    dp->h_rsegs = rsegs;
 
     // main set
     ExecSet &es = bt->main;
@@ -1287,6 +1412,7 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     if (need > 0.92 * (double)freeb)
         return fail(QV_E_OOM, "states need %.2f GiB, device has %.2f GiB free", need / 1073741824.0, freeb / 1073741824.0);
 
+    bt->fuse_min = ctx->fuse_min == kFuseAuto ? (prec == QV_C64 ? kFuseDefault : 0) : ctx->fuse_min;
     HIPCHK(configure(bt.get(), ctx->tile_qubits, ctx->contig));
 
     HIPCHK(bt->d_gates.upload(bt->gates));
@@ -1379,31 +1505,41 @@ static std::string tune_key(const qv_batch_s *bt)
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
     char buf[256];
-    snprintf(buf, sizeof buf, "%s/%s/%s/B%d/n%d/s%d/g%lld", arch.c_str(), bt->prec == QV_C64 ? "c64" : "c128",
-             bt->ctx->engine == 0 ? "tiled" : "lds", bt->B, nmax, (int)bt->plans.size(), (long long)gmax);
+    char fz[16];
+    if (bt->ctx->fuse_min == kFuseAuto) snprintf(fz, sizeof fz, "auto");
+    else snprintf(fz, sizeof fz, "%d", bt->ctx->fuse_min);
+    snprintf(buf, sizeof buf, "%s/%s/%s/B%d/n%d/s%d/g%lld/f%s", arch.c_str(), bt->prec == QV_C64 ? "c64" : "c128",
+             bt->ctx->engine == 0 ? "tiled" : "lds", bt->B, nmax, (int)bt->plans.size(), (long long)gmax, fz);
     return buf;
 }
 
-static bool tune_lookup(const std::string &key, int &T, int &contig)
+// Cache lines: key, tile qubits, contiguous qubits, fused-block width (register qubits, 4), minimum run
+// length of a fused block (0: none), forward time in ms.
+static bool tune_lookup(const std::string &key, int &T, int &contig, int &fm)
 {
     FILE *f = fopen(tune_path().c_str(), "r");
     if (!f) return false;
-    char k[256];
-    int t = 0, c = 0;
+    char line[512], k[256];
+    int t = 0, c = 0, w = 0, m = 0;
     double ms = 0;
     bool found = false;
-    while (fscanf(f, "%255s %d %d %lf", k, &t, &c, &ms) == 4)
-        if (key == k) { T = t; contig = c; found = true; }
+    while (fgets(line, sizeof line, f))
+        if (sscanf(line, "%255s %d %d %d %d %lf", k, &t, &c, &w, &m, &ms) == 6 && key == k) {
+            T = t;
+            contig = c;
+            fm = m;
+            found = true;
+        }
     fclose(f);
     return found;
 }
 
-static void tune_store(const std::string &key, int T, int contig, double ms)
+static void tune_store(const std::string &key, int T, int contig, int fm, double ms)
 {
     const std::string path = tune_path();
     FILE *f = fopen(path.c_str(), "a");
     if (!f) return;  // the cache is an optimisation only
-    fprintf(f, "%s %d %d %.6f\n", key.c_str(), T, contig, ms);
+    fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), T, contig, kRegBitsC64, fm, ms);
     fclose(f);
 }
 
@@ -1426,50 +1562,73 @@ static qv_status time_forward(qv_batch bt, double &ms)
     return QV_OK;
 }
 
+// The autotuner's candidates for a batch: tile sizes and contiguous-run lengths when some circuit needs
+// more than one pass and none is given explicitly, fused-block minimum runs under "fusion": "auto"
+// (complex64, register tiles). One candidate each: nothing to choose.
+struct TuneSpace {
+    std::vector<int> T, C, FM;
+    bool trivial() const { return T.size() * C.size() * FM.size() <= 1; }
+};
+
+static TuneSpace tune_space(const qv_batch_s *bt)
+{
+    const qv_ctx ctx = bt->ctx;
+    TuneSpace sp;
+    int nmax = 0;
+    for (int b = 0; b < bt->B; b++) nmax = std::max(nmax, bt->nq[b]);
+    const int tmax = bt->prec == QV_C64 ? 13 : 12, c_hi = bt->prec == QV_C64 ? 4 : 3;
+    const bool tiles = ctx->engine != 2 && !ctx->tile_qubits && !ctx->contig && nmax > tmax;
+    if (tiles) sp.T = {tmax, tmax - 1, tmax - 2}, sp.C = {c_hi, c_hi - 1};
+    else sp.T = {bt->tile_qubits}, sp.C = {bt->contig};
+    if (ctx->fuse_min == kFuseAuto && ctx->engine == 0 && bt->prec == QV_C64)
+        sp.FM.assign(std::begin(kFuseCandidates), std::end(kFuseCandidates));
+    else
+        sp.FM = {bt->fuse_min};
+    return sp;
+}
+
 // True when autotune() would leave the launch configuration as it is (no re-planning, no allocation).
 static bool tune_settled(qv_batch bt)
 {
-    if (bt->tuned) return true;
-    qv_ctx ctx = bt->ctx;
-    if (ctx->autotune == 0 || ctx->engine == 2 || ctx->tile_qubits || ctx->contig) return true;
-    int nmax = 0;
-    for (int b = 0; b < bt->B; b++) nmax = std::max(nmax, bt->nq[b]);
-    if (nmax <= (bt->prec == QV_C64 ? 13 : 12)) return true;
-    int T = 0, contig = 0;
-    if (tune_lookup(tune_key(bt), T, contig)) return T == bt->tile_qubits && contig == bt->contig;
-    return ctx->autotune != 2;
+    if (bt->tuned || bt->ctx->autotune == 0) return true;
+    if (tune_space(bt).trivial()) return true;
+    int T = 0, contig = 0, fm = 0;
+    if (tune_lookup(tune_key(bt), T, contig, fm))
+        return T == bt->tile_qubits && contig == bt->contig && fm == bt->fuse_min;
+    return bt->ctx->autotune != 2;
 }
 
 static qv_status autotune(qv_batch bt)
 {
     bt->tuned = 1;
-    qv_ctx ctx = bt->ctx;
-    if (ctx->autotune == 0 || ctx->engine == 2 || ctx->tile_qubits || ctx->contig) return QV_OK;
-    int nmax = 0;
-    for (int b = 0; b < bt->B; b++) nmax = std::max(nmax, bt->nq[b]);
-    const int tmax = bt->prec == QV_C64 ? 13 : 12;
-    if (nmax <= tmax) return QV_OK;  // every circuit is one whole-state pass: nothing to choose
+    if (bt->ctx->autotune == 0) return QV_OK;
+    const TuneSpace sp = tune_space(bt);
+    if (sp.trivial()) return QV_OK;
     const std::string key = tune_key(bt);
-    int T = 0, contig = 0;
-    if (tune_lookup(key, T, contig)) {
-        if (T != bt->tile_qubits || contig != bt->contig) HIPCHK(configure(bt, T, contig));
+    int T = 0, contig = 0, fm = 0;
+    if (tune_lookup(key, T, contig, fm)) {
+        if (T != bt->tile_qubits || contig != bt->contig || fm != bt->fuse_min) {
+            bt->fuse_min = fm;
+            HIPCHK(configure(bt, T, contig));
+        }
         return QV_OK;
     }
-    if (ctx->autotune != 2) return QV_OK;
-    const int c_hi = bt->prec == QV_C64 ? 4 : 3;
+    if (bt->ctx->autotune != 2) return QV_OK;
     double best = 1e300;
-    int bT = bt->tile_qubits, bc = bt->contig;
-    for (int t = tmax; t >= tmax - 2; t--) {
-        for (int c = c_hi; c >= c_hi - 1; c--) {
-            HIPCHK(configure(bt, t, c));
-            double ms = 0.0;
-            qv_status st = time_forward(bt, ms);
-            if (st != QV_OK) return st;
-            if (ms < best) { best = ms; bT = t; bc = c; }
-        }
-    }
+    int bT = bt->tile_qubits, bc = bt->contig, bf = bt->fuse_min;
+    for (int t : sp.T)
+        for (int c : sp.C)
+            for (int f : sp.FM) {
+                bt->fuse_min = f;
+                HIPCHK(configure(bt, t, c));
+                double ms = 0.0;
+                qv_status st = time_forward(bt, ms);
+                if (st != QV_OK) return st;
+                if (ms < best) { best = ms; bT = t; bc = c; bf = f; }
+            }
+    bt->fuse_min = bf;
     HIPCHK(configure(bt, bT, bc));
-    tune_store(key, bT, bc, best);
+    tune_store(key, bT, bc, bf, best);
     return QV_OK;
 }
 
@@ -1480,7 +1639,9 @@ static qv_status forward(qv_batch bt)
         if (st != QV_OK) return st;
     }
     DevPlans &dp = *bt->dp;
-    qv_status st = run_graph(bt, bt->g_fwd, [&](hipStream_t s, LaunchLog *log) {
+    qv_status st = ensure_generated(bt, bt->main, 0);
+    if (st != QV_OK) return st;
+    st = run_graph(bt, bt->g_fwd, [&](hipStream_t s, LaunchLog *log) {
         const int e = enqueue_matrices(*bt, s, log);
         if (e) return e;
         return enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
@@ -1713,6 +1874,8 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
     HIPCHK(hipEventRecord(bt->ev0, s));
     if (method == QV_ADJOINT) {
         if ((st = ensure_lambda(bt)) != QV_OK) return st;
+        if ((st = ensure_generated(bt, bt->main, 1)) != QV_OK) return st;
+        if ((st = time_generated_reverse(bt, bt->main)) != QV_OK) return st;
         // The reverse sweep starts from the final states of a forward pass with the current parameters;
         // run one first unless the last call left them in place.
         int64_t passes = 0, bytes = 0, launches = 0;
@@ -1732,6 +1895,9 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
         bt->last.algorithmic_bytes = bytes + bt->main.algo_bytes_rev;
     } else {
         if ((st = ensure_param_shift(bt)) != QV_OK) return st;
+        if ((st = ensure_generated(bt, bt->main, 0)) != QV_OK) return st;
+        for (auto &c : bt->ps_chunks)
+            if ((st = ensure_generated(bt, *c, 0)) != QV_OK) return st;
         st = run_graph(bt, bt->g_ps, [&](hipStream_t cs, LaunchLog *log) {
             int e = enqueue_matrices(*bt, cs, log);
             if (e) return e;
@@ -1993,6 +2159,8 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
         bt->last.algorithmic_bytes += js_bytes;
     } else if (method == QV_ADJOINT) {
         if ((st = ensure_lambda(bt)) != QV_OK) return st;
+        if ((st = ensure_generated(bt, bt->main, 1)) != QV_OK) return st;
+        if ((st = time_generated_reverse(bt, bt->main)) != QV_OK) return st;
         int64_t passes = 0, bytes = 0, launches = 0;
         if (!bt->fwd_valid) {
             if ((st = forward(bt)) != QV_OK) return st;
@@ -2000,6 +2168,7 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
             bytes += bt->last.algorithmic_bytes;
             launches += bt->last.launches;
         }
+        if ((st = ensure_generated(bt, bt->main, 0)) != QV_OK) return st;
         st = run_graph(bt, bt->g_js_adj, [&](hipStream_t cs, LaunchLog *log) {
             int e = divergence(cs, log);
             if (e) return e;
@@ -2032,6 +2201,9 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
             HIPCHK(c->d_diag_fb.upload(c->diag_fb));
             HIPCHK(c->d_diag_part.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, c->diag_fb.back())));
         }
+        if ((st = ensure_generated(bt, bt->main, 0)) != QV_OK) return st;
+        for (auto &c : bt->ps_chunks)
+            if ((st = ensure_generated(bt, *c, 0)) != QV_OK) return st;
         st = run_graph(bt, bt->g_js_ps, [&](hipStream_t cs, LaunchLog *log) {
             int e = enqueue_matrices(*bt, cs, log);
             if (e) return e;
@@ -2138,7 +2310,7 @@ qv_status qv_batch_stats(qv_batch bt, qv_stats *out)
     int pmax = 0;
     for (const Plan &pl : bt->plans) pmax = std::max(pmax, (int)pl.passes.size());
     out->passes_per_circuit_max = pmax;
-    out->pad = 0;
+    out->fuse_min_run = bt->ctx->engine == 0 ? bt->fuse_min : 0;
     return ok();
 }
 

@@ -34,7 +34,8 @@ class QvError(RuntimeError):
 class qv_stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int64), ("launches", ctypes.c_int64), ("algorithmic_bytes", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("norm_err_max", ctypes.c_double), ("tile_qubits", ctypes.c_int32),
-                ("contig_qubits", ctypes.c_int32), ("passes_per_circuit_max", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("contig_qubits", ctypes.c_int32), ("passes_per_circuit_max", ctypes.c_int32),
+                ("fuse_min_run", ctypes.c_int32)]
 
 
 class qv_launch_rec(ctypes.Structure):
@@ -44,7 +45,7 @@ class qv_launch_rec(ctypes.Structure):
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
                 "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices", "rtile_persist",
-                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum", "sample"]
+                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum", "sample", "rtile_gen", "rtile_adj_gen"]
 
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),

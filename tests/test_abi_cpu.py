@@ -137,6 +137,10 @@ def test_null_pointers_rejected():
 
 
 @pytest.mark.parametrize("opts,code", [('{"launch": "sometimes"}', "QV_E_INVALID"),
+                                       ('{"specialize": "sometimes"}', "QV_E_INVALID"),
+                                       ('{"adjoint_inner": "f16"}', "QV_E_INVALID"),
+                                       ('{"adjoint_inner": "f64"}', "QV_E_INVALID"),
+                                       ('{"adjoint_inner": "f64", "specialize": "off"}', "QV_E_INVALID"),
                                        ('{"wait_ms": -1}', "QV_E_INVALID"),
                                        ('{"wait_extra": -2}', "QV_E_INVALID"),
                                        ('{"fusion": 99}', "QV_E_INVALID"),

@@ -284,8 +284,9 @@ def _golden(name):
     return json.load(open(p))
 
 
-# the launch configuration bench.py times (autotuned tile, fused blocks of >= 8 gates, eager launches)
-BENCH_OPTS = {"fusion": "8", "autotune": "search", "graph": False, "launch_events": True}
+# the launch configuration bench.py times (tile size, contiguous run and fused-block minimum run chosen by
+# the autotuner, eager launches, adjoint levels on generated passes where they time faster)
+BENCH_OPTS = {"fusion": "auto", "autotune": "search", "graph": False, "launch_events": True, "specialize": "auto"}
 
 
 @pytest.mark.parametrize("layers,opts", [(2, {}), (4, {}), (8, {}), (2, BENCH_OPTS), (4, BENCH_OPTS),
@@ -381,6 +382,29 @@ def test_contig_qubits(qv, prec, contig):
     check(tv, tv_ref, prec, 1.0, "terms")
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
     check(g, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")
+
+
+def test_autotune_chooses_fused_block_run(qv, tmp_path, monkeypatch):
+    """Under "fusion": "auto" the search times fused-block minimum runs as well; the stored choice (tile,
+    contiguous run, block width 4, minimum run) is reused by a cached batch; results at parity."""
+    monkeypatch.setenv("QV_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    say("autotune fusion")
+    wl = W.qcl(n=16, layers=3, samples=6, seed_index=47)
+    e_ref, _, _, _ = oracle.expectations(wl)
+    b = qv.Batch(ctx_for(qv, autotune="search", fusion="auto"), wl, 0)
+    e, _ = b.expectations()
+    check(e, e_ref, 0, 1.0, "energies (search)")
+    st = b.stats()
+    assert st["fuse_min_run"] in (0, 4, 6, 8)
+    line = [x for x in (tmp_path / "tune.txt").read_text().split("\n") if x.strip()]
+    assert len(line) == 1 and line[0].split()[1:5] == [str(st["tile_qubits"]), str(st["contig_qubits"]), "4",
+                                                        str(st["fuse_min_run"])]
+    b2 = qv.Batch(ctx_for(qv, autotune="cached", fusion="auto"), wl, 0)
+    e2, _ = b2.expectations()
+    assert np.array_equal(e, e2)
+    assert b2.stats()["fuse_min_run"] == st["fuse_min_run"]
+    g_ref = oracle.grad_adjoint(wl)
+    check(b2.gradient(qv.QV_ADJOINT)[0], g_ref, 0, float(wl.B), "adjoint grad")
 
 
 def test_autotune_search_and_cache(qv, tmp_path, monkeypatch):
