@@ -18,6 +18,13 @@ constexpr int kBlock = 256;          // threads per workgroup for every kernel
 constexpr int kMaxGroupTerms = 8;    // Pauli terms evaluated together by one expectation item
 constexpr int kExpChunkLog2 = 14;    // amplitude pairs per expectation workgroup (16384; 4096 measured 15-17 % slower)
 constexpr int kStrideGroupsPerBlock = 1024;
+// Non-temporal hints for data that cannot stay in the L2 and last-level caches (4 MB per XCD, 256 MB)
+// until it is read again. A stride level makes one pass over every state of the batch, so its accesses
+// stream when the batch's states total kStreamBatchBytes; an expectation reads one state once per x-mask
+// group, so its reads stream when the largest state has kStreamStateBytes. Smaller data is re-read from
+// the caches and keeps the default policy.
+constexpr int64_t kStreamBatchBytes = (int64_t)256 << 20;
+constexpr int64_t kStreamStateBytes = (int64_t)64 << 20;
 constexpr int kRtileThreads = 512;  // register-tiled passes: workgroup size
 constexpr int kRegBitsC64 = 4;       // 16 complex64 amplitudes per thread (2^13-amplitude tiles)
 constexpr int kRegBitsC128 = 3;      // 8 complex128 amplitudes per thread (2^12-amplitude tiles)
@@ -174,7 +181,8 @@ struct LevelArgs {
     void *lam;
     double *partials;
     int32_t chunk;        // register-tiled levels: consecutive tiles per workgroup (set by the launcher)
-    int32_t pad;
+    int32_t stream;       // 1: the batch's states total at least kStreamBatchBytes (stride passes use
+                          // non-temporal accesses)
 };
 
 // One persistent launch runs every level of a direction: workgroups claim items (level blocks in level
@@ -223,6 +231,7 @@ struct ShiftMatArgs {
 struct ExpArgs {
     const DevGroup *groups;
     int32_t n_groups;
+    int32_t stream;       // 1: the largest state has at least kStreamStateBytes (non-temporal reads)
     int64_t n_blocks;
     const DevTerm *terms;
     const DevCirc *circs;

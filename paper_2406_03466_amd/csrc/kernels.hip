@@ -237,6 +237,170 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t n)
 // Stride pass: one gate straight from global memory. Each block handles kStrideGroupsPerBlock amplitude
 // pairs (one-qubit gates) or quads (two-qubit gates); op.p0/op.p1 hold the gate's qubits.
 // ------------------------------------------------------------------------------------------------------
+
+// 16 bytes of amplitudes: two complex64 or one complex128, moved as one vector load or store.
+template <typename R>
+struct Vec16 {
+    typedef float T __attribute__((ext_vector_type(4)));
+    static constexpr int E = 2;
+    __device__ static Cx<R> get(const T &v, int e) { return e ? Cx<R>{v.z, v.w} : Cx<R>{v.x, v.y}; }
+    __device__ static void put(T &v, int e, const Cx<R> &c)
+    {
+        if (e) { v.z = c.re; v.w = c.im; } else { v.x = c.re; v.y = c.im; }
+    }
+    __device__ static T shfl_xor(const T &v, int d)
+    {
+        return T{__shfl_xor(v.x, d, 64), __shfl_xor(v.y, d, 64), __shfl_xor(v.z, d, 64), __shfl_xor(v.w, d, 64)};
+    }
+};
+template <>
+struct Vec16<double> {
+    typedef double T __attribute__((ext_vector_type(2)));
+    static constexpr int E = 1;
+    __device__ static Cx<double> get(const T &v, int) { return Cx<double>{v.x, v.y}; }
+    __device__ static void put(T &v, int, const Cx<double> &c) { v.x = c.re; v.y = c.im; }
+    __device__ static T shfl_xor(const T &v, int d) { return T{__shfl_xor(v.x, d, 64), __shfl_xor(v.y, d, 64)}; }
+};
+
+// A one-qubit gate on qubit p as a stream over the state: every byte is read once and written once, in
+// 16-byte vectors, each thread issuing all loads of a round before its first store; with NT (states larger
+// than the caches) the accesses carry the non-temporal hint. Vector index j holds amplitudes E*j .. E*j+E-1, so qubit p is bit pb = p - log2(E)
+// of j. When pb < 6 the partner vector (j ^ 2^pb) is in the same wave: every lane reads the vector at its
+// own index, consecutive lanes consecutive vectors, and gets its partner from lane ^ 2^pb by a shuffle
+// (pb < 0, complex64 with p = 0: both amplitudes of a pair are in one vector). Otherwise a lane reads a
+// vector and its partner 2^pb vectors on (runs of at least 64 vectors per wave). The adjoint moves lambda
+// the same way and adds the pair's inner-product term where the generator's sum needs it (one lane per pair).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_vec(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void st_vec(const T &v, T *p)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename R, bool ADJ, bool NT>
+__device__ __forceinline__ double stride_one_qubit(Cx<R> *gpsi, Cx<R> *glam, int n, int p, int kind, bool train,
+                                                   const M2<R> &m, int64_t chunk)
+{
+    using V = Vec16<R>;
+    using VT = typename V::T;
+    constexpr int E = V::E, LE = E == 2 ? 1 : 0;
+    constexpr int UR = 4;                                    // vectors per round and thread
+    const int64_t nv = (int64_t)1 << (n - LE);
+    VT *vp = reinterpret_cast<VT *>(gpsi);
+    VT *vl = reinterpret_cast<VT *>(glam);
+    const int pb = p - LE;
+    double acc = 0.0;
+    if (pb < 6) {
+        constexpr int VB = 2 * kStrideGroupsPerBlock / E;   // the block's vectors: its groups' amplitudes
+        for (int r = 0; r < VB / kBlock; r += UR) {
+            // loads are not branched around (lanes past the end of a small state read its last vector and
+            // store nothing), so the compiler keeps them all in flight together
+            VT x[UR], l[UR];
+            int64_t j[UR];
+#pragma unroll
+            for (int k = 0; k < UR; k++) {
+                j[k] = chunk * VB + (int64_t)(r + k) * kBlock + threadIdx.x;
+                const int64_t jc = j[k] < nv ? j[k] : nv - 1;
+                x[k] = ld_vec<NT>(vp + jc);
+                if (ADJ) l[k] = ld_vec<NT>(vl + jc);
+            }
+#pragma unroll
+            for (int k = 0; k < UR; k++) {
+                VT o = x[k], ol = ADJ ? l[k] : x[k];
+                const bool live = j[k] < nv;   // lanes past the end hold a copy of the last vector
+                if (pb < 0) {
+                    Cx<R> a0 = V::get(x[k], 0), a1 = V::get(x[k], 1);
+                    if (ADJ) {
+                        Cx<R> u0 = V::get(l[k], 0), u1 = V::get(l[k], 1);
+                        if (train && live) acc += gen_inner<R>(kind, a0, a1, u0, u1);
+                        apply2(m, u0, u1);
+                        V::put(ol, 0, u0);
+                        V::put(ol, 1, u1);
+                    }
+                    apply2(m, a0, a1);
+                    V::put(o, 0, a0);
+                    V::put(o, 1, a1);
+                } else {
+                    const int d = 1 << pb;
+                    const VT w = V::shfl_xor(x[k], d);
+                    VT wl = w;
+                    if (ADJ) wl = V::shfl_xor(l[k], d);
+                    const bool hi = (j[k] >> pb) & 1;   // this lane holds the pairs' |1> side
+#pragma unroll
+                    for (int e = 0; e < E; e++) {
+                        Cx<R> a0 = V::get(hi ? w : x[k], e), a1 = V::get(hi ? x[k] : w, e);
+                        if (ADJ) {
+                            Cx<R> u0 = V::get(hi ? wl : l[k], e), u1 = V::get(hi ? l[k] : wl, e);
+                            if (train && live && !hi) acc += gen_inner<R>(kind, a0, a1, u0, u1);
+                            apply2(m, u0, u1);
+                            V::put(ol, e, hi ? u1 : u0);
+                        }
+                        apply2(m, a0, a1);
+                        V::put(o, e, hi ? a1 : a0);
+                    }
+                }
+                if (live) {
+                    st_vec<NT>(o, vp + j[k]);
+                    if (ADJ) st_vec<NT>(ol, vl + j[k]);
+                }
+            }
+        }
+        return acc;
+    }
+    constexpr int UB = kStrideGroupsPerBlock / E;            // the block's vector pairs
+    constexpr int UU = UR / 2;                               // pairs per round and thread
+    const int64_t nu = nv >> 1, half = (int64_t)1 << pb;
+    for (int r = 0; r < UB / kBlock; r += UU) {
+        VT x[UU], y[UU], lx[UU], ly[UU];
+        int64_t ia[UU];
+        bool in[UU];
+#pragma unroll
+        for (int k = 0; k < UU; k++) {
+            const int64_t u = chunk * UB + (int64_t)(r + k) * kBlock + threadIdx.x;
+            in[k] = u < nu;
+            ia[k] = (int64_t)insert0_64((uint64_t)(in[k] ? u : nu - 1), pb);
+            x[k] = ld_vec<NT>(vp + ia[k]);
+            y[k] = ld_vec<NT>(vp + ia[k] + half);
+            if (ADJ) {
+                lx[k] = ld_vec<NT>(vl + ia[k]);
+                ly[k] = ld_vec<NT>(vl + ia[k] + half);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < UU; k++) {
+            if (!in[k]) continue;
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                Cx<R> a0 = V::get(x[k], e), a1 = V::get(y[k], e);
+                if (ADJ) {
+                    Cx<R> u0 = V::get(lx[k], e), u1 = V::get(ly[k], e);
+                    if (train) acc += gen_inner<R>(kind, a0, a1, u0, u1);
+                    apply2(m, u0, u1);
+                    V::put(lx[k], e, u0);
+                    V::put(ly[k], e, u1);
+                }
+                apply2(m, a0, a1);
+                V::put(x[k], e, a0);
+                V::put(y[k], e, a1);
+            }
+            st_vec<NT>(x[k], vp + ia[k]);
+            st_vec<NT>(y[k], vp + ia[k] + half);
+            if (ADJ) {
+                st_vec<NT>(lx[k], vl + ia[k]);
+                st_vec<NT>(ly[k], vl + ia[k] + half);
+            }
+        }
+    }
+    return acc;
+}
+
 template <typename R, bool ADJ>
 __global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
 {
@@ -273,26 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_stride(LevelArgs a)
         }
         return;
     }
-    const uint64_t ngroups = 1ull << (n - 1);
-    const int p = op.p0;
-    const uint64_t bit = 1ull << p;
     M2<R> m = op_matrix<R>(a, C, sg.circ, op, P.op_begin);
     if (ADJ) m = dagger_r(m);
-    double acc = 0.0;
-    for (uint32_t e = threadIdx.x; e < kStrideGroupsPerBlock; e += kBlock) {
-        const uint64_t gi = g0 + e;
-        if (gi >= ngroups) break;
-        const uint64_t i0 = insert0_64(gi, p), i1 = i0 | bit;
-        Cx<R> x = gpsi[i0], y = gpsi[i1];
-        if (ADJ) {
-            Cx<R> u = glam[i0], v = glam[i1];
-            if (op.flags & OP_TRAIN) acc += gen_inner<R>(kind, x, y, u, v);
-            apply2(m, u, v);
-            glam[i0] = u; glam[i1] = v;
-        }
-        apply2(m, x, y);
-        gpsi[i0] = x; gpsi[i1] = y;
-    }
+    const bool train = (op.flags & OP_TRAIN) != 0;
+    const double acc = a.stream ? stride_one_qubit<R, ADJ, true>(gpsi, glam, n, op.p0, kind, train, m, chunk)
+                                : stride_one_qubit<R, ADJ, false>(gpsi, glam, n, op.p0, kind, train, m, chunk);
     if (ADJ && (op.flags & OP_TRAIN)) {
         const double s = block_sum(acc, red);
         if (threadIdx.x == 0) a.partials[sg.partial_base + chunk * P.n_train + op.train_slot] = s;
@@ -426,13 +575,24 @@ __global__ __launch_bounds__(kBlock) void k_init(Cx<R> *psi, const DevCirc *circ
 // item (two for pairs: the real and imaginary parts of conj(psi[b ^ x]) psi[b], one of whose weights is 0).
 // When x != 0, b = i with a zero inserted at bit h (the top bit of x), so popcount(b & z) = popcount(i & z'),
 // z' being z with bit h removed.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
+// One amplitude, with the non-temporal hint when NT (a large state is read once per group and cannot stay
+// cached between groups; a small one is re-read from the caches by its other groups).
+template <bool NT, typename R>
+__device__ __forceinline__ Cx<R> ld_amp(const Cx<R> *p)
 {
-    __shared__ double red[kBlock / 64];
-    const int64_t blk = (int64_t)blockIdx.x;
-    const DevGroup G = a.groups[find_block(a.groups, a.n_groups, blk)];
-    const int64_t chunk = blk - G.first_block;
+    typedef R V2 __attribute__((ext_vector_type(2)));
+    const V2 v = ld_vec<NT>(reinterpret_cast<const V2 *>(p));
+    return Cx<R>{v.x, v.y};
+}
+
+// The group's TERMS accumulators (1, 2, 4 or 8; those past the group's n_terms have weight zero, so no
+// term test sits in the loops). Loop steps whose 256 items all lie in the block's chunk run U at a time with
+// no bounds tests; the remaining steps run one at a time, an item past the end reading the chunk's last
+// item with weight zero. The block then writes one partial per term: wave sums, one barrier, and a fixed
+// order over the waves.
+template <typename R, bool NT, int TERMS>
+__device__ __forceinline__ void expect_group(const ExpArgs &a, const DevGroup &G, int64_t chunk, double *red)
+{
     const DevCirc C = a.circs[G.circ];
     const Cx<R> *st = reinterpret_cast<const Cx<R> *>(a.psi) + C.state_off;
     const int nt = G.n_terms;
@@ -442,81 +602,117 @@ __global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
     const uint64_t i0 = (uint64_t)chunk << G.chunk_log2;
     const uint64_t items = x ? (1ull << (C.n - 1)) : (1ull << C.n);
     const uint32_t lim = (uint32_t)(items - i0 < (uint64_t)per ? items - i0 : (uint64_t)per);
-    const uint32_t nk = (lim + kBlock - 1) / kBlock;
-    uint32_t zk[kMaxGroupTerms];   // the loop-step part of each term's z (item bits 8 and up, within the chunk)
-    double fr[kMaxGroupTerms], fi[kMaxGroupTerms];  // weights of Re w and Im w (the same for every thread)
-    double ts[kMaxGroupTerms], acc[kMaxGroupTerms];  // the thread's part of the sign; its sum
+    const uint32_t nk = (lim + kBlock - 1) / kBlock, nfull = lim / kBlock;
+    uint32_t zk[TERMS];   // the loop-step part of each term's z (item bits 8 and up, within the chunk)
+    double fr[TERMS], fi[TERMS];  // weights of Re w and Im w (the same for every thread)
+    double ts[TERMS], acc[TERMS];  // the thread's part of the sign; its sum
 #pragma unroll
-    for (int j = 0; j < kMaxGroupTerms; j++) {
+    for (int j = 0; j < TERMS; j++) {
         const uint64_t z = j < nt ? a.terms[G.term_begin + j].zmask : 0;
         const int q = j < nt ? a.terms[G.term_begin + j].ny : 0;
         const uint64_t zs = x ? ((z & ((1ull << h) - 1ull)) | ((z >> (h + 1)) << h)) : z;
         zk[j] = (uint32_t)(zs >> 8) & ((per - 1u) >> 8);
         // Re[i^q w] = wr, -wi, -wr, wi for q = 0..3; a pair counts twice
-        const double w2 = x ? 2.0 : 1.0;
+        const double w2 = j < nt ? (x ? 2.0 : 1.0) : 0.0;
         fr[j] = q == 0 ? w2 : q == 2 ? -w2 : 0.0;
         fi[j] = q == 1 ? -w2 : q == 3 ? w2 : 0.0;
         ts[j] = parity64((i0 | (uint64_t)threadIdx.x) & zs) ? -1.0 : 1.0;
         acc[j] = 0.0;
     }
-    // U loop steps per iteration: their loads are issued together; an item past the end (last step only)
-    // reads the last item and counts 0
-    constexpr uint32_t U = 4;
     if (x == 0) {
-        for (uint32_t k0 = 0; k0 < nk; k0 += U) {
+        constexpr uint32_t U = 8;
+        uint32_t k0 = 0;
+        for (; k0 + U <= nfull; k0 += U) {
             double w[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; u++) {
-                const uint32_t e = threadIdx.x + (k0 + u) * kBlock;
-                const Cx<R> v = st[i0 + (e < lim ? e : lim - 1)];
-                const double keep = e < lim ? 1.0 : 0.0;  // a product, not a branch: every load is issued
-                w[u] = keep * ((double)v.re * (double)v.re + (double)v.im * (double)v.im);
+                const Cx<R> v = ld_amp<NT>(st + i0 + threadIdx.x + (k0 + u) * kBlock);
+                w[u] = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
             }
 #pragma unroll
-            for (uint32_t u = 0; u < U; u++) {
-                const uint32_t k = k0 + u;
-                if (k < nk) {
+            for (uint32_t u = 0; u < U; u++)
 #pragma unroll
-                    for (int j = 0; j < kMaxGroupTerms; j++)
-                        if (j < nt) acc[j] = fma(__popc(k & zk[j]) & 1 ? -fr[j] : fr[j], w[u], acc[j]);
-                }
-            }
+                for (int j = 0; j < TERMS; j++)
+                    acc[j] = fma(__popc((k0 + u) & zk[j]) & 1 ? -fr[j] : fr[j], w[u], acc[j]);
+        }
+        for (; k0 < nk; k0++) {
+            const uint32_t e = threadIdx.x + k0 * kBlock;
+            const Cx<R> v = ld_amp<NT>(st + i0 + (e < lim ? e : lim - 1));
+            const double w = (e < lim ? 1.0 : 0.0) * ((double)v.re * (double)v.re + (double)v.im * (double)v.im);
+#pragma unroll
+            for (int j = 0; j < TERMS; j++) acc[j] = fma(__popc(k0 & zk[j]) & 1 ? -fr[j] : fr[j], w, acc[j]);
         }
     } else {
-        for (uint32_t k0 = 0; k0 < nk; k0 += U) {
+        // w = conj(psi[b ^ x]) psi[b] for the pair's lower index b (item i with a zero inserted at bit h)
+        constexpr uint32_t U = 4;
+        uint32_t k0 = 0;
+        for (; k0 + U <= nfull; k0 += U) {
             double wr[U], wi[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; u++) {
-                const uint32_t e = threadIdx.x + (k0 + u) * kBlock;
-                const uint64_t b = insert0_64(i0 + (e < lim ? e : lim - 1), h);
-                const Cx<R> a0 = st[b], a1 = st[b ^ x];
-                // w = conj(psi[b ^ x]) psi[b]
-                const double r = (double)a1.re * (double)a0.re + (double)a1.im * (double)a0.im;
-                const double m = (double)a1.re * (double)a0.im - (double)a1.im * (double)a0.re;
-                const double keep = e < lim ? 1.0 : 0.0;
-                wr[u] = keep * r;
-                wi[u] = keep * m;
+                const uint64_t b = insert0_64(i0 + threadIdx.x + (k0 + u) * kBlock, h);
+                const Cx<R> a0 = ld_amp<NT>(st + b), a1 = ld_amp<NT>(st + (b ^ x));
+                wr[u] = (double)a1.re * (double)a0.re + (double)a1.im * (double)a0.im;
+                wi[u] = (double)a1.re * (double)a0.im - (double)a1.im * (double)a0.re;
             }
 #pragma unroll
-            for (uint32_t u = 0; u < U; u++) {
-                const uint32_t k = k0 + u;
-                if (k < nk) {
+            for (uint32_t u = 0; u < U; u++)
 #pragma unroll
-                    for (int j = 0; j < kMaxGroupTerms; j++) {
-                        if (j < nt) {
-                            const bool neg = __popc(k & zk[j]) & 1;
-                            acc[j] = fma(neg ? -fr[j] : fr[j], wr[u], acc[j]);
-                            acc[j] = fma(neg ? -fi[j] : fi[j], wi[u], acc[j]);
-                        }
-                    }
+                for (int j = 0; j < TERMS; j++) {
+                    const bool neg = __popc((k0 + u) & zk[j]) & 1;
+                    acc[j] = fma(neg ? -fr[j] : fr[j], wr[u], acc[j]);
+                    acc[j] = fma(neg ? -fi[j] : fi[j], wi[u], acc[j]);
                 }
+        }
+        for (; k0 < nk; k0++) {
+            const uint32_t e = threadIdx.x + k0 * kBlock;
+            const uint64_t b = insert0_64(i0 + (e < lim ? e : lim - 1), h);
+            const Cx<R> a0 = ld_amp<NT>(st + b), a1 = ld_amp<NT>(st + (b ^ x));
+            const double keep = e < lim ? 1.0 : 0.0;
+            const double wr = keep * ((double)a1.re * (double)a0.re + (double)a1.im * (double)a0.im);
+            const double wi = keep * ((double)a1.re * (double)a0.im - (double)a1.im * (double)a0.re);
+#pragma unroll
+            for (int j = 0; j < TERMS; j++) {
+                const bool neg = __popc(k0 & zk[j]) & 1;
+                acc[j] = fma(neg ? -fr[j] : fr[j], wr, acc[j]);
+                acc[j] = fma(neg ? -fi[j] : fi[j], wi, acc[j]);
             }
         }
     }
-    for (int j = 0; j < nt; j++) {
-        const double s = block_sum(ts[j] * acc[j], red);
-        if (threadIdx.x == 0) a.partials[G.partial_base + chunk * nt + j] = s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < TERMS; j++) {
+        double v = ts[j] * acc[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wave * TERMS + j] = v;
     }
+    __syncthreads();
+    if ((int)threadIdx.x < nt) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; w++) s += red[w * TERMS + threadIdx.x];
+        a.partials[G.partial_base + chunk * nt + threadIdx.x] = s;
+    }
+}
+
+template <typename R, bool NT>
+__device__ __forceinline__ void expect_terms(const ExpArgs &a, const DevGroup &G, int64_t chunk, double *red)
+{
+    static_assert(kMaxGroupTerms == 8, "accumulator counts below cover groups of up to 8 terms");
+    if (G.n_terms <= 1) expect_group<R, NT, 1>(a, G, chunk, red);
+    else if (G.n_terms <= 2) expect_group<R, NT, 2>(a, G, chunk, red);
+    else if (G.n_terms <= 4) expect_group<R, NT, 4>(a, G, chunk, red);
+    else expect_group<R, NT, 8>(a, G, chunk, red);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_expect(ExpArgs a)
+{
+    __shared__ double red[(kBlock / 64) * kMaxGroupTerms];
+    const int64_t blk = (int64_t)blockIdx.x;
+    const DevGroup G = a.groups[find_block(a.groups, a.n_groups, blk)];
+    const int64_t chunk = blk - G.first_block;
+    if (a.stream) expect_terms<R, true>(a, G, chunk, red);
+    else expect_terms<R, false>(a, G, chunk, red);
 }
 
 // Second stage of the expectation reduction: one workgroup per output (a term value, or a circuit's norm)

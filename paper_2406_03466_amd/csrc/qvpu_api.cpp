@@ -346,6 +346,8 @@ struct qv_batch_s {
     int B = 0;
     qv_precision prec = QV_C64;
     int amp_bytes = 8;
+    int stream_levels = 0;  // states total >= kStreamBatchBytes (LevelArgs::stream)
+    int stream_expect = 0;  // largest state >= kStreamStateBytes (ExpArgs::stream)
     std::vector<int32_t> nq;
     std::vector<int64_t> goff;
     std::vector<qv_gate> gates;
@@ -790,6 +792,8 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
     a.rsegs = dp.rsegs.as<DevSeg>();
     a.max_train = lv.max_train;
     a.tab_bits = lv.tab_bits;
+    a.chunk = 0;
+    a.stream = bt.stream_levels;
     return a;
 }
 
@@ -947,6 +951,7 @@ static int enqueue_forward(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     ExpArgs ea;
     ea.groups = es.d_groups.as<DevGroup>();
     ea.n_groups = (int32_t)es.groups.size();
+    ea.stream = bt.stream_expect;
     ea.n_blocks = es.exp_blocks;
     ea.terms = es.d_terms.as<DevTerm>();
     ea.circs = es.d_circs.as<DevCirc>();
@@ -1385,6 +1390,15 @@ qv_status qv_batch_create(qv_ctx ctx, int32_t B, const int32_t *nq, const int64_
     bt->prec = prec;
     bt->amp_bytes = prec == QV_C64 ? 8 : 16;
     bt->nq.assign(nq, nq + B);
+    {
+        int64_t total = 0, largest = 0;
+        for (int b = 0; b < B; b++) {
+            total += (int64_t)bt->amp_bytes << nq[b];
+            largest = std::max(largest, (int64_t)bt->amp_bytes << nq[b]);
+        }
+        bt->stream_levels = total >= kStreamBatchBytes;
+        bt->stream_expect = largest >= kStreamStateBytes;
+    }
     bt->goff.assign(goff, goff + B + 1);
     bt->gates.assign(gates, gates + goff[B]);
     bt->nparams.assign(np, np + B);

@@ -319,14 +319,15 @@ def test_random1024_full_size(qv):
     check(tv, np.array(gold["term_values"]), 0, 1.0, "terms")
 
 
-@pytest.mark.parametrize("n", [26, 32])
-def test_large_state_closed_form(qv, n):
+@pytest.mark.parametrize("n,opts", [(26, {}), (32, {}), (26, {"engine": "stride"})])
+def test_large_state_closed_form(qv, n, opts):
     """One HEA layer on n qubits (32: a 32 GiB complex64 state) with the ZZ chain: the CNOT ladder is a
     prefix-XOR permutation, so E = sum_{i>=1} cos(theta_RY[i]) and dE/dtheta_RY[i] = -sin(theta_RY[i])
-    (0 for i = 0); checks 64-bit indexing at full size."""
-    say(f"large n={n}")
+    (0 for i = 0); checks 64-bit indexing at full size, and on the stride engine the non-temporal
+    passes taken for states larger than the caches."""
+    say(f"large n={n} opts={opts}")
     wl = W.large_hea(n, 1, seed_index=5)
-    b = qv.Batch(ctx_for(qv), wl, 0)
+    b = qv.Batch(ctx_for(qv, **opts), wl, 0)
     e, tv = b.expectations()
     ry = wl.theta[:n]
     check(tv, np.cos(ry[1:]), 0, 1.0, "ZZ terms")
@@ -336,6 +337,47 @@ def test_large_state_closed_form(qv, n):
     check(g, want, 0, n - 1.0, "grad")
     st = b.stats()
     assert st["norm_err_max"] < 1e-5
+    b.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_stride_engine_full_size(qv, prec):
+    """The stride engine on one 22-qubit circuit (RY, RX, RZ and H on every qubit, a CNOT ladder, CZs, a
+    second RY layer): every one-qubit access pattern of its global-memory passes (both amplitudes of a pair
+    in one 16-byte vector, the partner vector in another lane of the wave, the partner 2^p vectors on), at
+    full size; energy, term values and the adjoint gradient against the oracle."""
+    say(f"stride engine full size prec={prec}")
+    n = 22
+    rng = np.random.default_rng(2211)
+    gates, k = [], 0
+    for q in range(n):
+        gates.append(W.gate(W.RY, q, -1, k)); k += 1
+        gates.append(W.gate(W.RX, q, -1, k)); k += 1
+    gates += [W.gate(W.H, q, -1, -1) for q in range(0, n, 3)]
+    for q in range(n):
+        gates.append(W.gate(W.RZ, q, -1, k)); k += 1
+    gates += [W.gate(W.CNOT, q, q + 1, -1) for q in range(n - 1)]
+    gates += [W.gate(W.CZ, q, (q + 7) % n, -1) for q in range(0, n, 5)]
+    for q in range(n):
+        gates.append(W.gate(W.RY, q, -1, k)); k += 1
+    theta = rng.uniform(0, 2 * np.pi, k)
+    # terms with values of order one (random 22-qubit Pauli strings have values near zero)
+    strings = [{0: "Z"}, {0: "Z", 1: "Z"}, {0: "X"}, {5: "Z", 6: "Z"}, {20: "Z", 21: "Z"}, {21: "X"},
+               {10: "Y", 11: "Y"}, {0: "Z", 1: "X"}]
+    masks = [W.parse_pauli("".join(d.get(q, "I") for q in range(n))) for d in strings]
+    xm = np.array([m[0] for m in masks], np.uint64)
+    zm = np.array([m[1] for m in masks], np.uint64)
+    co = rng.normal(0.0, 1.0, len(strings))
+    wl = W.single(f"stride{n}", n, gates, theta, (xm, zm, co))
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    g_ref = oracle.grad_adjoint(wl)
+    b = qv.Batch(ctx_for(qv, engine="stride"), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    g, _ = b.gradient(qv.QV_ADJOINT)
+    check(g, g_ref, prec, s, "adjoint grad")
     b.close()
 
 
