@@ -121,7 +121,7 @@ def test_c2_full(qv, prec):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("tile,engine", [(6, "tiled"), (9, "tiled"), (None, "tiled"), (8, "lds"), (None, "lds"),
-                                         (None, "fused"), (8, "fused")])
+                                         (None, "fused"), (8, "fused"), (None, "stride")])
 def test_uneven_batch(qv, prec, tile, engine):
     """Circuits of 2..16 qubits and 0..80 gates in one batch: per-circuit energies, terms, states and
     adjoint gradients (own parameters per circuit) with upstream weights."""
@@ -144,6 +144,29 @@ def test_uneven_batch(qv, prec, tile, engine):
         psi = b.state(c)
         err = np.max(np.abs(psi - psi_ref))
         assert err < (1e-13 if prec == 1 else 1e-5), (c, err)
+    g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+    check(g, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")
+    g2, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
+    check(g2, g_ref, prec, s * np.sum(np.abs(up)), "param-shift grad")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("engine", ["tiled", "lds", "stride"])
+def test_one_to_three_qubit_circuits(qv, prec, engine):
+    """The degenerate sizes: circuits of 1, 2 and 3 qubits (a complex64 state of 1 qubit is one 16-byte
+    vector, so most lanes of a stride pass lie past its end), every one-qubit gate kind: energies, terms
+    and adjoint and parameter-shift gradients against the oracle."""
+    say(f"1-3 qubits prec={prec} engine={engine}")
+    wl = W.random_batch(18, 1, 3, 1, 24, 3, seed_index=43,
+                        kinds=[W.H, W.X, W.Y, W.Z, W.S, W.T, W.RX, W.RY, W.RZ])
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    up = np.linspace(1.0, -0.5, wl.B)
+    g_ref = oracle.grad_adjoint(wl, up)
+    b = qv.Batch(ctx_for(qv, engine=engine), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
     g, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
     check(g, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")
     g2, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
