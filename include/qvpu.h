@@ -145,6 +145,9 @@ typedef struct qv_batch_s *qv_batch;
  *                      every later item skip its work and the call return QV_E_DEVICE). Sweeps whose passes
  *                      are not all register-tiled, or whose tiles do not fit one persistent workgroup's
  *                      LDS, run one launch per level;
+ *   "persist_chunk"  : 0..64, consecutive queue items a persistent workgroup claims at once (default 0:
+ *                      4 forward, 8 reverse, fewer when the sweep has few items); where consecutive
+ *                      items are tiles of one circuit's pass, each prefetches the next;
  *   "wait_ms"        : 0..600000, longest dependency wait of a persistent launch (default 4000);
  *   "wait_extra"     : int >= 0 (default 0), added to every dependency count of a persistent launch so that
  *                      those waits cannot be met: for testing the time-out path only;

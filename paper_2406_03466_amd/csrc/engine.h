@@ -198,7 +198,7 @@ struct PersistArgs {
     LevelArgs base;              // segs/n_segs are taken per level; lds_t, tab_bits, max_train are maxima
     const PersistLevel *levels;
     int32_t n_levels;
-    int32_t pad;
+    int32_t chunk;               // consecutive items a workgroup claims at once (set by the launcher)
     int64_t n_items;
     unsigned long long *head;    // queue head, zero before the launch
     unsigned long long *done;    // finished tiles per circuit, zero before the launch

@@ -150,68 +150,118 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v)
 
 // Persistent form: workgroups stay resident and claim items from a queue. Items are the blocks of all
 // levels in level order, so every item an item waits for was claimed earlier by a running workgroup and
-// every wait ends. A finished tile is published with a device-scope release fence before its circuit's
-// counter is incremented; a waiting workgroup acquires after it has seen the count.
+// every wait ends. A workgroup claims `chunk` consecutive items at a time and runs them in order; where the
+// next item of its chunk is the next tile of the same (circuit, pass), the current tile's last register
+// segment loads it straight into LDS, as in the level kernels, and the next item needs no wait of its own
+// (it shares its predecessor's dependency). A finished tile is published once every wave's stores have
+// completed (a wait on the vector memory counter), a barrier, thread 0's device-scope release fence and the
+// increment of its circuit's counter; a waiting workgroup acquires after it has seen the count.
 //
-// The claim loop keeps every thread of a workgroup on the same path: the next item is claimed by thread 0
-// in the same region that publishes the finished one, fenced by barriers on both sides, and the loop test
-// reads the claimed item as a wave-uniform value. (With the claim at the top of the loop and the
-// publication at its bottom, each under its own `threadIdx.x == 0` test, the compiler joins the two regions
-// across the loop's back edge and turns the loop into two nested loops whose inner one lets wave 0's other
-// lanes return to the top barrier without lane 0, re-read the old item and run it again, forever.)
+// The loop keeps every thread of a workgroup on the same path: all work of thread 0 for one step
+// (publishing the finished item, claiming the next chunk when this one is used up, waiting for the next
+// item's dependency) is one region between two barriers, and the loop reads the next item, the chunk end and
+// the run flag back as wave-uniform values. (With the claim at the top of the loop and the publication at
+// its bottom, each under its own `threadIdx.x == 0` test, the compiler joins the two regions across the
+// loop's back edge and turns the loop into two nested loops whose inner one lets wave 0's other lanes
+// return to the top barrier without lane 0, re-read the old item and run it again, forever.)
 //
 // A wait is bounded by wait_ticks of the constant-rate wall clock. A wait that runs out sets *error; from
 // then on every workgroup skips the work of the items it claims (it still counts them finished, so no
 // other wait blocks on them) and the host reports the launch's results as invalid.
+struct PersistItem {
+    LevelArgs a;
+    int64_t blk, next_blk;
+    Seg sg;
+};
+
+// Level, block and segment of an item; next_blk is the item's successor tile in the same (circuit, pass)
+// when the item after it (below `end`) is that tile, else -1.
+__device__ __forceinline__ PersistItem persist_item(const PersistArgs &pa, int64_t item, int64_t end)
+{
+    int lo = 0, hi = pa.n_levels - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pa.levels[mid].first_item <= item) lo = mid; else hi = mid - 1;
+    }
+    const PersistLevel lv = pa.levels[lo];
+    PersistItem it;
+    it.a = pa.base;
+    it.a.segs = pa.base.segs + lv.seg_off;
+    it.a.n_segs = lv.n_segs;
+    it.blk = item - lv.first_item;
+    const int si = find_block(it.a.segs, it.a.n_segs, it.blk);
+    it.sg = it.a.segs[si];
+    const int64_t level_blocks = (lo + 1 < pa.n_levels ? pa.levels[lo + 1].first_item : pa.n_items) - lv.first_item;
+    const int64_t send = si + 1 < it.a.n_segs ? it.a.segs[si + 1].first_block : level_blocks;
+    it.next_blk = (item + 1 < end && it.blk + 1 < send) ? it.blk + 1 : -1;
+    return it;
+}
+
+// Thread 0: waits until the circuit of `sg` has finished sg.wait tiles; false when the wait ran out or an
+// earlier one did.
+__device__ __forceinline__ bool persist_wait(const PersistArgs &pa, const Seg &sg)
+{
+    bool run = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (run && sg.wait > 0) {
+        const int64_t need = sg.wait + pa.wait_extra;
+        const int64_t t0 = wall_clock64();
+        while ((int64_t)__hip_atomic_load(pa.done + sg.circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(2);
+            if (wall_clock64() - t0 > pa.wait_ticks) {
+                atomicOr(pa.error, 1);
+                run = false;
+                break;
+            }
+        }
+    }
+    __threadfence();
+    return run;
+}
+
 template <typename R, bool ADJ, int RB, int NT>
 __device__ __forceinline__ void persistent_body(const PersistArgs &pa)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ long long item_s;
+    __shared__ long long item_s, end_s;
     __shared__ int run_s;
-    if (threadIdx.x == 0) item_s = (long long)atomicAdd(pa.head, 1ull);
+    const int64_t K = pa.chunk;
+    if (threadIdx.x == 0) {
+        const int64_t first = (int64_t)atomicAdd(pa.head, (unsigned long long)K);
+        item_s = first;
+        end_s = first + K < pa.n_items ? first + K : pa.n_items;
+        run_s = first < pa.n_items ? (int)persist_wait(pa, persist_item(pa, first, end_s).sg) : 0;
+    }
     __syncthreads();
     int64_t item = uniform_i64(item_s);
+    int64_t end = uniform_i64(end_s);
+    bool run = uniform_i64(run_s) != 0;
+    bool pre = false;
     while (item < pa.n_items) {
-        int lo = 0, hi = pa.n_levels - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pa.levels[mid].first_item <= item) lo = mid; else hi = mid - 1;
-        }
-        const PersistLevel lv = pa.levels[lo];
-        LevelArgs a = pa.base;
-        a.segs = pa.base.segs + lv.seg_off;
-        a.n_segs = lv.n_segs;
-        const int64_t blk = item - lv.first_item;
-        const Seg sg = a.segs[find_block(a.segs, a.n_segs, blk)];
+        const PersistItem it = persist_item(pa, item, end);
+        pre = run ? rtile_body<R, ADJ, RB, NT>(it.a, smem, it.blk, it.sg, pre, it.next_blk) : false;
+        // every wave's stores of the tile have reached the L2 (vmcnt 0; expcnt and lgkmcnt left alone), so
+        // thread 0's device-scope release below (one L2 write-back) covers them all
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
         if (threadIdx.x == 0) {
-            int run = __hip_atomic_load(pa.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-            if (run && sg.wait > 0) {
-                const int64_t need = sg.wait + pa.wait_extra;
-                const int64_t t0 = wall_clock64();
-                while ((int64_t)__hip_atomic_load(pa.done + sg.circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                       need) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (wall_clock64() - t0 > pa.wait_ticks) {
-                        atomicOr(pa.error, 1);
-                        run = 0;
-                        break;
-                    }
-                }
+            __threadfence();
+            atomicAdd(pa.done + it.sg.circ, 1ull);
+            int64_t next = item + 1, nend = end;
+            if (next >= end) {
+                next = (int64_t)atomicAdd(pa.head, (unsigned long long)K);
+                nend = next + K < pa.n_items ? next + K : pa.n_items;
             }
-            __threadfence();
-            run_s = run;
-        }
-        __syncthreads();
-        if (uniform_i64(run_s)) rtile_body<R, ADJ, RB, NT>(a, smem, blk, sg, false, -1);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            atomicAdd(pa.done + sg.circ, 1ull);
-            item_s = (long long)atomicAdd(pa.head, 1ull);
+            // a prefetched successor shares this item's dependency and run flag
+            int r = run ? 1 : 0;
+            if (!pre && next < pa.n_items) r = (int)persist_wait(pa, persist_item(pa, next, nend).sg);
+            item_s = next;
+            end_s = nend;
+            run_s = r;
         }
         __syncthreads();
         item = uniform_i64(item_s);
+        end = uniform_i64(end_s);
+        run = uniform_i64(run_s) != 0;
     }
 }
 
@@ -264,8 +314,8 @@ struct Vec16<double> {
 
 // A one-qubit gate on qubit p as a stream over the state: every byte is read once and written once, in
 // 16-byte vectors, each thread issuing all loads of a round before its first store; with NT (states larger
-// than the caches) the accesses carry the non-temporal hint. Vector index j holds amplitudes E*j .. E*j+E-1, so qubit p is bit pb = p - log2(E)
-// of j. When pb < 6 the partner vector (j ^ 2^pb) is in the same wave: every lane reads the vector at its
+// than the caches) the accesses carry the non-temporal hint. Vector index j holds amplitudes
+// E*j .. E*j+E-1, so qubit p is bit pb = p - log2(E) of j. When pb < 6 the partner vector (j ^ 2^pb) is in the same wave: every lane reads the vector at its
 // own index, consecutive lanes consecutive vectors, and gets its partner from lane ^ 2^pb by a shuffle
 // (pb < 0, complex64 with p = 0: both amplitudes of a pair are in one vector). Otherwise a lane reads a
 // vector and its partner 2^pb vectors on (runs of at least 64 vectors per wave). The adjoint moves lambda
@@ -1195,14 +1245,23 @@ int launch_persistent(const PersistArgs &a, int precision, int adjoint, void *st
     hipError_t e = (hipError_t)persistent_blocks(precision, adjoint, a.base.lds_t, a.base.tab_bits, a.base.max_train,
                                                  &blocks);
     if (e != hipSuccess) return e;
-    if ((int64_t)blocks > a.n_items) blocks = (int)a.n_items;
+    // items claimed at once: as requested, else the level kernels' tile chunk halved until every
+    // workgroup gets a claim
+    PersistArgs pa = a;
+    int64_t chunk = a.chunk;
+    if (chunk <= 0) {
+        chunk = adjoint ? tile_chunk<true>() : tile_chunk<false>();
+        while (chunk > 1 && (a.n_items + chunk - 1) / chunk < blocks) chunk >>= 1;
+    }
+    pa.chunk = (int32_t)chunk;
+    if ((int64_t)blocks > (a.n_items + chunk - 1) / chunk) blocks = (int)((a.n_items + chunk - 1) / chunk);
     const dim3 grid((unsigned)blocks), block(kRtileThreads);
     if (precision == QV_C64) {
-        if (adjoint) hipLaunchKernelGGL((k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
+        if (adjoint) hipLaunchKernelGGL((k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, pa);
+        else hipLaunchKernelGGL((k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, pa);
     } else {
-        if (adjoint) hipLaunchKernelGGL((k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
+        if (adjoint) hipLaunchKernelGGL((k_rtile_adj_persist<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, pa);
+        else hipLaunchKernelGGL((k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, pa);
     }
     return hipGetLastError();
 }

@@ -137,6 +137,7 @@ struct qv_ctx_s {
     int autotune = 1;           // 0 off, 1 cached (use a stored choice), 2 search (time candidates once)
     int persistent = 0;         // 1: one persistent work-queue launch per direction instead of one per level
     int wait_ms = 4000;         // persistent launches: longest dependency wait
+    int persist_chunk = 0;      // persistent launches: items a workgroup claims at once (0: the launcher's choice)
     int wait_extra = 0;         // persistent launches: added to every dependency count (tests of the time-out)
     int fuse_min = 0;           // >0: fuse runs of at least this many register-local gates into MFMA blocks
     int fold_cnots = 1;         // 1: CNOT runs at register-segment boundaries fold into the LDS addressing
@@ -903,7 +904,7 @@ static int enqueue_persistent(const qv_batch_s &bt, ExecSet &es, const DevPlans 
     pa.base.max_train = es.p_max_train[dir];
     pa.levels = (dir == 0 ? es.d_p_fwd : es.d_p_rev).as<PersistLevel>();
     pa.n_levels = (int32_t)lvs.size();
-    pa.pad = 0;
+    pa.chunk = bt.ctx->persist_chunk;
     pa.n_items = dir == 0 ? es.p_fwd_items : es.p_rev_items;
     pa.head = es.d_p_head.as<unsigned long long>();
     pa.done = es.d_p_done.as<unsigned long long>();
@@ -1113,6 +1114,10 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
             const int w = atoi(v.c_str());
             if (w < 0 || w > 600000) return fail(QV_E_INVALID, "wait_ms must be in [0, 600000]");
             c->wait_ms = w;
+        } else if (k == "persist_chunk") {
+            const int w = atoi(v.c_str());
+            if (w < 0 || w > 64) return fail(QV_E_INVALID, "persist_chunk must be in [0, 64]");
+            c->persist_chunk = w;
         } else if (k == "wait_extra") {
             const int w = atoi(v.c_str());
             if (w < 0) return fail(QV_E_INVALID, "wait_extra must be >= 0");

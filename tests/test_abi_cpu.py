@@ -142,6 +142,7 @@ def test_null_pointers_rejected():
                                        ('{"adjoint_inner": "f64"}', "QV_E_INVALID"),
                                        ('{"adjoint_inner": "f64", "specialize": "off"}', "QV_E_INVALID"),
                                        ('{"wait_ms": -1}', "QV_E_INVALID"),
+                                       ('{"persist_chunk": 65}', "QV_E_INVALID"),
                                        ('{"wait_extra": -2}', "QV_E_INVALID"),
                                        ('{"fusion": 99}', "QV_E_INVALID"),
                                        ('{"fusion": "sometimes"}', "QV_E_INVALID"),
