@@ -404,6 +404,39 @@ def test_stride_engine_full_size(qv, prec):
     b.close()
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_neighbour_and_long_range_terms(qv, prec):
+    """A many-term observable on a 20-qubit circuit: neighbour XX, YY and XZ terms, single-qubit Z and X,
+    and long-range strings (X0 X19, Y2 Z9 X17, X5 X19, Y6 Z9 X13 Y19), 88 terms, several sharing an x-mask
+    (XX with YY, X with XZ): term values, energy and adjoint gradient against the oracle."""
+    say(f"neighbour and long-range terms prec={prec}")
+    n = 20
+    rng = np.random.default_rng(7720)
+    wl0 = W.large_hea(n, 2, seed_index=9)
+    strings = []
+    for i in range(n - 1):
+        strings.append({i: "X", i + 1: "X"})
+        strings.append({i: "Y", i + 1: "Y"})
+        strings.append({i: "X", i + 1: "Z"})
+    strings += [{i: "Z"} for i in range(n)] + [{i: "X"} for i in range(0, n, 3)]
+    strings += [{0: "X", 19: "X"}, {2: "Y", 9: "Z", 17: "X"}, {5: "X", 19: "X"}, {6: "Y", 9: "Z", 13: "X", 19: "Y"}]
+    masks = [W.parse_pauli("".join(d.get(q, "I") for q in range(n))) for d in strings]
+    xm = np.array([m[0] for m in masks], np.uint64)
+    zm = np.array([m[1] for m in masks], np.uint64)
+    co = rng.normal(0.0, 1.0, len(strings))
+    wl = W.single("tiles20", n, [tuple(g) for g in wl0.circuit(0)], wl0.theta_of(0), (xm, zm, co))
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    g_ref = oracle.grad_adjoint(wl)
+    b = qv.Batch(ctx_for(qv), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(tv, tv_ref, prec, 1.0, "terms")
+    check(e, e_ref, prec, s, "energy")
+    g, _ = b.gradient(qv.QV_ADJOINT)
+    check(g, g_ref, prec, s, "adjoint grad")
+    b.close()
+
+
 def test_error_paths_on_device(qv):
     import ctypes
     say("error paths")
