@@ -197,20 +197,26 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                                        "speedup": round(s_ps / s_ad, 1),
                                        "param_shift_circuits": wl.B * (2 * wl.n_grad() + 1)}
         b.close()
-    # the benchmark workload in complex128 (FP64 throughout; register tiles of 2^12 amplitudes)
+    # the benchmark workload in complex128 (FP64 throughout; register tiles of 2^12 amplitudes), with the
+    # general tile kernels and with generated adjoint passes where they time faster
     if only in (None, "qcl"):
         wl = W.config3(8)
-        b = qvpu.Batch(ctx(fusion="off"), wl, qvpu.QV_C128)
-        e, _ = b.expectations(want_terms=False)
-        up = 2.0 * (e - wl.extra["y"]) / wl.B
+        rec = {}
+        for spec in ("off", "auto"):
+            b = qvpu.Batch(ctx(fusion="off", specialize=spec), wl, qvpu.QV_C128)
+            e, _ = b.expectations(want_terms=False)
+            up = 2.0 * (e - wl.extra["y"]) / wl.B
 
-        def grad128():
-            b.expectations(want_terms=False)
-            b.gradient(qvpu.QV_ADJOINT, upstream=up)
+            def grad128():
+                b.expectations(want_terms=False)
+                b.gradient(qvpu.QV_ADJOINT, upstream=up)
 
-        s_ad = timed(grad128, sync, 3)
-        out["qcl20_L8_S64_c128"] = {"adjoint_gradients_per_s": round(1.0 / s_ad, 3), "ms": round(s_ad * 1e3, 3)}
-        b.close()
+            s_ad = timed(grad128, sync, 3)
+            key = "" if spec == "off" else "_specialize_auto"
+            rec["adjoint_gradients_per_s" + key] = round(1.0 / s_ad, 3)
+            rec["ms" + key] = round(s_ad * 1e3, 3)
+            b.close()
+        out["qcl20_L8_S64_c128"] = rec
     # the 16-qubit VQE parameter-shift gradient (513 circuits) and 1024 uneven random circuits, each with
     # one launch per pass level and with every sweep in one persistent launch
     wl = W.config2()
