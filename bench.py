@@ -130,7 +130,8 @@ def copy_ceiling(torch, stream, reps: int = 10) -> dict:
 def stride_profile(qvpu, W, stream, sync, n: int) -> dict:
     """The stride engine alone on one n-qubit complex64 state: RY and RZ on every qubit (2n one-qubit
     gates, each one global-memory pass reading and writing the whole state), then the ZZ-chain
-    expectation. Per-launch HIP events give each kernel's average time and algorithmic GB/s."""
+    expectation. Per-launch HIP events give each kernel's average time and algorithmic GB/s. Then the same
+    forward call on the stride, LDS-tile and register-tile engines, each with its gate-equivalent GB/s."""
     gates = [W.gate(W.RY, q, -1, q) for q in range(n)] + [W.gate(W.RZ, q, -1, n + q) for q in range(n)]
     theta = np.random.default_rng(SEED_PROFILE).uniform(0, 2 * np.pi, 2 * n)
     zm = np.array([(1 << i) | (1 << (i + 1)) for i in range(n - 1)], np.uint64)
@@ -152,7 +153,39 @@ def stride_profile(qvpu, W, stream, sync, n: int) -> dict:
         out[k] = {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4),
                   "algorithmic_bytes_per_launch": int(v["avg_bytes"]), "gbs": round(v["gbs"], 1),
                   "frac_of_peak": round(v["gbs"] / HBM_PEAK_GBS, 4)}
+    # the same forward call on each engine: what LDS tiles and register tiles buy over one pass per gate
+    eng = {}
+    for engine in ("stride", "lds", "tiled"):
+        ctx = qvpu.Context(0, stream.cuda_stream, json.dumps({"engine": engine, "graph": True}))
+        b = qvpu.Batch(ctx, wl, qvpu.QV_C64)
+        sec = timed(lambda: b.expectations(), sync, 3)
+        eng[engine] = {"forward_ms": round(sec * 1e3, 3), "passes": b.stats()["passes_per_circuit_max"],
+                       "gate_equivalent": gate_equivalent(wl, 8, False, sec)}
+        b.close()
+    out["engines"] = eng
     return out
+
+
+def unfused_bytes(wl, amp_bytes: int, adjoint: bool) -> int:
+    """HBM bytes the plain per-gate method would move for one call over the batch: every gate one pass over
+    the state (2S), every distinct x-mask of the observable one read (S); with adjoint, the seed lambda = H psi
+    (read psi, write lambda: 2S) and every gate once more over psi and lambda (4S). Dividing by the measured
+    time gives the "gate-equivalent" bandwidth, which shows what tiling and fusion buy over that method."""
+    total = 0
+    for b in range(wl.B):
+        S = (1 << int(wl.n_qubits[b])) * amp_bytes
+        G = int(wl.gate_offsets[b + 1] - wl.gate_offsets[b])
+        groups = len(set(int(x) for x in wl.terms(b)[0])) if wl.term_offsets is not None else 0
+        total += (2 * G + groups) * S
+        if adjoint:
+            total += (2 + 4 * G) * S
+    return total
+
+
+def gate_equivalent(wl, amp_bytes: int, adjoint: bool, seconds: float) -> dict:
+    by = unfused_bytes(wl, amp_bytes, adjoint)
+    gbs = by / seconds / 1e9
+    return {"unfused_bytes": by, "gbs": round(gbs, 1), "times_hbm_peak": round(gbs / HBM_PEAK_GBS, 2)}
 
 
 def timed(fn, stream_sync, reps: int = 1) -> float:
@@ -239,6 +272,8 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
             key = "" if launch == "levels" else "_persistent"
             rec["circuit_evals_per_s" + key] = round(wl.B / s, 1)
             rec["ms" + key] = round(s * 1e3, 3)
+            if launch == "levels":
+                rec["gate_equivalent"] = gate_equivalent(wl, 8, False, s)
             b.close()
         out["random1024_expectations_c64"] = rec
     # MC-VQE-shaped batches at Table 1's sizes: one circuit per CIS state, mean-energy gradient
@@ -295,7 +330,9 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
         sg = timed(lambda: b.gradient(qvpu.QV_ADJOINT), sync, 1)
         st = b.stats()
         out[f"hea32_L10_c64_fusion_{fusion}"] = {"forward_ms": round(sf * 1e3, 2), "gradient_ms": round(sg * 1e3, 2),
-                                                  "passes": st["passes_per_circuit_max"]}
+                                                  "passes": st["passes_per_circuit_max"],
+                                                  "gate_equivalent_forward": gate_equivalent(wl, 8, False, sf),
+                                                  "gate_equivalent_gradient": gate_equivalent(wl, 8, True, sg)}
         b.close()
     return out
 
@@ -511,6 +548,7 @@ def main():
                    "autotuned": not (args.tile_qubits or args.contig), "launch": args.launch,
                    "fusion": args.fusion, "specialize": args.specialize},
         "roofline": roofline,
+        "gate_equivalent": gate_equivalent(wl, 8, True, ms_step / 1e3),
         "fused_blocks": fused,
         "circuit_evals_per_s": round(circuit_evals_per_s, 1),
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 4), "gbs": round(v["gbs"], 1),
