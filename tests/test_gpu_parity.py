@@ -173,6 +173,51 @@ def test_one_to_three_qubit_circuits(qv, prec, engine):
     check(g2, g_ref, prec, s * np.sum(np.abs(up)), "param-shift grad")
 
 
+def _degenerate_batch():
+    """Four circuits, own parameters and own observables: 5 qubits with no gates; 6 qubits whose parameter 0
+    drives three gates (RY, RX, RZ on different qubits) and parameter 1 one; 4 qubits with gates and no
+    terms; 3 qubits with fixed angles only (no parameters)."""
+    rng = np.random.default_rng(4411)
+    g = W.gate
+    c0 = []
+    c1 = [g(W.H, 1), g(W.RY, 0, -1, 0), g(W.CNOT, 0, 3), g(W.RX, 2, -1, 0), g(W.RY, 5, -1, 1), g(W.CNOT, 2, 5),
+          g(W.RZ, 4, -1, 0), g(W.H, 4), g(W.CZ, 4, 1), g(W.RY, 3, -1, 1)]
+    c2 = [g(W.H, 0), g(W.RY, 1, -1, 0), g(W.CNOT, 0, 2), g(W.RZ, 3, -1, 1)]
+    c3 = [g(W.RX, 0, -1, -1, 0.3), g(W.CNOT, 0, 1), g(W.RY, 2, -1, -1, 1.1), g(W.T, 2)]
+    t0 = (np.array([0, 2], np.uint64), np.array([1, 4 | 8], np.uint64), np.array([0.7, -1.3]))
+    t1 = W.random_paulis(rng, 6, 6)
+    t2 = (np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0))
+    t3 = W.random_paulis(rng, 4, 3)
+    theta = rng.uniform(0, 2 * np.pi, 4)
+    return W._pack("degenerate", [c0, c1, c2, c3], [5, 6, 4, 3], [0, 2, 2, 0], False, theta,
+                   [t0, t1, t2, t3], False)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("engine", ["tiled", "stride"])
+def test_degenerate_circuits_and_shared_parameter(qv, prec, engine):
+    """A circuit without gates (|0...0>: Z strings give their coefficient, X strings 0), one without terms
+    (energy and gradient 0), one without parameters, and a parameter driving three gates (its gradient sums
+    the three, by the adjoint and by per-gate shifts): energies, terms and both gradients against the
+    oracle, whose chain rule is pinned against finite differences on the CPU."""
+    say(f"degenerate prec={prec} engine={engine}")
+    wl = _degenerate_batch()
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    assert abs(e_ref[0] - 0.7) < 1e-15 and e_ref[2] == 0.0
+    up = np.array([1.0, -0.5, 2.0, 0.25])
+    g_ref = oracle.grad_param_shift(wl, up)
+    b = qv.Batch(ctx_for(qv, engine=engine), wl, prec)
+    e, tv = b.expectations()
+    s = obs_scale(wl)
+    check(e, e_ref, prec, s, "energy")
+    check(tv, tv_ref, prec, 1.0, "terms")
+    g_ad, _ = b.gradient(qv.QV_ADJOINT, upstream=up)
+    check(g_ad, g_ref, prec, s * np.sum(np.abs(up)), "adjoint grad")
+    g_ps, _ = b.gradient(qv.QV_PARAM_SHIFT, upstream=up)
+    check(g_ps, g_ref, prec, s * np.sum(np.abs(up)), "param-shift grad")
+    b.close()
+
+
 def test_waves_and_engines_bitwise(qv):
     """Results do not depend on how many circuits are in flight (n-virtual-qpus): bitwise equal."""
     say("waves")
