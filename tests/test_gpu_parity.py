@@ -387,12 +387,13 @@ def test_random1024_full_size(qv):
     check(tv, np.array(gold["term_values"]), 0, 1.0, "terms")
 
 
-@pytest.mark.parametrize("n,opts", [(26, {}), (32, {}), (26, {"engine": "stride"})])
+@pytest.mark.parametrize("n,opts", [(26, {}), (32, {}), (33, {}), (26, {"engine": "stride"})])
 def test_large_state_closed_form(qv, n, opts):
-    """One HEA layer on n qubits (32: a 32 GiB complex64 state) with the ZZ chain: the CNOT ladder is a
-    prefix-XOR permutation, so E = sum_{i>=1} cos(theta_RY[i]) and dE/dtheta_RY[i] = -sin(theta_RY[i])
-    (0 for i = 0); checks 64-bit indexing at full size, and on the stride engine the non-temporal
-    passes taken for states larger than the caches."""
+    """One HEA layer on n qubits (32: a 32 GiB complex64 state; 33: 64 GiB, amplitude indices past 2^32,
+    128 GiB with lambda) with the ZZ chain: the CNOT ladder is a prefix-XOR permutation, so
+    E = sum_{i>=1} cos(theta_RY[i]) and dE/dtheta_RY[i] = -sin(theta_RY[i]) (0 for i = 0); checks 64-bit
+    indexing at full size, and on the stride engine the non-temporal passes taken for states larger than
+    the caches."""
     say(f"large n={n} opts={opts}")
     wl = W.large_hea(n, 1, seed_index=5)
     b = qv.Batch(ctx_for(qv, **opts), wl, 0)
