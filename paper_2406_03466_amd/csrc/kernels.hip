@@ -794,6 +794,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize_energies(FinalizeArgs a)
 }
 
 // lambda_b[o] = w_b sum_t c_t (P_t psi_b)[o], (P psi)[o] = i^{ny} (-1)^{popcount((o^x) & z)} psi[o ^ x].
+// A block covers 4096 consecutive amplitudes of one circuit, a thread kLambdaPer of them,
+// o = o0 | tid | (j << 8), in rounds of kLambdaRound. Each round walks the terms in the host's x-mask order:
+// at each new mask the thread reads psi[o ^ x] for the round's amplitudes at once, then adds every term of
+// that mask. A term's sign splits like the expectation's: (-1)^popcount(x & z) and the thread's part
+// (o0 | tid) & z once per term, the part of j from the wave-uniform z.
+constexpr int kLambdaPer = 4096 / kBlock;
+constexpr int kLambdaRound = 8;
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
 {
@@ -806,45 +814,51 @@ __global__ __launch_bounds__(kBlock) void k_lambda(LambdaArgs a)
     Cx<R> *lam = reinterpret_cast<Cx<R> *>(a.lam) + C.state_off;
     const double w = a.upstream ? a.upstream[C.base_circ] : 1.0;
     const int64_t tb = a.obs_begin[c], te = a.obs_begin[c + 1];
-    for (uint32_t e = threadIdx.x; e < 4096u; e += kBlock) {
-        const uint64_t o = o0 + e;
-        if (o >= dim) break;
-        // diagonal terms (x-mask 0) scale psi[o] itself: their signed coefficients are summed first; the
-        // host orders the other terms by x-mask, so terms sharing one read psi[o ^ x] once
-        double d = 0.0, sr = 0.0, si = 0.0;
-        uint64_t px = 0;
-        double vr = 0.0, vi = 0.0;
+    const uint64_t ot = o0 | (uint64_t)threadIdx.x;
+    for (int h = 0; h < kLambdaPer; h += kLambdaRound) {
+        double ar[kLambdaRound], ai[kLambdaRound];
+        Cx<R> v[kLambdaRound];
+#pragma unroll
+        for (int j = 0; j < kLambdaRound; j++) {
+            ar[j] = ai[j] = 0.0;
+            v[j].re = v[j].im = (R)0;
+        }
+        uint64_t px = ~0ull;
         for (int64_t t = tb; t < te; t++) {
             const DevObsTerm term = ldu(a.obs + t);
-            if (term.xmask == 0) {
-                d += parity64(o & term.zmask) ? -term.coeff : term.coeff;
-                continue;
-            }
-            const uint64_t b = o ^ term.xmask;
             if (term.xmask != px) {
-                const Cx<R> v = st[b];
-                vr = v.re;
-                vi = v.im;
                 px = term.xmask;
+#pragma unroll
+                for (int j = 0; j < kLambdaRound; j++) {
+                    const uint64_t o = ot | ((uint64_t)(h + j) << 8);
+                    v[j] = st[(o < dim ? o : 0ull) ^ px];   // past a small state's end: a valid amplitude
+                }
             }
-            double pr, pi;
-            switch (term.ny) {
-            case 0: pr = vr; pi = vi; break;
-            case 1: pr = -vi; pi = vr; break;
-            case 2: pr = -vr; pi = -vi; break;
-            default: pr = vi; pi = -vr; break;
+            // c i^ny as a complex weight, signed by the parts of the sign that do not depend on j
+            const double c0 =
+                (parity64(term.xmask & term.zmask) ^ parity64(ot & term.zmask)) ? -term.coeff : term.coeff;
+            const double wr = (term.ny & 1) ? 0.0 : ((term.ny & 2) ? -c0 : c0);
+            const double wi = (term.ny & 1) ? ((term.ny & 2) ? -c0 : c0) : 0.0;
+            const uint32_t zj = (uint32_t)(term.zmask >> 8) & (uint32_t)(kLambdaPer - 1);
+#pragma unroll
+            for (int j = 0; j < kLambdaRound; j++) {
+                const bool neg = __popc((uint32_t)(h + j) & zj) & 1;
+                const double sr = neg ? -wr : wr, si = neg ? -wi : wi;
+                const double xr = (double)v[j].re, xi = (double)v[j].im;
+                ar[j] = fma(sr, xr, fma(-si, xi, ar[j]));
+                ai[j] = fma(sr, xi, fma(si, xr, ai[j]));
             }
-            const double cf = parity64(b & term.zmask) ? -term.coeff : term.coeff;
-            sr += cf * pr;
-            si += cf * pi;
         }
-        const Cx<R> v0 = st[o];
-        sr += d * (double)v0.re;
-        si += d * (double)v0.im;
-        Cx<R> out;
-        out.re = (R)(w * sr);
-        out.im = (R)(w * si);
-        lam[o] = out;
+#pragma unroll
+        for (int j = 0; j < kLambdaRound; j++) {
+            const uint64_t o = ot | ((uint64_t)(h + j) << 8);
+            if (o < dim) {
+                Cx<R> out;
+                out.re = (R)(w * ar[j]);
+                out.im = (R)(w * ai[j]);
+                lam[o] = out;
+            }
+        }
     }
 }
 
