@@ -41,7 +41,7 @@ def _embed_headers() -> None:
            f"static const char *kGenHeaderNames[] = {{{', '.join(names)}}};\n"
            f"static const char *kGenHeaderText[] = {{\n" + ",\n".join(texts) + "};\n")
     path = os.path.join(OBJDIR, "jit_headers.inc")
-    tmp = path + ".tmp"
+    tmp = f"{path}.tmp{os.getpid()}"   # parallel test workers each write their own before the rename
     with open(tmp, "w") as f:
         f.write(out)
     os.replace(tmp, path)

@@ -39,6 +39,10 @@ size_t lds_bytes(const GenPassDesc &d)
     return b;
 }
 
+// Written after every op: the compiler may not move instructions across it, which keeps each op's
+// loads and arithmetic together instead of spread over the whole straight-line program.
+const char *const kOpFence = "        __builtin_amdgcn_sched_barrier(0);\n";
+
 void op_args(std::ostringstream &o, const DevOp &op)
 {
     o << (op.flags >> kOpCodeShift) << ", " << (int)op.kind << ", " << (int)op.p0 << ", " << (int)op.p1 << ", "
@@ -53,21 +57,22 @@ void emit_fwd(std::ostringstream &o, const GenPassDesc &d, const DevSeg &S, int 
         if (op.kind == kFusedKind) {
             if (!fuse) continue;  // complex128: the block's gates follow and run one by one
             const int m = op.pad, fidx = op.p0 | (op.p1 << 8);
-            o << "        if (";
-            for (int g = 1; g <= m; g++) o << (g > 1 ? " || " : "") << "C.shift_gate == " << d.ops[rel0 + j + g].gate;
-            o << ") {\n";
+            // the shifted gate's index is opaque at each block (see gen_mat)
+            o << "        if (gen_shift_in<";
+            for (int g = 1; g <= m; g++) o << (g > 1 ? ", " : "") << d.ops[rel0 + j + g].gate;
+            o << ">(C)) {\n";
             for (int g = 1; g <= m; g++) {
                 o << "            gen_fwd_op<R, RB, ";
                 op_args(o, d.ops[rel0 + j + g]);
                 o << ">(a, C, circ, mp, " << j + g << ", Et, v);\n";
             }
-            o << "        } else {\n            gen_fused<" << fidx << ">(a, C, lane, v);\n        }\n";
+            o << "        } else {\n            gen_fused<" << fidx << ">(a, C, lane, v);\n        }\n" << kOpFence;
             j += m;
             continue;
         }
         o << "        gen_fwd_op<R, RB, ";
         op_args(o, op);
-        o << ">(a, C, circ, mp, " << j << ", Et, v);\n";
+        o << ">(a, C, circ, mp, " << j << ", Et, v);\n" << kOpFence;
     }
 }
 
@@ -81,7 +86,7 @@ void emit_adj(std::ostringstream &o, const GenPassDesc &d, const DevSeg &S, int 
         o << (below ? "        if (!stop_early) gen_adj_op<R, RB, NT, " : "        gen_adj_op<R, RB, NT, ");
         op_args(o, op);
         o << ", " << ((op.flags & OP_TRAIN) ? 1 : 0) << ", " << op.train_slot
-          << ">(a, C, circ, mp, " << j << ", Et, active, lane, wave, red, av, lv);\n";
+          << ">(a, C, circ, mp, " << j << ", Et, active, lane, wave, red, av, lv);\n" << kOpFence;
     }
 }
 

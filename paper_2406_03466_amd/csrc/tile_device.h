@@ -736,21 +736,32 @@ struct InterpProg {
     static constexpr bool kGenerated = false;
 };
 
-// One op of a generated program, forward: its matrix from the circuit's table (k: the op's index within its
-// segment), or the shifted matrix of a parameter-shift variant's moved gate; the op-code switch of
-// code_apply folds away, its operands being constants.
+// The matrix of one op of a generated program: from the circuit's table (k: the op's index within its
+// segment), or the shifted matrix of a parameter-shift variant's moved gate. The shifted gate's index is
+// made opaque at each op: otherwise the compiler hoists every op's test GATE == shift_gate (a 64-bit lane
+// mask each) out of the tile loops, and hundreds of live scalar registers spill into vector registers
+// (into scratch under the forward's 128-register cap).
+template <typename R, int GATE>
+__device__ __forceinline__ M2<R> gen_mat(const LevelArgs &a, const DevCirc &C, int circ, const M2<R> *mp, int k)
+{
+    int shift = C.shift_gate;
+    asm volatile("" : "+s"(shift));
+    M2<R> mat = ldu(mp + k);
+    if (GATE == shift) {
+        mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
+        scalar_wait(mat);
+    }
+    return mat;
+}
+
+// One op of a generated program, forward; the op-code switch of code_apply folds away, its operands being
+// constants.
 template <typename R, int RB, int CODE, int KIND, int P0, int P1, int K0, int K1, int GATE>
 __device__ __forceinline__ void gen_fwd_op(const LevelArgs &a, const DevCirc &C, int circ, const M2<R> *mp, int k,
                                            uint32_t Et, Regs<R, 1 << RB> &v)
 {
-    M2<R> mat;
-    if constexpr (KIND != QV_CNOT && KIND != QV_CZ) {
-        mat = ldu(mp + k);
-        if (GATE == C.shift_gate) {
-            mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
-            scalar_wait(mat);
-        }
-    }
+    M2<R> mat{};
+    if constexpr (KIND != QV_CNOT && KIND != QV_CZ) mat = gen_mat<R, GATE>(a, C, circ, mp, k);
     DevOp op;
     op.gate = GATE;
     op.kind = (uint8_t)KIND;
@@ -772,14 +783,8 @@ __device__ __forceinline__ void gen_adj_op(const LevelArgs &a, const DevCirc &C,
                                            uint32_t Et, bool active, int lane, int wave, double *red,
                                            Regs<R, 1 << RB> &av, Regs<R, 1 << RB> &lv)
 {
-    M2<R> mat;
-    if constexpr (KIND != QV_CNOT && KIND != QV_CZ) {
-        mat = ldu(mp + k);
-        if (GATE == C.shift_gate) {
-            mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + circ);
-            scalar_wait(mat);
-        }
-    }
+    M2<R> mat{};
+    if constexpr (KIND != QV_CNOT && KIND != QV_CZ) mat = gen_mat<R, GATE>(a, C, circ, mp, k);
     DevOp op;
     op.gate = GATE;
     op.kind = (uint8_t)KIND;
@@ -798,11 +803,25 @@ __device__ __forceinline__ void gen_adj_op(const LevelArgs &a, const DevCirc &C,
     }
 }
 
-// A fused block of a generated forward program: its 16x16 product on MFMA (complex64).
+// Whether a parameter-shift variant's shifted gate is one of GATES (a fused block's gates), with the
+// shifted index opaque here so that the test is not hoisted out of the tile loops (see gen_fwd_op).
+template <int... GATES>
+__device__ __forceinline__ bool gen_shift_in(const DevCirc &C)
+{
+    int shift = C.shift_gate;
+    asm volatile("" : "+s"(shift));
+    return ((shift == GATES) || ...);
+}
+
+// A fused block of a generated forward program: its 16x16 product on MFMA (complex64). The block's index
+// is opaque here, so that its 16 A-operand loads stay at the block instead of being hoisted, for every
+// block of the program, out of the tile loops (16 live vector registers per block, spilled).
 template <int FIDX>
 __device__ __forceinline__ void gen_fused(const LevelArgs &a, const DevCirc &C, int lane, Regs<float, 16> &v)
 {
-    fused_mfma(v, a.fmats + (C.fused_off + FIDX) * (int64_t)kFusedFloats, lane);
+    int f = FIDX;
+    asm volatile("" : "+s"(f));
+    fused_mfma(v, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
 }
 
 template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg>
