@@ -447,8 +447,8 @@ def main():
                   "rtile_adj": "k_rtile_adj<float,4,512>", "rtile": "k_rtile_fwd<float,4,512>",
                   "rtile_adj_persist": "k_rtile_adj_persist<float,4,512>",
                   "rtile_persist": "k_rtile_fwd_persist<float,4,512>",
-                  "rtile_adj_gen": "qv_gen_pass (generated adjoint tile pass, complex64)",
-                  "rtile_gen": "qv_gen_pass (generated forward tile pass, complex64)"}.get(dom, dom)
+                  "rtile_adj_gen": "qv_gen_adj (generated adjoint tile pass, complex64)",
+                  "rtile_gen": "qv_gen_fwd (generated forward tile pass, complex64)"}.get(dom, dom)
     workload_tag = f"qcl20_L{args.layers}"
     traffic = pmc_traffic(dom, workload_tag)
     if dom in TILE_KERNELS:

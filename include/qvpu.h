@@ -163,9 +163,11 @@ typedef struct qv_batch_s *qv_batch;
  *                      straight-line code, compiled with hipRTC on the first call that needs it; code
  *                      objects are kept in the directory named by QV_GEN_CACHE, default
  *                      $HOME/.cache/qvpu_gen), in reverse (adjoint) sweeps only, in both directions, or
- *                      ("auto") in the reverse levels where it measured faster: the first adjoint call
- *                      then times one reverse sweep with each kind of kernel. Same results as the general
- *                      kernels, up to floating-point contraction; QV_E_DEVICE if the compilation fails;
+ *                      ("auto") in the levels of either direction where it measured faster: the first call
+ *                      that runs sweeps of a direction times two of them with each kind of kernel. A
+ *                      generated forward pass applies a fused block's gates one by one. Same results as the
+ *                      general kernels, up to floating-point contraction; QV_E_DEVICE if the compilation
+ *                      fails;
  *   "adjoint_inner"  : "f32" (default) or "f64" (needs "specialize" "adjoint", "on" or "auto"): in complex64
  *                      adjoint sweeps a thread's Im <lambda| G |psi> products are summed in FP32 before the
  *                      FP64 wave, tile and circuit sums ("f32"), or every product of two FP32 amplitude

@@ -51,25 +51,14 @@ void op_args(std::ostringstream &o, const DevOp &op)
 
 void emit_fwd(std::ostringstream &o, const GenPassDesc &d, const DevSeg &S, int rel0)
 {
-    const bool fuse = d.precision == QV_C64;
+    // A fused block's gates run one by one here (they follow its marker). With the block's MFMA product
+    // in the same straight-line program, the forward pass needs about 200 registers a lane: at the
+    // 128 of two workgroups per CU the register set is spilled around every segment, and at one
+    // workgroup per CU the pass is slower than the general kernel with its blocks, so a level takes
+    // whichever of the two kernels times faster.
     for (int j = 0; j < S.n_ops; j++) {
         const DevOp &op = d.ops[rel0 + j];
-        if (op.kind == kFusedKind) {
-            if (!fuse) continue;  // complex128: the block's gates follow and run one by one
-            const int m = op.pad, fidx = op.p0 | (op.p1 << 8);
-            // the shifted gate's index is opaque at each block (see gen_mat)
-            o << "        if (gen_shift_in<";
-            for (int g = 1; g <= m; g++) o << (g > 1 ? ", " : "") << d.ops[rel0 + j + g].gate;
-            o << ">(C)) {\n";
-            for (int g = 1; g <= m; g++) {
-                o << "            gen_fwd_op<R, RB, ";
-                op_args(o, d.ops[rel0 + j + g]);
-                o << ">(a, C, circ, mp, " << j + g << ", Et, v);\n";
-            }
-            o << "        } else {\n            gen_fused<" << fidx << ">(a, C, lane, v);\n        }\n" << kOpFence;
-            j += m;
-            continue;
-        }
+        if (op.kind == kFusedKind) continue;
         o << "        gen_fwd_op<R, RB, ";
         op_args(o, op);
         o << ">(a, C, circ, mp, " << j << ", Et, v);\n" << kOpFence;
@@ -161,7 +150,7 @@ namespace {
 std::string compile(const std::string &src, std::string &err)
 {
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "qv_gen_pass.hip", kGenHeaderCount, kGenHeaderText,
+    if (hiprtcCreateProgram(&prog, src.c_str(), "qv_gen.hip", kGenHeaderCount, kGenHeaderText,
                             kGenHeaderNames) != HIPRTC_SUCCESS) {
         err = "hiprtcCreateProgram failed";
         return {};
@@ -194,6 +183,8 @@ std::mutex g_mu;
 std::map<std::pair<int, uint64_t>, Loaded> g_loaded;  // (device, source key) -> module
 
 }  // namespace
+
+const char *gen_kernel_name(int adjoint) { return adjoint ? "qv_gen_adj" : "qv_gen_fwd"; }
 
 std::string gen_pass_source(const GenPassDesc &d)
 {
@@ -234,7 +225,8 @@ std::string gen_pass_source(const GenPassDesc &d)
     }
     o << "    }\n};\n\n}  // namespace qv\n\n";
     o << "extern \"C\" __global__ __launch_bounds__(" << kRtileThreads << ")"
-      << (d.adjoint ? "" : " __attribute__((amdgpu_waves_per_eu(4)))") << " void qv_gen_pass(qv::LevelArgs a)\n{\n"
+      << (d.adjoint ? "" : " __attribute__((amdgpu_waves_per_eu(4)))") << " void " << gen_kernel_name(d.adjoint)
+      << "(qv::LevelArgs a)\n{\n"
       << "    __shared__ __align__(16) unsigned char smem[" << lds_bytes(d) << "];\n"
       << "    qv::rtile_tiles<" << (c64 ? "float" : "double") << ", " << (d.adjoint ? "true" : "false") << ", "
       << (c64 ? kRegBitsC64 : kRegBitsC128) << ", " << kRtileThreads << ", qv::GenProg>(a, smem);\n}\n";
@@ -297,10 +289,13 @@ int gen_kernels(const std::vector<std::string> &srcs, std::vector<void *> &fns, 
             err = "hipModuleLoadData failed for a generated tile pass";
             return he;
         }
-        he = hipModuleGetFunction(&ld.fn, ld.mod, "qv_gen_pass");
+        // the source names its kernel for its direction
+        const char *name = gen_kernel_name(srcs[i].find(std::string(" void ") + gen_kernel_name(1) + "(") !=
+                                           std::string::npos);
+        he = hipModuleGetFunction(&ld.fn, ld.mod, name);
         if (he != hipSuccess) {
             (void)hipModuleUnload(ld.mod);
-            err = "generated tile pass has no kernel qv_gen_pass";
+            err = std::string("generated tile pass has no kernel ") + name;
             return he;
         }
         std::lock_guard<std::mutex> lk(g_mu);

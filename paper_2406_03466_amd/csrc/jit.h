@@ -22,7 +22,10 @@ struct GenPassDesc {
     int inner_f64 = 0;            // complex64 adjoint: inner products formed and summed in FP64
 };
 
-// HIP C++ source of the kernel `qv_gen_pass` for one pass and direction.
+// Name of a generated pass's kernel: qv_gen_fwd (forward sweep) or qv_gen_adj (reverse sweep).
+const char *gen_kernel_name(int adjoint);
+
+// HIP C++ source of the kernel gen_kernel_name(d.adjoint) for one pass and direction.
 std::string gen_pass_source(const GenPassDesc &d);
 
 // hipRTC alone (no device): the code object of one generated source, or an empty string and err.

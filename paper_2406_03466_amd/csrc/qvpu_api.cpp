@@ -309,7 +309,7 @@ struct ExecSet {
     std::vector<PartialRef> grefs;
     int64_t algo_bytes_fwd = 0, algo_bytes_rev = 0, passes_fwd = 0, passes_rev = 0;
     bool gen_ready[2] = {false, false};  // generated kernels looked up for the forward / reverse levels
-    bool gen_timed = false;              // reverse levels: generated or general kernel chosen by timing
+    bool gen_timed[2] = {false, false};  // forward / reverse levels: generated or general kernel chosen by timing
     int64_t init_bytes = 0, exp_bytes = 0, lam_bytes = 0;
 
     // device copies
@@ -481,7 +481,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                          int amp_bytes)
 {
     es.gen_ready[0] = es.gen_ready[1] = false;
-    es.gen_timed = false;
+    es.gen_timed[0] = es.gen_timed[1] = false;
     es.segs.clear(); es.fwd.clear(); es.rev.clear();
     es.partial_count = 0;
     es.algo_bytes_fwd = es.algo_bytes_rev = es.passes_fwd = es.passes_rev = 0;
@@ -1018,48 +1018,89 @@ static int enqueue_reverse(const qv_batch_s &bt, ExecSet &es, const DevPlans &dp
     return logged(log, s, QV_K_GRAD_REDUCE, -1, 0, [&] { return launch_grad_reduce(ga, s); });
 }
 
-// "specialize": "auto": reverse sweeps alternately with the general kernels and with the generated ones
-// (two of each, every one after its own forward pass, eager, with per-launch events), then every reverse
-// level keeps the kernel with the lower of its two times. Once per execution set; it leaves no valid final
-// states behind.
-static qv_status time_generated_reverse(qv_batch_s *bt, ExecSet &es)
+// "specialize": "auto": sweeps of one direction alternately with the general kernels and with the generated
+// ones (kTimingSweeps in all, eager, with per-launch events), then every level of that direction keeps the
+// kernel with the lower of its two times. `sweep` enqueues one timed sweep and logs the levels of direction
+// `dir` (a reverse sweep runs after its own forward pass, whose levels keep their kernels). Once per
+// execution set and direction; it leaves no valid final states behind.
+template <class Sweep>
+static qv_status time_generated(qv_batch_s *bt, ExecSet &es, int dir, Sweep &&sweep)
 {
-    if (!(bt->ctx->specialize & kSpecializeTimed) || es.gen_timed || bt->ctx->persistent) return QV_OK;
-    es.gen_timed = true;
+    if (!(bt->ctx->specialize & kSpecializeTimed) || es.gen_timed[dir] || bt->ctx->persistent) return QV_OK;
+    es.gen_timed[dir] = true;
+    std::vector<Level> &lvs = dir ? es.rev : es.fwd;
     std::vector<void *> gens;
     bool any = false;
-    for (const Level &lv : es.rev) {
+    for (const Level &lv : lvs) {
         gens.push_back(lv.gen);
         any |= lv.gen != nullptr;
     }
     if (!any) return QV_OK;
-    const DevPlans &dp = *bt->dp;
+    const int k_general = dir ? QV_K_RTILE_ADJ : QV_K_RTILE, k_gen = dir ? QV_K_RTILE_ADJ_GEN : QV_K_RTILE_GEN;
     hipStream_t s = bt->ctx->stream();
     std::vector<double> ms[2];
-    ms[0].assign(es.rev.size(), 1e300);
-    ms[1].assign(es.rev.size(), 1e300);
+    ms[0].assign(lvs.size(), 1e300);
+    ms[1].assign(lvs.size(), 1e300);
     for (int run = 0; run < kTimingSweeps; run++) {
         const int variant = run & 1;
-        for (size_t L = 0; L < es.rev.size(); L++) es.rev[L].gen = variant ? gens[L] : nullptr;
+        for (size_t L = 0; L < lvs.size(); L++) lvs[L].gen = variant ? gens[L] : nullptr;
         LaunchLog log;
-        int e = enqueue_matrices(*bt, s, nullptr);
-        if (!e)
-            e = enqueue_forward(*bt, es, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
-                                bt->d_norms.as<double>(), s, nullptr);
-        if (!e) e = enqueue_adjoint(*bt, es, dp, s, &log);
+        const int e = sweep(s, &log);
         if (e) return fail(QV_E_DEVICE, "timing launch failed: %s", hipGetErrorString((hipError_t)e));
         HIPCHK(hipStreamSynchronize(s));
         for (size_t i = 0; i < log.recs.size(); i++) {
             const qv_launch_rec &r = log.recs[i];
-            if (r.level < 0 || (size_t)r.level >= es.rev.size()) continue;
-            if (r.kernel != QV_K_RTILE_ADJ && r.kernel != QV_K_RTILE_ADJ_GEN) continue;
+            if (r.level < 0 || (size_t)r.level >= lvs.size()) continue;
+            if (r.kernel != k_general && r.kernel != k_gen) continue;
             float f = 0.f;
             HIPCHK(hipEventElapsedTime(&f, log.ev[i].first, log.ev[i].second));
             ms[variant][(size_t)r.level] = std::min(ms[variant][(size_t)r.level], (double)f);
         }
     }
-    for (size_t L = 0; L < es.rev.size(); L++) es.rev[L].gen = (gens[L] && ms[1][L] < ms[0][L]) ? gens[L] : nullptr;
+    for (size_t L = 0; L < lvs.size(); L++) lvs[L].gen = (gens[L] && ms[1][L] < ms[0][L]) ? gens[L] : nullptr;
     bt->fwd_valid = false;
+    return QV_OK;
+}
+
+// The reverse levels of the main execution set, each sweep after its own forward pass.
+static qv_status time_generated_reverse(qv_batch_s *bt, ExecSet &es)
+{
+    const DevPlans &dp = *bt->dp;
+    return time_generated(bt, es, 1, [&](hipStream_t s, LaunchLog *log) {
+        int e = enqueue_matrices(*bt, s, nullptr);
+        if (!e)
+            e = enqueue_forward(*bt, es, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                                bt->d_norms.as<double>(), s, nullptr);
+        if (!e) e = enqueue_adjoint(*bt, es, dp, s, log);
+        return e;
+    });
+}
+
+// The forward levels of the main execution set and of every parameter-shift chunk (kernels generated for
+// them first). A chunk's sweeps write the variants' scratch states and energies, as its real sweep does.
+static qv_status generated_forward(qv_batch_s *bt, bool with_chunks)
+{
+    const DevPlans &dp = *bt->dp;
+    qv_status st = ensure_generated(bt, bt->main, 0);
+    if (st != QV_OK) return st;
+    st = time_generated(bt, bt->main, 0, [&](hipStream_t s, LaunchLog *log) {
+        const int e = enqueue_matrices(*bt, s, nullptr);
+        if (e) return e;
+        return enqueue_forward(*bt, bt->main, dp, bt->d_psi.p, bt->d_energies.as<double>(), bt->d_tv.as<double>(),
+                               bt->d_norms.as<double>(), s, log);
+    });
+    if (st != QV_OK || !with_chunks) return st;
+    for (size_t i = 0; i < bt->ps_chunks.size(); i++) {
+        ExecSet &es = *bt->ps_chunks[i];
+        if ((st = ensure_generated(bt, es, 0)) != QV_OK) return st;
+        st = time_generated(bt, es, 0, [&](hipStream_t s, LaunchLog *log) {
+            const int e = enqueue_matrices(*bt, s, nullptr);
+            if (e) return e;
+            return enqueue_forward(*bt, es, dp, bt->d_ps_psi.p, bt->d_ps_energies.as<double>() + bt->ps_chunk_var0[i],
+                                   bt->d_ps_tv.as<double>(), nullptr, s, log);
+        });
+        if (st != QV_OK) return st;
+    }
     return QV_OK;
 }
 
@@ -1140,7 +1181,7 @@ qv_status qv_ctx_create(int32_t device, void *hip_stream, const char *options_js
         } else if (k == "specialize") {
             if (v == "on" || v == "1" || v == "true") c->specialize = 3;
             else if (v == "adjoint") c->specialize = 2;
-            else if (v == "auto") c->specialize = 2 | kSpecializeTimed;
+            else if (v == "auto") c->specialize = 3 | kSpecializeTimed;
             else if (v == "off" || v == "0" || v == "false") c->specialize = 0;
             else return fail(QV_E_INVALID, "specialize must be \"on\", \"adjoint\", \"auto\" or \"off\"");
         } else if (k == "adjoint_inner") {
@@ -1658,7 +1699,7 @@ static qv_status forward(qv_batch bt)
         if (st != QV_OK) return st;
     }
     DevPlans &dp = *bt->dp;
-    qv_status st = ensure_generated(bt, bt->main, 0);
+    qv_status st = generated_forward(bt, false);
     if (st != QV_OK) return st;
     st = run_graph(bt, bt->g_fwd, [&](hipStream_t s, LaunchLog *log) {
         const int e = enqueue_matrices(*bt, s, log);
@@ -1914,9 +1955,7 @@ qv_status qv_batch_gradient(qv_batch bt, qv_grad_method method, const double *up
         bt->last.algorithmic_bytes = bytes + bt->main.algo_bytes_rev;
     } else {
         if ((st = ensure_param_shift(bt)) != QV_OK) return st;
-        if ((st = ensure_generated(bt, bt->main, 0)) != QV_OK) return st;
-        for (auto &c : bt->ps_chunks)
-            if ((st = ensure_generated(bt, *c, 0)) != QV_OK) return st;
+        if ((st = generated_forward(bt, true)) != QV_OK) return st;
         st = run_graph(bt, bt->g_ps, [&](hipStream_t cs, LaunchLog *log) {
             int e = enqueue_matrices(*bt, cs, log);
             if (e) return e;
@@ -2187,7 +2226,7 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
             bytes += bt->last.algorithmic_bytes;
             launches += bt->last.launches;
         }
-        if ((st = ensure_generated(bt, bt->main, 0)) != QV_OK) return st;
+        if ((st = generated_forward(bt, false)) != QV_OK) return st;
         st = run_graph(bt, bt->g_js_adj, [&](hipStream_t cs, LaunchLog *log) {
             int e = divergence(cs, log);
             if (e) return e;
@@ -2220,9 +2259,7 @@ qv_status qv_batch_js_gradient(qv_batch bt, qv_grad_method method, const double 
             HIPCHK(c->d_diag_fb.upload(c->diag_fb));
             HIPCHK(c->d_diag_part.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, c->diag_fb.back())));
         }
-        if ((st = ensure_generated(bt, bt->main, 0)) != QV_OK) return st;
-        for (auto &c : bt->ps_chunks)
-            if ((st = ensure_generated(bt, *c, 0)) != QV_OK) return st;
+        if ((st = generated_forward(bt, true)) != QV_OK) return st;
         st = run_graph(bt, bt->g_js_ps, [&](hipStream_t cs, LaunchLog *log) {
             int e = enqueue_matrices(*bt, cs, log);
             if (e) return e;

@@ -803,27 +803,6 @@ __device__ __forceinline__ void gen_adj_op(const LevelArgs &a, const DevCirc &C,
     }
 }
 
-// Whether a parameter-shift variant's shifted gate is one of GATES (a fused block's gates), with the
-// shifted index opaque here so that the test is not hoisted out of the tile loops (see gen_fwd_op).
-template <int... GATES>
-__device__ __forceinline__ bool gen_shift_in(const DevCirc &C)
-{
-    int shift = C.shift_gate;
-    asm volatile("" : "+s"(shift));
-    return ((shift == GATES) || ...);
-}
-
-// A fused block of a generated forward program: its 16x16 product on MFMA (complex64). The block's index
-// is opaque here, so that its 16 A-operand loads stay at the block instead of being hoisted, for every
-// block of the program, out of the tile loops (16 live vector registers per block, spilled).
-template <int FIDX>
-__device__ __forceinline__ void gen_fused(const LevelArgs &a, const DevCirc &C, int lane, Regs<float, 16> &v)
-{
-    int f = FIDX;
-    asm volatile("" : "+s"(f));
-    fused_mfma(v, a.fmats + (C.fused_off + f) * (int64_t)kFusedFloats, lane);
-}
-
 template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg>
 __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *smem, int64_t blk, const Seg &sg,
                                            bool preloaded, int64_t next_blk)

@@ -82,8 +82,8 @@ def test_qcl20_generated_vs_general_and_oracle(qv, layers, spec, inner):
         want = {"off": set(), "adjoint": {"rtile_adj_gen"}, "on": {"rtile_gen", "rtile_adj_gen"}}.get(mode)
         if want is not None:
             assert kinds == want, kinds
-        else:   # auto: generated kernels only where they timed faster, and only in the adjoint
-            assert kinds <= {"rtile_adj_gen"}, kinds
+        else:   # auto: generated kernels only in the levels where they timed faster
+            assert kinds <= {"rtile_gen", "rtile_adj_gen"}, kinds
         out[mode] = (e, g)
         b.close()
     ee = check(out[spec][0], gold["energies"], 0, 1.0, "energies")
@@ -124,6 +124,27 @@ def test_c1_generated(qv, prec, opts):
     check(tv, tv_ref, prec, 1.0, "terms")
     check(b.gradient(qv.QV_ADJOINT)[0], g_ref, prec, s, "adjoint grad")
     check(b.gradient(qv.QV_PARAM_SHIFT)[0], g_ref, prec, s, "param-shift grad")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_c1_auto_timed_levels(qv, prec):
+    """"specialize": "auto": the forward levels of the base circuits and of every chunk of parameter-shift
+    variants, and the reverse levels, are each timed with both kinds of kernel on their first call, then keep
+    the faster. Energies, terms and both gradients against the oracle, twice (the second call runs the
+    kernels chosen by the first)."""
+    say(f"c1 auto prec={prec}")
+    wl = W.config1()
+    e_ref, tv_ref, _, _ = oracle.expectations(wl)
+    g_ref = oracle.grad_param_shift(wl)
+    b = qv.Batch(ctx_for(qv, specialize="auto", fusion=2), wl, prec)
+    s = obs_scale(wl)
+    for _ in range(2):
+        e, tv = b.expectations()
+        check(e, e_ref, prec, s, "energies")
+        check(tv, tv_ref, prec, 1.0, "terms")
+        check(b.gradient(qv.QV_PARAM_SHIFT)[0], g_ref, prec, s, "param-shift grad")
+        check(b.gradient(qv.QV_ADJOINT)[0], g_ref, prec, s, "adjoint grad")
+    b.close()
 
 
 @pytest.mark.parametrize("prec", [1, 0])
