@@ -220,11 +220,13 @@ qv_status qv_validate_batch(int32_t n_circuits, const int32_t *n_qubits, const i
                             const int64_t *term_offsets, const uint64_t *xmask, const uint64_t *zmask,
                             const double *coeff, int32_t obs_shared, qv_precision precision);
 
-/* Sets the parameter vector: n_params[0] doubles when shared, else sum of n_params. theta is a host
- * pointer, or a device pointer when theta_on_device is nonzero. Host values are checked to be finite. */
+/* Sets the parameter vector (Section 4.1 and Section 4.2: each iteration of the variational loop runs the
+ * same circuits again with new angles): n_params[0] doubles when shared, else sum of n_params. theta is a
+ * host pointer, or a device pointer when theta_on_device is nonzero. Host values are checked to be finite. */
 qv_status qv_batch_set_params(qv_batch batch, const double *theta, int32_t theta_on_device);
 
-/* Executes every circuit from |0...0> and writes energies[B] (E_b = sum_t c_t <P_t>) and, when
+/* Executes every circuit from |0...0> (Section 3.2: the whole circuit vector on one buffer) and writes
+ * energies[B] (E_b = sum_t c_t <P_t>, Eq. 1) and, when
  * term_values is not NULL, the expectation of every term in term order: for a shared observable
  * B*T values, circuit-major; otherwise sum_b T_b values in the order of the term arrays.
  * The final states stay on the device for a following adjoint gradient. */
@@ -299,10 +301,14 @@ qv_status qv_batch_js_gradient(qv_batch batch, qv_grad_method method, const doub
 qv_status qv_batch_sample(qv_batch batch, int64_t shots, const double *uniforms, int64_t *samples,
                           uint64_t *bitstrings, int64_t *counts, int64_t *n_distinct, int32_t on_device);
 
-/* Copies the final state of circuit b after the last forward pass: 2^n complex numbers, interleaved
- * (re, im), float for QV_C64 and double for QV_C128. */
+/* Copies the final state of circuit b after the last forward pass (the state-vector simulation behind
+ * every result of Section 4): 2^n complex numbers, interleaved (re, im), float for QV_C64 and double for
+ * QV_C128. */
 qv_status qv_batch_state(qv_batch batch, int32_t circuit, void *out, int32_t out_on_device);
 
+/* Counts and timing of the last call (passes, launches, algorithmic bytes, device time: the quantities
+ * behind a timing like those of Section 4), the norm check and the batch's tuned plan parameters, written
+ * to *out. QV_E_INVALID when batch or out is NULL. */
 qv_status qv_batch_stats(qv_batch batch, qv_stats *out);
 
 /* Launch records of the qv_batch_expectations / qv_batch_gradient calls made since the records were

@@ -185,22 +185,24 @@ def test_hea_ladder_generated(qv, n, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-def test_mcvqe_and_ddcl_generated(qv, prec):
+@pytest.mark.parametrize("spec", ["on", "auto"])
+def test_mcvqe_and_ddcl_generated(qv, prec, spec):
     """MC-VQE at 16 qubits (CIS preparation, merged entanglers, 92 terms; adjoint and parameter-shift mean
-    energy gradients) and the DDCL circuit at 12 qubits (Jensen-Shannon gradient by both rules)."""
+    energy gradients) and the DDCL circuit at 12 qubits (Jensen-Shannon gradient by both rules), with
+    generated passes everywhere or where they timed faster (the divergence calls time their own levels)."""
     from oracle import ddcl as OD
-    say(f"mcvqe/ddcl generated prec={prec}")
+    say(f"mcvqe/ddcl generated prec={prec} specialize={spec}")
     wl = W.mcvqe(16)
     up = np.full(wl.B, 1.0 / wl.B)
     g_ref = oracle.grad_adjoint(wl, up)
-    b = qv.Batch(ctx_for(qv, specialize="on"), wl, prec)
+    b = qv.Batch(ctx_for(qv, specialize=spec), wl, prec)
     s = float(np.abs(wl.coeff).sum())
     check(b.gradient(qv.QV_ADJOINT, upstream=up)[0], g_ref, prec, s, "mcvqe adjoint")
     check(b.gradient(qv.QV_PARAM_SHIFT, upstream=up)[0], g_ref, prec, s, "mcvqe param-shift")
     wl2 = W.ddcl(12, 3)
     t = wl2.extra["target"]
     g2 = OD.js_grad_param_shift(wl2, t)
-    b2 = qv.Batch(ctx_for(qv, specialize="on"), wl2, prec)
+    b2 = qv.Batch(ctx_for(qv, specialize=spec), wl2, prec)
     for method in (qv.QV_ADJOINT, qv.QV_PARAM_SHIFT):
         js, g = b2.js_gradient(t, method)
         check(js, OD.js_values(wl2, t), prec, 1.0, "divergence")
