@@ -199,7 +199,7 @@ def timed(fn, stream_sync, reps: int = 1) -> float:
     return (time.time() - t0) / reps
 
 
-def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
+def other_workloads(qvpu, W, stream, sync, only=None, specialize="off", specialize_heavy=None) -> dict:
     """The other workload shapes, each on its own batch (created and freed here): circuit learning with 2
     and 4 layers (adjoint vs parameter-shift gradients/s), the 16-qubit VQE parameter-shift gradient (513
     circuits), 1024 uneven random circuits, MC-VQE-shaped batches at 16-22 qubits (adjoint and
@@ -208,8 +208,17 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
     forward and adjoint, with and without fused MFMA blocks."""
     out = {}
 
+    # DDCL and the 32-qubit circuit have long passes: generating them costs minutes of compilation on a
+    # machine with an empty cache, so the full benchmark can run them with another "specialize" setting
+    heavy = specialize if specialize_heavy is None else specialize_heavy
+    t_start = time.time()
+
+    def done(key):   # progress on stderr while the one JSON line waits
+        print(f"# {key} done at {time.time() - t_start:.0f} s", file=sys.stderr, flush=True)
+
     def ctx(**o):
         o.setdefault("graph", True)
+        o.setdefault("specialize", specialize)
         return qvpu.Context(0, stream.cuda_stream, json.dumps(o))
 
     # circuit learning at 20 qubits with 2 and 4 layers: adjoint gradient vs parameter-shift, same engine
@@ -229,6 +238,7 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                                        "param_shift_gradients_per_s": round(1.0 / s_ps, 4),
                                        "speedup": round(s_ps / s_ad, 1),
                                        "param_shift_circuits": wl.B * (2 * wl.n_grad() + 1)}
+        done(f"qcl20_L{layers}_S64")
         b.close()
     # the benchmark workload in complex128 (FP64 throughout; register tiles of 2^12 amplitudes), with the
     # general tile kernels and with generated adjoint passes where they time faster
@@ -250,6 +260,7 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
             rec["ms" + key] = round(s_ad * 1e3, 3)
             b.close()
         out["qcl20_L8_S64_c128"] = rec
+        done("qcl20_L8_S64_c128")
     # the 16-qubit VQE parameter-shift gradient (513 circuits) and 1024 uneven random circuits, each with
     # one launch per pass level and with every sweep in one persistent launch
     wl = W.config2()
@@ -263,6 +274,7 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
             rec["gradient_ms" + key] = round(s * 1e3, 3)
             b.close()
         out[f"hea16_L8_T100_param_shift_{name}"] = rec
+        done(f"hea16_L8_T100_param_shift_{name}")
     if only in (None, "random1024"):
         wl = W.config4()
         rec = {"circuits": wl.B}
@@ -276,6 +288,7 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                 rec["gate_equivalent"] = gate_equivalent(wl, 8, False, s)
             b.close()
         out["random1024_expectations_c64"] = rec
+        done("random1024_expectations_c64")
     # MC-VQE-shaped batches at Table 1's sizes: one circuit per CIS state, mean-energy gradient
     for nq in ((16, 18, 20, 22) if only in (None, "mcvqe") else ()):
         wl = W.mcvqe(nq)
@@ -289,12 +302,13 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                                         "param_shift_circuits": wl.B * (2 * P + 1),
                                         "param_shift_circuit_evals_per_s": round(wl.B * (2 * P + 1) / s_ps, 1),
                                         "terms": nh, "params": P, "per_state_per_term_circuits": 2 * nh * P}
+        done(f"mcvqe{nq}_S{wl.B}_c64")
         b.close()
     # DDCL-shaped circuits at Table 2's sizes (10 layers, 60 N_q parameters): Jensen-Shannon loss gradient
     for nq in ((20, 22, 24, 26) if only in (None, "ddcl") else ()):
         wl = W.ddcl(nq, 10)
         t = wl.extra["target"]
-        b = qvpu.Batch(ctx(), wl, qvpu.QV_C64)
+        b = qvpu.Batch(ctx(specialize=heavy), wl, qvpu.QV_C64)
         s_ad = timed(lambda: b.js_gradient(t, qvpu.QV_ADJOINT), sync, 3)
         rec = {"adjoint_gradient_ms": round(s_ad * 1e3, 3), "params": wl.n_grad(),
                "param_shift_circuits": 2 * wl.n_grad() + 1}
@@ -315,7 +329,7 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
             sub = W.Workload(wl.name + f"[{K} params]", wl.n_qubits, wl.gate_offsets, g, np.array([K], np.int32),
                              False, wl.theta[:K].copy(), wl.term_offsets, wl.xmask, wl.zmask, wl.coeff, False,
                              dict(wl.extra))
-            b = qvpu.Batch(ctx(), sub, qvpu.QV_C64)
+            b = qvpu.Batch(ctx(specialize=heavy), sub, qvpu.QV_C64)
             s_ps = timed(lambda: b.js_gradient(t, qvpu.QV_PARAM_SHIFT), sync, 1)
             per = s_ps / (2 * K + 1)
             rec["param_shift_gradient_ms"] = round(per * (2 * wl.n_grad() + 1) * 1e3, 1)
@@ -323,9 +337,10 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
             rec["param_shift_measured"] = f"extrapolated: {2 * K + 1} circuits timed ({s_ps * 1e3:.1f} ms)"
             b.close()
         out[f"ddcl{nq}_L10_c64"] = rec
+        done(f"ddcl{nq}_L10_c64")
     wl = W.config5() if only in (None, "hea32") else None
     for fusion in (["off", "8"] if wl is not None else []):
-        b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13), wl, qvpu.QV_C64)
+        b = qvpu.Batch(ctx(fusion=fusion, tile_qubits=13, specialize=heavy), wl, qvpu.QV_C64)
         sf = timed(lambda: b.expectations(), sync, 1)
         sg = timed(lambda: b.gradient(qvpu.QV_ADJOINT), sync, 1)
         st = b.stats()
@@ -333,6 +348,7 @@ def other_workloads(qvpu, W, stream, sync, only=None) -> dict:
                                                   "passes": st["passes_per_circuit_max"],
                                                   "gate_equivalent_forward": gate_equivalent(wl, 8, False, sf),
                                                   "gate_equivalent_gradient": gate_equivalent(wl, 8, True, sg)}
+        done(f"hea32_L10_c64_fusion_{fusion}")
         b.close()
     return out
 
@@ -386,7 +402,8 @@ def main():
             out["copy_ceiling"] = copy_ceiling(torch, st)
             print(json.dumps(out), flush=True)
             return
-        print(json.dumps(other_workloads(qvpu, W, st, torch.cuda.synchronize, args.only)), flush=True)
+        print(json.dumps(other_workloads(qvpu, W, st, torch.cuda.synchronize, args.only, args.specialize)),
+              flush=True)
         return
 
     dev = torch.device("cuda:0")
@@ -558,7 +575,7 @@ def main():
     out.update(extra)
     out["copy_ceiling"] = copy_ceiling(torch, stream)
     if not args.no_extras:
-        out["other_workloads"] = other_workloads(qvpu, W, stream, torch.cuda.synchronize)
+        out["other_workloads"] = other_workloads(qvpu, W, stream, torch.cuda.synchronize, None, args.specialize, "off")
         out["other_workloads"]["stride26_c64"] = stride_profile(qvpu, W, stream, torch.cuda.synchronize, 26)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)

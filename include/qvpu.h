@@ -160,7 +160,8 @@ typedef struct qv_batch_s *qv_batch;
  *                      store addresses instead of running as ops (same results, no arithmetic);
  *   "specialize"     : "off" (default), "adjoint", "on" or "auto": every register-tiled level whose
  *                      circuits all run one plan pass runs a kernel generated for that pass (its ops as
- *                      straight-line code, compiled with hipRTC on the first call that needs it; code
+ *                      straight-line code, compiled with hipRTC on the first call that needs it, by
+ *                      QV_GEN_THREADS threads, default one per host CPU up to 16; code
  *                      objects are kept in the directory named by QV_GEN_CACHE, default
  *                      $HOME/.cache/qvpu_gen), in reverse (adjoint) sweeps only, in both directions, or
  *                      ("auto") in the levels of either direction where it measured faster: the first call

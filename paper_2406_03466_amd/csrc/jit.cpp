@@ -258,7 +258,9 @@ int gen_kernels(const std::vector<std::string> &srcs, std::vector<void *> &fns, 
         if (!read_file(cache_path(keys[i]), code[i])) compile_list.push_back(i);
     if (!compile_list.empty()) {
         const char *env = getenv("QV_GEN_THREADS");
-        size_t nthreads = env ? (size_t)std::max(1, atoi(env)) : 8;
+        // default: one compiler thread per host CPU, at most 16
+        const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+        size_t nthreads = env ? (size_t)std::max(1, atoi(env)) : std::min<size_t>(hw, 16);
         nthreads = std::min(nthreads, compile_list.size());
         std::vector<std::thread> pool;
         std::mutex next_mu;
