@@ -297,6 +297,18 @@ __device__ __forceinline__ void r_diag(Regs<R, N> &v, R d0r, R d0i, R d1r, R d1i
     }
 }
 
+// diag(1, r) on register bit K: only the amplitudes whose bit K is set change.
+template <int K, int N, typename R>
+__device__ __forceinline__ void r_phase1(Regs<R, N> &v, R rr, R ri)
+{
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        if (!(j & (1 << K))) continue;
+        const Cx<R> x = v.get(j);
+        v.set(j, rr * x.re - ri * x.im, rr * x.im + ri * x.re);
+    }
+}
+
 template <int N, typename R>
 __device__ __forceinline__ void t_scale(Regs<R, N> &v, R dr, R di)
 {
@@ -422,14 +434,18 @@ __device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s,
     r_real<K>(l, c, s);
 }
 
+// The inverse diagonal op diag(d0, d1) (unit modulus) is applied as d0 diag(1, conj(d0) d1) with the factor
+// d0 left out: psi and lambda then carry the same extra phase, which leaves every later Im <l| G |a>
+// unchanged, and only half the amplitudes are multiplied. The reverse sweep's final states are not results.
 template <int K, int N, typename R>
 __device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, R d0r, R d0i, R d1r, R d1i, bool train,
                                          double &ip)
 {
     // of the diagonal kinds only RZ carries a parameter
     if (train) ip = r_inner<K, QV_RZ>(a, l);
-    r_diag<K>(a, d0r, d0i, d1r, d1i);
-    r_diag<K>(l, d0r, d0i, d1r, d1i);
+    const R rr = d0r * d1r + d0i * d1i, ri = d0r * d1i - d0i * d1r;
+    r_phase1<K>(a, rr, ri);
+    r_phase1<K>(l, rr, ri);
 }
 
 template <int K, int N, typename R>
