@@ -409,6 +409,24 @@ __device__ __forceinline__ double r_inner(const Regs<R, N> &a, const Regs<R, N> 
     return (double)acc[0] + (double)acc[1];
 }
 
+// Im <l| Z_K |a> for register bit K from the amplitudes with bit K set alone: -2 sum Im conj(l1) a1. Over a
+// whole state Im <l|a> = 0 (the seed is a Hermitian observable or a real diagonal applied to psi, and the
+// sweep applies one unitary to both), so the bit-0 half sums to minus the bit-1 half. Exact for the total
+// over all tiles of a circuit, which is what the gradient takes.
+template <int K, int N, typename R>
+__device__ __forceinline__ double r_inner_z1(const Regs<R, N> &a, const Regs<R, N> &l)
+{
+    typedef typename InnerAcc<R>::type A;
+    A acc[2] = {(A)0, (A)0};
+#pragma unroll
+    for (int j = 0, n = 0; j < N; j++) {
+        if (!(j & (1 << K))) continue;
+        const Cx<R> x = a.get(j), y = l.get(j);
+        acc[n++ & 1] += (A)y.re * (A)x.im - (A)y.im * (A)x.re;
+    }
+    return -2.0 * ((double)acc[0] + (double)acc[1]);
+}
+
 // Im <l| Z_p |a> when qubit p is a thread bit with value `bit`.
 template <int N, typename R>
 __device__ __forceinline__ double t_inner_z(const Regs<R, N> &a, const Regs<R, N> &l, int bit)
@@ -442,7 +460,7 @@ __device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, R d0r, R 
                                          double &ip)
 {
     // of the diagonal kinds only RZ carries a parameter
-    if (train) ip = r_inner<K, QV_RZ>(a, l);
+    if (train) ip = r_inner_z1<K>(a, l);
     const R rr = d0r * d1r + d0i * d1i, ri = d0r * d1i - d0i * d1r;
     r_phase1<K>(a, rr, ri);
     r_phase1<K>(l, rr, ri);
