@@ -228,6 +228,18 @@ struct ShiftMatArgs {
     int64_t n_circ;
 };
 
+// One circuit's final state made textbook: the kernels build RZ(a) as e^{ia/2} RZ(a), so the state is
+// multiplied by exp(-i/2 sum of the circuit's RZ angles) on its way out.
+struct StatePhaseArgs {
+    const qv_gate *gates;   // the circuit's gate records
+    const double *theta;    // the circuit's parameters (gate.param indexes them)
+    int64_t n_gates;
+    const void *src;        // amplitudes to copy (a range of the circuit's state)
+    void *dst;              // device destination of the scaled copy
+    int64_t n_amps;
+    double *phase;          // two doubles of device memory: cos and sin of the restoring phase
+};
+
 struct ExpArgs {
     const DevGroup *groups;
     int32_t n_groups;
@@ -377,6 +389,8 @@ int launch_segment_sum(const SegSumArgs &a, void *stream);
 int launch_fill(double *p, int64_t n, double v, void *stream);
 int launch_matrices(const MatArgs &a, int precision, void *stream);
 int launch_shift_matrices(const ShiftMatArgs &a, int precision, void *stream);
+int launch_rz_phase(const StatePhaseArgs &a, void *stream);            // writes a.phase
+int launch_scale_copy(const StatePhaseArgs &a, int precision, void *stream);  // dst = phase * src
 
 // Fused 4-qubit blocks: for every circuit and block, the product of the block's gates (16x16 complex),
 // written as the 32x32 real matrix [[Re, -Im], [Im, Re]] interleaved per amplitude, in MFMA A order.

@@ -539,6 +539,42 @@ __global__ __launch_bounds__(kBlock) void k_shift_matrices(ShiftMatArgs a)
     reinterpret_cast<M2<R> *>(a.smats)[i] = narrow<R>(md);
 }
 
+// The restoring phase of one circuit's state (one workgroup): exp(-i/2 sum of its RZ angles), each angle
+// taken modulo 4 pi first (the period of e^{-ia/2}).
+__global__ __launch_bounds__(kBlock) void k_rz_phase(StatePhaseArgs a)
+{
+    __shared__ double red[kBlock / 64];
+    const double period = 4.0 * 3.14159265358979323846;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < a.n_gates; i += kBlock) {
+        const qv_gate g = a.gates[i];
+        if (g.kind == QV_RZ) acc += fmod(g.param >= 0 ? a.theta[g.param] : g.angle, period);
+    }
+    const double sum = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        double sn, cs;
+        sincos(-0.5 * sum, &sn, &cs);
+        a.phase[0] = cs;
+        a.phase[1] = sn;
+    }
+}
+
+// dst = phase * src over a range of one circuit's amplitudes (grid-stride).
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_scale_copy(StatePhaseArgs a)
+{
+    const R c = (R)a.phase[0], s = (R)a.phase[1];
+    const Cx<R> *src = reinterpret_cast<const Cx<R> *>(a.src);
+    Cx<R> *dst = reinterpret_cast<Cx<R> *>(a.dst);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n_amps; i += (int64_t)gridDim.x * kBlock) {
+        const Cx<R> x = src[i];
+        Cx<R> y;
+        y.re = c * x.re - s * x.im;
+        y.im = c * x.im + s * x.re;
+        dst[i] = y;
+    }
+}
+
 // Fused-block matrices: one workgroup per (circuit, block) multiplies the block's gates into a 16x16
 // complex matrix in LDS (thread (r, c) owns entry r, c; each gate acts on the rows of its register bits),
 // then writes the 32x32 real form in the order fused_mfma reads it: entry s*64 + l is A[l % 32][2s + l / 32].
@@ -1471,6 +1507,22 @@ int launch_matrices(const MatArgs &a, int precision, void *stream)
     const dim3 grid((unsigned)((a.n_gates + kBlock - 1) / kBlock));
     if (precision == QV_C64) hipLaunchKernelGGL((k_matrices<float>), grid, dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL((k_matrices<double>), grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+int launch_rz_phase(const StatePhaseArgs &a, void *stream)
+{
+    hipLaunchKernelGGL(k_rz_phase, dim3(1), dim3(kBlock), 0, reinterpret_cast<hipStream_t>(stream), a);
+    return hipGetLastError();
+}
+
+int launch_scale_copy(const StatePhaseArgs &a, int precision, void *stream)
+{
+    if (a.n_amps <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t blocks = std::min<int64_t>((a.n_amps + kBlock - 1) / kBlock, (int64_t)device_cus() * 16);
+    if (precision == QV_C64) hipLaunchKernelGGL((k_scale_copy<float>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_scale_copy<double>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

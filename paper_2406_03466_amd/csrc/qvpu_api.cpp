@@ -203,22 +203,23 @@ struct Level {
 
 // Algorithmic flops per amplitude of a gate, by what the gate's matrix needs, averaged over the two
 // amplitudes of a pair: RX and RY mix a pair with real weights (two real-times-complex products and one
-// complex add per output, 6); RZ multiplies both amplitudes by a phase (one complex multiply, 6); T
-// multiplies one of the two (3); H adds and subtracts the pair and scales by a real (4); X, Y, Z, S, CNOT
-// and CZ only move amplitudes or flip signs (0). Fused-block markers add nothing (their gates are counted).
+// complex add per output, 6); RZ (built as diag(1, e^{ia})) and T multiply one of the two by a phase (3);
+// H adds and subtracts the pair and scales by a real (4); X, Y, Z, S, CNOT and CZ only move amplitudes or
+// flip signs (0). Fused-block markers add nothing (their gates are counted).
 static double op_flops(int kind)
 {
     switch (kind) {
-    case QV_RX: case QV_RY: case QV_RZ: return 6.0;
+    case QV_RX: case QV_RY: return 6.0;
     case QV_H: return 4.0;
-    case QV_T: return 3.0;
+    case QV_RZ: case QV_T: return 3.0;
     default: return 0.0;
     }
 }
 
-// Per amplitude: forward applies each gate once; the adjoint un-applies it from psi and lambda and takes
-// the imaginary part of one complex product per trainable gate (4). The adjoint's sweep over a circuit's
-// first register-tiled pass (last_rev) stops at its first trainable gate, so the gates below it count nothing.
+// Per amplitude: forward applies each gate once; the adjoint un-applies it from psi and lambda and, per
+// trainable gate, takes the imaginary part of one complex product per amplitude (4), or for RZ of the
+// amplitudes with the gate's bit set only (2). The adjoint's sweep over a circuit's first register-tiled
+// pass (last_rev) stops at its first trainable gate, so the gates below it count nothing.
 static double pass_flops(const PlanPass &pp, bool adjoint, bool last_rev = false)
 {
     size_t from = 0;
@@ -227,9 +228,13 @@ static double pass_flops(const PlanPass &pp, bool adjoint, bool last_rev = false
         for (size_t i = 0; i < pp.ops.size(); i++)
             if (pp.ops[i].kind != kFusedKind && pp.ops[i].train_slot >= 0) { from = i; break; }
     }
-    double f = 0.0;
-    for (size_t i = from; i < pp.ops.size(); i++) f += op_flops(pp.ops[i].kind);
-    return adjoint ? 2.0 * f + 4.0 * pp.n_train : f;
+    double f = 0.0, inner = 0.0;
+    for (size_t i = from; i < pp.ops.size(); i++) {
+        f += op_flops(pp.ops[i].kind);
+        if (adjoint && pp.ops[i].kind != kFusedKind && pp.ops[i].train_slot >= 0)
+            inner += pp.ops[i].kind == QV_RZ ? 2.0 : 4.0;
+    }
+    return adjoint ? 2.0 * f + inner : f;
 }
 
 static int pass_kind(const PlanPass &pp)
@@ -379,6 +384,7 @@ struct qv_batch_s {
     bool ps_ready = false;
 
     DBuf d_gates, d_theta, d_psi, d_lam, d_energies, d_tv, d_norms, d_grad, d_upstream;
+    DBuf d_state_phase, d_state_stage;  // qv_batch_state: the restoring phase; staging for host outputs
     DBuf d_gate_circ, d_mats;   // circuit of each matrix-table entry; 2x2 matrix of each circuit's plan ops
     DBuf d_fmats, d_fuse_fb;    // fused-block matrices; per-circuit block prefix for k_fuse
     int64_t n_mats = 0, n_fused = 0;
@@ -2334,10 +2340,40 @@ qv_status qv_batch_state(qv_batch bt, int32_t circuit, void *out, int32_t out_on
     if (!bt->fwd_valid) return fail(QV_E_STATE, "no forward state: call qv_batch_expectations first");
     HIPCHK(enter_device(bt->ctx->device));
     const DevCirc &c = bt->main.circs[circuit];
-    const size_t bytes = ((size_t)1 << c.n) * bt->amp_bytes;
-    HIPCHK(hipMemcpyAsync(out, (char *)bt->d_psi.p + (size_t)c.state_off * bt->amp_bytes, bytes,
-                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, bt->ctx->stream()));
-    if (!out_on_device) HIPCHK(hipStreamSynchronize(bt->ctx->stream()));
+    hipStream_t s = bt->ctx->stream();
+    // the kernels' states lack the phase exp(-i/2 sum of RZ angles) (gate_matrix builds RZ as diag(1, e^{ia})):
+    // copied out through a kernel that multiplies it back, in chunks through a staging buffer for host outputs
+    if (!bt->d_state_phase.p) HIPCHK(bt->d_state_phase.alloc(2 * sizeof(double)));
+    StatePhaseArgs pa;
+    pa.gates = bt->d_gates.as<qv_gate>() + c.gate_off;
+    pa.theta = bt->d_theta.as<double>() + c.param_base;
+    pa.n_gates = bt->goff[(size_t)circuit + 1] - bt->goff[(size_t)circuit];
+    pa.phase = bt->d_state_phase.as<double>();
+    int e = launch_rz_phase(pa, s);
+    if (e) return fail(QV_E_DEVICE, "phase launch failed: %s", hipGetErrorString((hipError_t)e));
+    const int64_t n_amps = (int64_t)1 << c.n;
+    const char *src = (const char *)bt->d_psi.p + (size_t)c.state_off * bt->amp_bytes;
+    if (out_on_device) {
+        pa.src = src;
+        pa.dst = out;
+        pa.n_amps = n_amps;
+        e = launch_scale_copy(pa, bt->prec, s);
+        if (e) return fail(QV_E_DEVICE, "state copy failed: %s", hipGetErrorString((hipError_t)e));
+        return ok();
+    }
+    const int64_t chunk = std::min<int64_t>(n_amps, ((int64_t)64 << 20) / bt->amp_bytes);
+    if (bt->d_state_stage.bytes < (size_t)(chunk * bt->amp_bytes))
+        HIPCHK(bt->d_state_stage.alloc((size_t)(chunk * bt->amp_bytes)));
+    for (int64_t i = 0; i < n_amps; i += chunk) {
+        pa.src = src + (size_t)i * bt->amp_bytes;
+        pa.dst = bt->d_state_stage.p;
+        pa.n_amps = std::min(chunk, n_amps - i);
+        e = launch_scale_copy(pa, bt->prec, s);
+        if (e) return fail(QV_E_DEVICE, "state copy failed: %s", hipGetErrorString((hipError_t)e));
+        HIPCHK(hipMemcpyAsync((char *)out + (size_t)i * bt->amp_bytes, bt->d_state_stage.p,
+                              (size_t)pa.n_amps * bt->amp_bytes, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
     return ok();
 }
 

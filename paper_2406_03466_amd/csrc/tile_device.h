@@ -42,12 +42,17 @@ __device__ __forceinline__ uint64_t deposit(uint64_t v, uint64_t mask)
 
 __device__ __forceinline__ int parity64(uint64_t v) { return __popcll(v) & 1; }
 
-// Matrix of a one-qubit gate (textbook definitions; rotations are exp(-i a sigma / 2)).
+// Matrix of a one-qubit gate: textbook definitions (rotations are exp(-i a sigma / 2)), except RZ, built as
+// diag(1, e^{ia}) = e^{ia/2} RZ(a). Every diagonal kind then has 1 as its first entry, so a diagonal op
+// multiplies only the amplitudes whose bit is set. A circuit's final state differs from the textbook one by
+// the factor e^{ia/2} of each of its RZ gates; every result but the state itself is independent of a global
+// phase, and the state is multiplied by the inverse product before it is handed out (k_scale_state).
 __device__ inline void gate_matrix(int kind, double a, M2d &m)
 {
     for (int k = 0; k < 4; k++) { m.re[k] = 0.0; m.im[k] = 0.0; }
     double s, c;
     sincos(0.5 * a, &s, &c);
+    if (kind == QV_RZ) sincos(a, &s, &c);
     const double r = 0.70710678118654752440;
     switch (kind) {
     case QV_H: m.re[0] = r; m.re[1] = r; m.re[2] = r; m.re[3] = -r; break;
@@ -58,7 +63,7 @@ __device__ inline void gate_matrix(int kind, double a, M2d &m)
     case QV_T: m.re[0] = 1; m.re[3] = r; m.im[3] = r; break;
     case QV_RX: m.re[0] = c; m.im[1] = -s; m.im[2] = -s; m.re[3] = c; break;
     case QV_RY: m.re[0] = c; m.re[1] = -s; m.re[2] = s; m.re[3] = c; break;
-    case QV_RZ: m.re[0] = c; m.im[0] = -s; m.re[3] = c; m.im[3] = s; break;
+    case QV_RZ: m.re[0] = 1; m.re[3] = c; m.im[3] = s; break;
     default: m.re[0] = 1; m.re[3] = 1; break;
     }
 }
@@ -285,18 +290,6 @@ __device__ __forceinline__ void r_gen(Regs<R, N> &v, const M2<R> &m)
     }
 }
 
-// diag(d0, d1) on register bit K.
-template <int K, int N, typename R>
-__device__ __forceinline__ void r_diag(Regs<R, N> &v, R d0r, R d0i, R d1r, R d1i)
-{
-#pragma unroll
-    for (int j = 0; j < N; j++) {
-        const R dr = (j & (1 << K)) ? d1r : d0r, di = (j & (1 << K)) ? d1i : d0i;
-        const Cx<R> x = v.get(j);
-        v.set(j, dr * x.re - di * x.im, dr * x.im + di * x.re);
-    }
-}
-
 // diag(1, r) on register bit K: only the amplitudes whose bit K is set change.
 template <int K, int N, typename R>
 __device__ __forceinline__ void r_phase1(Regs<R, N> &v, R rr, R ri)
@@ -452,18 +445,15 @@ __device__ __forceinline__ void adj_real(Regs<R, N> &a, Regs<R, N> &l, R c, R s,
     r_real<K>(l, c, s);
 }
 
-// The inverse diagonal op diag(d0, d1) (unit modulus) is applied as d0 diag(1, conj(d0) d1) with the factor
-// d0 left out: psi and lambda then carry the same extra phase, which leaves every later Im <l| G |a>
-// unchanged, and only half the amplitudes are multiplied. The reverse sweep's final states are not results.
+// The inverse of a diagonal op diag(1, d1) (gate_matrix's form of every diagonal kind) on psi and lambda:
+// only the amplitudes whose bit K is set change.
 template <int K, int N, typename R>
-__device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, R d0r, R d0i, R d1r, R d1i, bool train,
-                                         double &ip)
+__device__ __forceinline__ void adj_diag(Regs<R, N> &a, Regs<R, N> &l, R d1r, R d1i, bool train, double &ip)
 {
     // of the diagonal kinds only RZ carries a parameter
     if (train) ip = r_inner_z1<K>(a, l);
-    const R rr = d0r * d1r + d0i * d1i, ri = d0r * d1i - d0i * d1r;
-    r_phase1<K>(a, rr, ri);
-    r_phase1<K>(l, rr, ri);
+    r_phase1<K>(a, d1r, d1i);
+    r_phase1<K>(l, d1r, d1i);
 }
 
 template <int K, int N, typename R>
@@ -503,7 +493,7 @@ __device__ __forceinline__ void code_apply(Regs<R, 1 << RB> &v, int code, const 
     const R d0i = INV ? -mat.im[0] : mat.im[0], d1i = INV ? -mat.im[3] : mat.im[3];
     switch (code) {
     K4_CASES(OC_RY, (r_real<K>(v, cr, sr)))
-    K4_CASES(OC_DIAG, (r_diag<K>(v, d0r, d0i, d1r, d1i)))
+    K4_CASES(OC_DIAG, (r_phase1<K>(v, d1r, d1i)))   // diagonal kinds are diag(1, d1) (gate_matrix)
     case OC_DIAG_T: {
         const bool b = (Et >> op.p0) & 1u;
         t_scale(v, b ? d1r : d0r, b ? d1i : d0i);
@@ -532,7 +522,7 @@ __device__ __forceinline__ double code_adjoint(Regs<R, 1 << RB> &a, Regs<R, 1 <<
     const R d0r = mat.re[0], d1r = mat.re[3], d0i = -mat.im[0], d1i = -mat.im[3];
     switch (code) {
     K4_CASES(OC_RY, (adj_real<K>(a, l, cr, sr, train, ip)))
-    K4_CASES(OC_DIAG, (adj_diag<K>(a, l, d0r, d0i, d1r, d1i, train, ip)))
+    K4_CASES(OC_DIAG, (adj_diag<K>(a, l, d1r, d1i, train, ip)))
     case OC_DIAG_T: {
         const bool b = (Et >> op.p0) & 1u;
         if (train) ip = t_inner_z(a, l, (int)b);
