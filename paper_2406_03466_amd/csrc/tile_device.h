@@ -863,7 +863,25 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
     // needed): only the last nseg segments run, the lowest of them only down to that op.
     const bool stop_early = ADJ && sg.last;
     const int nseg = stop_early ? P.adj_last_nseg : P.n_seg;
-    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && T >= (uint32_t)APP && nseg > 0;
+    // A circuit's first pass starts from |0...0> and its gates act on the tile's qubits only, so a tile with
+    // a qubit outside the tile set at 1 (base != 0) holds zeros throughout that pass. The forward stores
+    // zeros for it; in the adjoint's sweep over that pass psi is zero there, so each of its inner products
+    // is zero and psi and lambda are not needed afterwards: the tile only clears its partial sums. Only the
+    // circuit's tile 0 then runs the pass, and it prefetches nothing (every later tile is such a tile).
+    if (base != 0 && (stop_early || (!ADJ && sg.first))) {
+        if (ADJ) {
+            for (int slot = threadIdx.x; slot < P.n_train; slot += NT) a.partials[sg.partial_base + tile * P.n_train + slot] = 0.0;
+            return false;
+        }
+        for (uint32_t h = threadIdx.x; h < nh; h += NT) segtab[h] = deposit(h, himask);
+        __syncthreads();
+        Cx<R> z;
+        z.re = (R)0;
+        z.im = (R)0;
+        for (uint32_t e = threadIdx.x; e < T; e += NT) gpsi[base | segtab[e >> lowc] | (e & lmask)] = z;
+        return false;
+    }
+    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && !stop_early && T >= (uint32_t)APP && nseg > 0;
 
     if (preloaded) {
         // this tile was loaded by the previous tile's last segment (same pass: the run table is in place)
