@@ -1142,12 +1142,29 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
 template <bool ADJ>
 constexpr int tile_chunk() { return ADJ ? 8 : 4; }
 
+// The chunk a workgroup takes when the grid has one workgroup per chunk. The GPU deals workgroups to its 8
+// XCDs in turn (workgroup b to XCD b mod 8), so chunk b would put every 8th chunk on one XCD: a level whose
+// work is concentrated in every 16th or 32nd chunk (a circuit's first pass, where only each circuit's tile
+// 0 runs) would run on one XCD. Instead each XCD takes one contiguous range of the chunks (a bijection of
+// [0, n)), which spreads such patterns over all eight. Evenly loaded levels keep chunk b (measured 1-4 %
+// faster in that order).
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t n)
+{
+    constexpr int64_t X = 8;
+    const int64_t q = n / X, r = n % X, x = b % X, i = b / X;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg>
 __device__ __forceinline__ void rtile_tiles(const LevelArgs &a, unsigned char *smem)
 {
     const int64_t ch = a.chunk;
     const int64_t nchunks = (a.n_blocks + ch - 1) / ch;
-    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    // a level of circuits' first passes (judged by its first segment) has its work in each circuit's tile 0
+    const Seg s0 = a.segs[0];
+    const bool spread = (int64_t)gridDim.x == nchunks && (ADJ ? s0.last : s0.first) != 0;
+    for (int64_t c0 = blockIdx.x; c0 < nchunks; c0 += gridDim.x) {
+        const int64_t c = spread ? xcd_chunk(c0, nchunks) : c0;
         const int64_t b0 = c * ch, b1 = b0 + ch < a.n_blocks ? b0 + ch : a.n_blocks;
         bool pre = false;
         for (int64_t blk = b0; blk < b1; blk++) {
