@@ -96,6 +96,9 @@ struct DevPass {
     // counted from the pass's end, that hold it or later ops (0: the pass has no trainable op).
     int32_t first_train;
     int32_t adj_last_nseg;
+    // Qubits outside the tile that no earlier pass of the circuit touches: they are still |0>, so a tile with
+    // one of them at 1 holds zeros throughout the pass.
+    uint64_t zero_mask;
 };
 
 struct DevCirc {

@@ -351,11 +351,33 @@ Plan plan_stride(const PlanInput &in)
     return pl;
 }
 
+std::vector<uint64_t> pass_zero_masks(const Plan &pl)
+{
+    std::vector<uint64_t> out;
+    uint64_t touched = 0;  // qubits acted on by the passes before this one
+    auto touch = [&](const PlanOp &op) {
+        if (op.kind == kFusedKind) return;
+        touched |= 1ull << op.q0;
+        if (op.q1 >= 0) touched |= 1ull << op.q1;
+    };
+    for (const PlanPass &pp : pl.passes) {
+        out.push_back(~pp.local_mask & ~touched);  // bits at or above the circuit's width never occur in a base
+        for (const PlanOp &op : pp.ops) touch(op);
+        for (const PlanSeg &sg : pp.segs) {
+            for (const PlanOp &op : sg.lead) touch(op);
+            for (const PlanOp &op : sg.trail) touch(op);
+        }
+    }
+    return out;
+}
+
 void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops, std::vector<DevSeg> &segs)
 {
+    const std::vector<uint64_t> zero = pass_zero_masks(pl);
     for (const PlanPass &pp : pl.passes) {
         DevPass d{};
         d.local_mask = pp.local_mask;
+        d.zero_mask = zero[(size_t)(&pp - pl.passes.data())];
         d.t = pp.t;
         d.op_begin = (int32_t)ops.size();
         d.n_ops = (int32_t)pp.ops.size();

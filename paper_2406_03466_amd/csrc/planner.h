@@ -88,6 +88,10 @@ int fused_blocks(const Plan &pl);
 // One stride pass per gate.
 Plan plan_stride(const PlanInput &in);
 
+// Per pass: the qubits outside its tile that no earlier pass touches (folded CNOTs included). They are still
+// |0> when the pass runs, so a tile with one of them at 1 holds zeros throughout it.
+std::vector<uint64_t> pass_zero_masks(const Plan &pl);
+
 // Appends a plan's passes and ops in device form.
 void lower_plan(const Plan &pl, std::vector<DevPass> &passes, std::vector<DevOp> &ops,
                 std::vector<DevSeg> &segs);

@@ -480,6 +480,18 @@ static int64_t tiles_of(const DevCirc &c, const Plan &pl, int p)
     return (int64_t)1 << (c.n - pp.t);
 }
 
+// Tiles a forward launch runs for pass p of circuit c. A register-tiled pass after the circuit's first
+// leaves out the tiles with a qubit of its zero mask at 1: they hold the zeros earlier passes wrote
+// (rtile_body numbers the rest first). zero: pass_zero_masks of the circuit's plan.
+static int64_t fwd_tiles(const DevCirc &c, const Plan &pl, int p, const std::vector<uint64_t> &zero)
+{
+    const PlanPass &pp = pl.passes[p];
+    if (p == 0 || pass_kind(pp) != LK_RTILE) return tiles_of(c, pl, p);
+    const uint64_t full = c.n >= 64 ? ~0ull : ((1ull << c.n) - 1ull);
+    const uint64_t outside = full & ~pp.local_mask;
+    return (int64_t)1 << __builtin_popcountll(outside & ~zero[(size_t)p]);
+}
+
 // Builds the launch levels (forward and reverse) and the adjoint partial-sum layout of a set.
 // Circuits are launched in waves of at most `wave` circuits; every wave runs all its levels before the
 // next wave starts. Results do not depend on the wave size.
@@ -493,17 +505,22 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
     es.algo_bytes_fwd = es.algo_bytes_rev = es.passes_fwd = es.passes_rev = 0;
     const int N = es.n_circ;
     if (wave <= 0 || wave > N) wave = N;
+    // zero masks per plan
+    std::vector<std::vector<uint64_t>> zero(plans.size());
+    for (size_t i = 0; i < plans.size(); i++) zero[i] = pass_zero_masks(plans[i]);
     // partial bases per (circuit, pass)
     std::vector<std::vector<int64_t>> pbase(N);
     for (int c = 0; c < N; c++) {
         const Plan &pl = plans[es.plan_of[c]];
         pbase[c].resize(pl.passes.size());
+        const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
         for (size_t p = 0; p < pl.passes.size(); p++) {
             pbase[c][p] = es.partial_count;
             es.partial_count += tiles_of(es.circs[c], pl, (int)p) * pl.passes[p].n_train;
+            // the tiles a forward pass leaves out are neither read nor written
+            es.algo_bytes_fwd += 2 * S / tiles_of(es.circs[c], pl, (int)p) *
+                                 fwd_tiles(es.circs[c], pl, (int)p, zero[(size_t)es.plan_of[c]]);
         }
-        const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
-        es.algo_bytes_fwd += 2 * S * (int64_t)pl.passes.size();
         es.algo_bytes_rev += 4 * S * (int64_t)pl.passes.size();
         es.passes_fwd += (int64_t)pl.passes.size();
         es.passes_rev += (int64_t)pl.passes.size();
@@ -533,22 +550,31 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         s.first = (dir == 0 && p == 0 && !pp.stride) ? 1 : 0;
                         s.last = (dir == 1 && p == 0) ? 1 : 0;
                         s.wait = 0;
+                        const std::vector<uint64_t> &zm = zero[(size_t)es.plan_of[c]];
                         if (dir == 0) {
-                            for (int q = 0; q < p; q++) s.wait += tiles_of(es.circs[c], pl, q);
+                            for (int q = 0; q < p; q++) s.wait += fwd_tiles(es.circs[c], pl, q, zm);
                         } else {
                             for (int q = p + 1; q < np; q++) s.wait += tiles_of(es.circs[c], pl, q);
                         }
                         es.segs.push_back(s);
                         lv.n_segs++;
-                        lv.n_blocks += tiles_of(es.circs[c], pl, p);
+                        const int64_t all = tiles_of(es.circs[c], pl, p);
+                        const int64_t run = dir == 0 ? fwd_tiles(es.circs[c], pl, p, zm) : all;
+                        lv.n_blocks += run;
                         lv.lds_t = std::max(lv.lds_t, pp.t);
                         lv.max_train = std::max(lv.max_train, pp.n_train);
                         lv.tab_bits = std::max(lv.tab_bits, pp.t - pp.lowc);
                         // forward: read + write (first pass: write only); adjoint: psi and lambda read + write
-                        // (the circuit's last reverse pass: read only)
+                        // (the circuit's last reverse pass: read only). Register-tiled first passes compute
+                        // only tile 0 (rtile_body): the forward writes the other tiles' zeros, the adjoint
+                        // leaves them alone.
                         const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
-                        lv.bytes += (dir == 0 ? (s.first ? 1 : 2) : (s.last ? 2 : 4)) * S;
-                        lv.flops += pass_flops(pp, dir == 1, s.last != 0) * (double)((int64_t)1 << es.circs[c].n);
+                        const bool rt = pass_kind(pp) == LK_RTILE;
+                        const int64_t work = (rt && p == 0) ? 1 : run;
+                        lv.bytes += dir == 0 ? (s.first ? S : 2 * (S / all) * run)
+                                             : (s.last ? 2 * (S / all) * work : 4 * S);
+                        lv.flops += pass_flops(pp, dir == 1, s.last != 0) * (double)((int64_t)1 << es.circs[c].n) *
+                                    ((double)work / (double)all);
                     }
                     if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
                 }

@@ -846,7 +846,18 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
     double *red = reinterpret_cast<double *>(segtab + (1 << a.tab_bits));
 
     const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
-    const uint64_t base = deposit((uint64_t)tile, full & ~P.local_mask);
+    // Forward passes after a circuit's first: a tile with a qubit of zero_mask at 1 holds zeros, which the
+    // earlier passes wrote there (a gate acting on zeros leaves exact zeros), so it is left alone. The
+    // circuit's tiles are numbered with those last: tile i < 2^live has base deposit(i, outside & ~zero_mask)
+    // and the rest do nothing, which keeps a level's working tiles contiguous.
+    const uint64_t outside = full & ~P.local_mask;
+    const uint64_t zm = (!ADJ && !sg.first) ? (P.zero_mask & outside) : 0ull;
+    const int live = __popcll(outside & ~zm);
+    if (zm != 0 && (tile >> live) != 0) {
+        if (preloaded) __builtin_amdgcn_s_waitcnt(0);  // never the case: no tile prefetches such a tile
+        return false;
+    }
+    const uint64_t base = deposit((uint64_t)tile, outside & ~zm);
     const uint64_t himask = P.local_mask & ~((1ull << lowc) - 1ull);
     const uint32_t nh = 1u << (t - lowc);
     const uint32_t lmask = (1u << lowc) - 1u;
@@ -881,7 +892,8 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
         for (uint32_t e = threadIdx.x; e < T; e += NT) gpsi[base | segtab[e >> lowc] | (e & lmask)] = z;
         return false;
     }
-    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && !stop_early && T >= (uint32_t)APP && nseg > 0;
+    const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && !stop_early && T >= (uint32_t)APP && nseg > 0 &&
+                    !(zm != 0 && ((next_blk - sg.first_block) >> live) != 0);
 
     if (preloaded) {
         // this tile was loaded by the previous tile's last segment (same pass: the run table is in place)
@@ -973,7 +985,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
         if (remap && !(pf && last_seg)) __syncthreads();
         if (pf && last_seg) {
             __syncthreads();  // every wave has its registers: LDS may be overwritten
-            const uint64_t nbase = deposit((uint64_t)(next_blk - sg.first_block), full & ~P.local_mask);
+            const uint64_t nbase = deposit((uint64_t)(next_blk - sg.first_block), outside & ~zm);
             for (uint32_t c = (uint32_t)wave; c < T / APP; c += NT / 64) {
                 // load c covers LDS positions [c*APP, (c+1)*APP); position q holds element swz(q)
                 if constexpr (sizeof(R) == 4) {
