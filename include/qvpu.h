@@ -113,7 +113,8 @@ typedef enum {
     QV_K_SEGMENT_SUM = 19,       /* per-circuit sums of partials in a fixed order */
     QV_K_SAMPLE = 20,            /* shots from the output distributions and their bit-string counts */
     QV_K_RTILE_GEN = 21,         /* register-tiled pass, forward, kernel generated for the pass */
-    QV_K_RTILE_ADJ_GEN = 22      /* register-tiled pass, adjoint, kernel generated for the pass */
+    QV_K_RTILE_ADJ_GEN = 22,     /* register-tiled pass, adjoint, kernel generated for the pass */
+    QV_K_RTILE_LAM = 23          /* register-tiled pass, adjoint, tiles where psi is zero: lambda alone */
 } qv_kernel_id;
 
 /* One kernel launch of the last call, timed with a HIP event pair on the context's stream. bytes is the

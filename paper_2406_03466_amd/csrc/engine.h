@@ -129,6 +129,7 @@ struct Seg {
     int32_t last;         // adjoint: 1 for the circuit's first pass (undone last) -- psi and lambda are not
                           // needed afterwards, so the tile is not written back
     int64_t wait;         // persistent launch: tiles of this circuit that must be finished first
+    int64_t tile_off;     // tile number of the segment's first block (a pass's tiles may span two launches)
 };
 
 // Expectation work: one Pauli x-mask group of one circuit. Blocks [first_block, ...) cover its chunks.
@@ -392,6 +393,7 @@ int launch_segment_sum(const SegSumArgs &a, void *stream);
 int launch_fill(double *p, int64_t n, double v, void *stream);
 int launch_matrices(const MatArgs &a, int precision, void *stream);
 int launch_shift_matrices(const ShiftMatArgs &a, int precision, void *stream);
+int launch_rlevel_lam(const LevelArgs &a, int precision, void *stream);  // adjoint tiles where psi is zero
 int launch_rz_phase(const StatePhaseArgs &a, void *stream);            // writes a.phase
 int launch_scale_copy(const StatePhaseArgs &a, int precision, void *stream);  // dst = phase * src
 

@@ -139,6 +139,15 @@ __global__ __launch_bounds__(NT) void k_rtile_adj(LevelArgs a)
     rtile_tiles<R, true, RB, NT>(a, smem);
 }
 
+// The tiles of an adjoint pass where psi is zero: lambda alone, with the forward's LDS layout and register
+// budget (two workgroups per CU).
+template <typename R, int RB, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rtile_lam(LevelArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    rtile_tiles<R, true, RB, NT, InterpProg, true>(a, smem);
+}
+
 // A value every lane of the workgroup holds (read back from LDS after a barrier), made wave-uniform for the
 // compiler, so that control flow depending on it is uniform.
 __device__ __forceinline__ int64_t uniform_i64(int64_t v)
@@ -238,7 +247,12 @@ __device__ __forceinline__ void persistent_body(const PersistArgs &pa)
     bool pre = false;
     while (item < pa.n_items) {
         const PersistItem it = persist_item(pa, item, end);
-        pre = run ? rtile_body<R, ADJ, RB, NT>(it.a, smem, it.blk, it.sg, pre, it.next_blk) : false;
+        // the adjoint's tiles where psi is zero run the lambda-only code, as their own launch does in levels mode
+        bool lam = false;
+        if constexpr (ADJ) lam = run && lam_tile(it.a, it.blk, it.sg);
+        if (!run) pre = false;
+        else if (lam) pre = rtile_body<R, ADJ, RB, NT, InterpProg, true>(it.a, smem, it.blk, it.sg, pre, it.next_blk);
+        else pre = rtile_body<R, ADJ, RB, NT>(it.a, smem, it.blk, it.sg, pre, it.next_blk);
         // every wave's stores of the tile have reached the L2 (vmcnt 0; expcnt and lgkmcnt left alone), so
         // thread 0's device-scope release below (one L2 write-back) covers them all
         __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -1241,6 +1255,8 @@ int prepare_kernels()
         {reinterpret_cast<const void *>(&k_rtile_adj<float, kRegBitsC64, kRtileThreads>), lim},
         {reinterpret_cast<const void *>(&k_rtile_fwd<double, kRegBitsC128, kRtileThreads>), lim},
         {reinterpret_cast<const void *>(&k_rtile_adj<double, kRegBitsC128, kRtileThreads>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_lam<float, kRegBitsC64, kRtileThreads>), lim},
+        {reinterpret_cast<const void *>(&k_rtile_lam<double, kRegBitsC128, kRtileThreads>), lim},
         {reinterpret_cast<const void *>(&k_rtile_fwd_persist<float, kRegBitsC64, kRtileThreads>), plim},
         {reinterpret_cast<const void *>(&k_rtile_adj_persist<float, kRegBitsC64, kRtileThreads>), plim},
         {reinterpret_cast<const void *>(&k_rtile_fwd_persist<double, kRegBitsC128, kRtileThreads>), plim},
@@ -1402,6 +1418,24 @@ int launch_rlevel(const LevelArgs &a_in, int precision, int adjoint, void *strea
         if (adjoint) hipLaunchKernelGGL((k_rtile_adj<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
         else hipLaunchKernelGGL((k_rtile_fwd<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
     }
+    return hipGetLastError();
+}
+
+int launch_rlevel_lam(const LevelArgs &a_in, int precision, void *stream)
+{
+    if (a_in.n_blocks <= 0) return hipSuccess;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int amp = precision == QV_C64 ? 8 : 16;
+    const size_t lds = tile_lds_bytes(a_in.lds_t, a_in.tab_bits, amp, 0);
+    if (lds > (size_t)kLdsLimit) return hipErrorInvalidValue;
+    LevelArgs a = a_in;
+    const int64_t resident = (int64_t)device_cus() * 2;
+    int64_t chunk = tile_chunk<false>();
+    while (chunk > 1 && (a.n_blocks + chunk - 1) / chunk < resident) chunk >>= 1;
+    a.chunk = (int32_t)chunk;
+    dim3 grid((unsigned)((a.n_blocks + chunk - 1) / chunk)), block(kRtileThreads);
+    if (precision == QV_C64) hipLaunchKernelGGL((k_rtile_lam<float, kRegBitsC64, kRtileThreads>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_rtile_lam<double, kRegBitsC128, kRtileThreads>), grid, block, lds, s, a);
     return hipGetLastError();
 }
 

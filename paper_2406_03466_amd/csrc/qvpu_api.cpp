@@ -186,7 +186,8 @@ struct DBuf {
     T *as() const { return reinterpret_cast<T *>(p); }
 };
 
-enum LevelKind { LK_RTILE = 0, LK_TILE = 1, LK_STRIDE = 2 };
+// LK_LAM: the tiles of a register-tiled reverse pass where psi is zero (lambda alone, k_rtile_lam)
+enum LevelKind { LK_RTILE = 0, LK_TILE = 1, LK_STRIDE = 2, LK_LAM = 3 };
 
 struct Level {
     int64_t seg_off;
@@ -496,7 +497,7 @@ static int64_t fwd_tiles(const DevCirc &c, const Plan &pl, int p, const std::vec
 // Circuits are launched in waves of at most `wave` circuits; every wave runs all its levels before the
 // next wave starts. Results do not depend on the wave size.
 static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std::vector<int> &pass_base, int wave,
-                         int amp_bytes)
+                         int amp_bytes, bool split_zero = false)
 {
     es.gen_ready[0] = es.gen_ready[1] = false;
     es.gen_timed[0] = es.gen_timed[1] = false;
@@ -533,7 +534,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
         for (int c = w0; c < w1; c++) maxp = std::max(maxp, (int)plans[es.plan_of[c]].passes.size());
         for (int dir = 0; dir < 2; dir++) {
             for (int L = 0; L < maxp; L++) {
-                for (int kind = 0; kind < 3; kind++) {
+                for (int kind = 0; kind < 4; kind++) {
                     Level lv{(int64_t)es.segs.size(), 0, 0, 0, kind, 0, 0.0, 0, 0};
                     for (int c = w0; c < w1; c++) {
                         const Plan &pl = plans[es.plan_of[c]];
@@ -541,7 +542,13 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         if (L >= np) continue;
                         const int p = dir == 0 ? L : np - 1 - L;
                         const PlanPass &pp = pl.passes[p];
-                        if (pass_kind(pp) != kind) continue;
+                        const std::vector<uint64_t> &zm = zero[(size_t)es.plan_of[c]];
+                        // a register-tiled reverse pass after the circuit's first, with tiles where psi is
+                        // zero: those (numbered last) go to the LK_LAM launch of its depth
+                        const int64_t all = tiles_of(es.circs[c], pl, p);
+                        const int64_t live = dir == 1 && split_zero && p > 0 && pass_kind(pp) == LK_RTILE
+                                                 ? fwd_tiles(es.circs[c], pl, p, zm) : all;
+                        if (kind == LK_LAM ? live == all : pass_kind(pp) != kind) continue;
                         Seg s;
                         s.first_block = lv.n_blocks;
                         s.partial_base = pbase[c][p];
@@ -550,7 +557,7 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         s.first = (dir == 0 && p == 0 && !pp.stride) ? 1 : 0;
                         s.last = (dir == 1 && p == 0) ? 1 : 0;
                         s.wait = 0;
-                        const std::vector<uint64_t> &zm = zero[(size_t)es.plan_of[c]];
+                        s.tile_off = kind == LK_LAM ? live : 0;
                         if (dir == 0) {
                             for (int q = 0; q < p; q++) s.wait += fwd_tiles(es.circs[c], pl, q, zm);
                         } else {
@@ -558,8 +565,8 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         }
                         es.segs.push_back(s);
                         lv.n_segs++;
-                        const int64_t all = tiles_of(es.circs[c], pl, p);
-                        const int64_t run = dir == 0 ? fwd_tiles(es.circs[c], pl, p, zm) : all;
+                        const int64_t run = dir == 0 ? fwd_tiles(es.circs[c], pl, p, zm)
+                                                     : (kind == LK_LAM ? all - live : live);
                         lv.n_blocks += run;
                         lv.lds_t = std::max(lv.lds_t, pp.t);
                         lv.max_train = std::max(lv.max_train, pp.n_train);
@@ -571,10 +578,12 @@ static void build_levels(ExecSet &es, const std::vector<Plan> &plans, const std:
                         const int64_t S = ((int64_t)1 << es.circs[c].n) * amp_bytes;
                         const bool rt = pass_kind(pp) == LK_RTILE;
                         const int64_t work = (rt && p == 0) ? 1 : run;
+                        // LK_LAM: lambda alone read, undone once and written
                         lv.bytes += dir == 0 ? (s.first ? S : 2 * (S / all) * run)
-                                             : (s.last ? 2 * (S / all) * work : 4 * S);
-                        lv.flops += pass_flops(pp, dir == 1, s.last != 0) * (double)((int64_t)1 << es.circs[c].n) *
-                                    ((double)work / (double)all);
+                                             : (s.last ? 2 * (S / all) * work
+                                                       : (kind == LK_LAM ? 2 : 4) * (S / all) * run);
+                        lv.flops += pass_flops(pp, dir == 1 && kind != LK_LAM, s.last != 0) *
+                                    (double)((int64_t)1 << es.circs[c].n) * ((double)work / (double)all);
                     }
                     if (lv.n_segs) (dir == 0 ? es.fwd : es.rev).push_back(lv);
                 }
@@ -833,6 +842,7 @@ static LevelArgs level_args(const qv_batch_s &bt, const ExecSet &es, const DevPl
 static int launch_kind(const Level &lv, const LevelArgs &a, int prec, int adjoint, hipStream_t s)
 {
     if (lv.kind == LK_STRIDE) return launch_stride_level(a, prec, adjoint, s);
+    if (lv.kind == LK_LAM) return launch_rlevel_lam(a, prec, s);
     if (lv.kind == LK_RTILE && lv.gen) return launch_rlevel_gen(a, adjoint, lv.gen, s);
     if (lv.kind == LK_RTILE) return launch_rlevel(a, prec, adjoint, s);
     return launch_level(a, prec, adjoint, s);
@@ -841,6 +851,7 @@ static int launch_kind(const Level &lv, const LevelArgs &a, int prec, int adjoin
 static int log_id(const Level &lv, int adjoint)
 {
     if (lv.kind == LK_STRIDE) return adjoint ? QV_K_STRIDE_ADJ : QV_K_STRIDE;
+    if (lv.kind == LK_LAM) return QV_K_RTILE_LAM;
     if (lv.kind == LK_RTILE && lv.gen) return adjoint ? QV_K_RTILE_ADJ_GEN : QV_K_RTILE_GEN;
     if (lv.kind == LK_RTILE) return adjoint ? QV_K_RTILE_ADJ : QV_K_RTILE;
     return adjoint ? QV_K_TILE_ADJ : QV_K_TILE;
@@ -1433,7 +1444,7 @@ static hipError_t configure(qv_batch_s *bt, int tile_qubits, int contig)
         HIPRET(bt->d_fmats.alloc(sizeof(float) * (size_t)std::max<int64_t>(1, fo) * kFusedFloats));
         HIPRET(bt->d_fuse_fb.upload(ffb));
     }
-    build_levels(es, bt->plans, dp->pass_base, ctx->n_vqpu, bt->amp_bytes);
+    build_levels(es, bt->plans, dp->pass_base, ctx->n_vqpu, bt->amp_bytes, ctx->persistent == 0);
     ObsView ov{bt->toff.data(), bt->xm.data(), bt->zm.data(), bt->cf.data(), bt->obs_shared};
     std::vector<int> obs_of(B);
     std::vector<int64_t> out_base(B);

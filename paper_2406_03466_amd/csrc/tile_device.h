@@ -827,13 +827,28 @@ __device__ __forceinline__ void gen_adj_op(const LevelArgs &a, const DevCirc &C,
     }
 }
 
-template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg>
+// Whether tile blk of an adjoint segment lies where psi is zero throughout the pass (a qubit of the pass's
+// zero mask at 1, in rtile_body's numbering, which puts those tiles last): a tile for the LAM code.
+__device__ __forceinline__ bool lam_tile(const LevelArgs &a, int64_t blk, const Seg &sg)
+{
+    if (sg.last) return false;
+    const DevPass P = ldu(a.passes + sg.pass);
+    const DevCirc C = ldu(a.circs + sg.circ);
+    const uint64_t full = (C.n >= 64) ? ~0ull : ((1ull << C.n) - 1ull);
+    const uint64_t outside = full & ~P.local_mask;
+    const int live = __popcll(outside & ~(P.zero_mask & outside));
+    return ((blk - sg.first_block + sg.tile_off) >> live) != 0;
+}
+
+// LAM: an adjoint launch over tiles where psi is zero throughout the pass (a qubit of the pass's zero mask
+// at 1): lambda alone is loaded, undone (each op's inverse) and stored, and the partial sums are zero.
+template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg, bool LAM = false>
 __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *smem, int64_t blk, const Seg &sg,
                                            bool preloaded, int64_t next_blk)
 {
     static_assert(RB >= 1 && RB <= 4, "register-bit dispatch covers register bits 0..3");
     constexpr int N = 1 << RB;
-    const int64_t tile = blk - sg.first_block;
+    const int64_t tile = blk - sg.first_block + sg.tile_off;
     const DevPass P = ldu(a.passes + sg.pass);
     const DevCirc C = ldu(a.circs + sg.circ);
     const int n = C.n, t = P.t, lowc = P.pad;
@@ -841,8 +856,9 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
     const int TL = 1 << (a.lds_t);
 
     Cx<R> *sp = reinterpret_cast<Cx<R> *>(smem);
-    Cx<R> *sl = sp + (ADJ ? TL : 0);
-    uint64_t *segtab = reinterpret_cast<uint64_t *>(sp + (ADJ ? 2 * TL : TL));
+    // a LAM launch keeps lambda where psi would be (it never touches psi): one tile of LDS, like the forward
+    Cx<R> *sl = sp + (ADJ && !LAM ? TL : 0);
+    uint64_t *segtab = reinterpret_cast<uint64_t *>(sp + (ADJ && !LAM ? 2 * TL : TL));
     double *red = reinterpret_cast<double *>(segtab + (1 << a.tab_bits));
 
     const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
@@ -852,12 +868,19 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
     // and the rest do nothing, which keeps a level's working tiles contiguous.
     const uint64_t outside = full & ~P.local_mask;
     const uint64_t zm = (!ADJ && !sg.first) ? (P.zero_mask & outside) : 0ull;
-    const int live = __popcll(outside & ~zm);
+    // The adjoint numbers the tiles of a pass after the circuit's first the same way, those where psi can
+    // be nonzero first (tile i: bits of i below `live` go to outside & ~zero_mask, the rest to zero_mask):
+    // the host launches those with the full kernel and the others with the LAM kernel.
+    const uint64_t zz = ADJ ? (sg.last ? 0ull : (P.zero_mask & outside)) : zm;
+    const int live = __popcll(outside & ~zz);
     if (zm != 0 && (tile >> live) != 0) {
         if (preloaded) __builtin_amdgcn_s_waitcnt(0);  // never the case: no tile prefetches such a tile
         return false;
     }
-    const uint64_t base = deposit((uint64_t)tile, outside & ~zm);
+    auto tile_base = [&](int64_t i) {
+        return deposit((uint64_t)i & ((1ull << live) - 1ull), outside & ~zz) | deposit((uint64_t)i >> live, zz);
+    };
+    const uint64_t base = tile_base(tile);
     const uint64_t himask = P.local_mask & ~((1ull << lowc) - 1ull);
     const uint32_t nh = 1u << (t - lowc);
     const uint32_t lmask = (1u << lowc) - 1u;
@@ -892,8 +915,10 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
         for (uint32_t e = threadIdx.x; e < T; e += NT) gpsi[base | segtab[e >> lowc] | (e & lmask)] = z;
         return false;
     }
+    // (a tile prefetches only a successor of its own kind: a LAM tile keeps lambda where psi would be)
+    const int64_t ntile = next_blk - sg.first_block + sg.tile_off;
     const bool pf = next_blk >= 0 && !(!ADJ && sg.first) && !stop_early && T >= (uint32_t)APP && nseg > 0 &&
-                    !(zm != 0 && ((next_blk - sg.first_block) >> live) != 0);
+                    !(zm != 0 && (ntile >> live) != 0) && (!ADJ || LAM == (zz != 0 && (ntile >> live) != 0));
 
     if (preloaded) {
         // this tile was loaded by the previous tile's last segment (same pass: the run table is in place)
@@ -918,7 +943,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
                 const uint32_t e = e0 + (uint32_t)u * NT;
                 if (e < T) {
                     const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
-                    bp.set(u, gpsi[g]);
+                    if (!LAM) bp.set(u, gpsi[g]);
                     if (ADJ) bl.set(u, glam[g]);
                 }
             }
@@ -926,7 +951,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
             for (int u = 0; u < TB; u++) {
                 const uint32_t e = e0 + (uint32_t)u * NT;
                 if (e < T) {
-                    sp[swz(e)] = bp.get(u);
+                    if (!LAM) sp[swz(e)] = bp.get(u);
                     if (ADJ) sl[swz(e)] = bl.get(u);
                 }
             }
@@ -976,7 +1001,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
                 for (int k = 0; k < RB; k++)
                     if (j >> k & 1) D ^= rl[k];
                 const uint32_t addr = PL ^ swz(D);
-                av.set(j, sp[addr]);
+                if (!LAM) av.set(j, sp[addr]);
                 if (ADJ) lv.set(j, sl[addr]);
             }
         }
@@ -985,7 +1010,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
         if (remap && !(pf && last_seg)) __syncthreads();
         if (pf && last_seg) {
             __syncthreads();  // every wave has its registers: LDS may be overwritten
-            const uint64_t nbase = deposit((uint64_t)(next_blk - sg.first_block), outside & ~zm);
+            const uint64_t nbase = tile_base(next_blk - sg.first_block + sg.tile_off);
             for (uint32_t c = (uint32_t)wave; c < T / APP; c += NT / 64) {
                 // load c covers LDS positions [c*APP, (c+1)*APP); position q holds element swz(q)
                 if constexpr (sizeof(R) == 4) {
@@ -993,9 +1018,10 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
                     const uint32_t e = swz(d >> 1);
                     const uint64_t g = nbase | segtab[e >> lowc] | (e & lmask);
                     const float *src = reinterpret_cast<const float *>(gpsi + g) + (d & 1u);
-                    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
-                                                     (void __attribute__((address_space(3))) *)(sp + c * APP),
-                                                     4, 0, 0);
+                    if (!LAM)
+                        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                                                         (void __attribute__((address_space(3))) *)(sp + c * APP),
+                                                         4, 0, 0);
                     if (ADJ) {
                         const float *lsrc = reinterpret_cast<const float *>(glam + g) + (d & 1u);
                         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)lsrc,
@@ -1005,9 +1031,10 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
                 } else {
                     const uint32_t e = swz(c * APP + (uint32_t)lane);
                     const uint64_t g = nbase | segtab[e >> lowc] | (e & lmask);
-                    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(gpsi + g),
-                                                     (void __attribute__((address_space(3))) *)(sp + c * APP),
-                                                     16, 0, 0);
+                    if (!LAM)
+                        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(gpsi + g),
+                                                         (void __attribute__((address_space(3))) *)(sp + c * APP),
+                                                         16, 0, 0);
                     if (ADJ)
                         __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(glam + g),
                                                          (void __attribute__((address_space(3))) *)(sl + c * APP),
@@ -1036,7 +1063,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
                             if (j >> k & 1) D ^= rb2[k];
                         const uint32_t e = es ^ D;
                         const uint64_t g = base | segtab[e >> lowc] | (e & lmask);
-                        gpsi[g] = v.get(j);
+                        if (!LAM) gpsi[g] = v.get(j);
                         if (ADJ) glam[g] = l.get(j);
                     }
                 }
@@ -1049,7 +1076,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
                     for (int k = 0; k < RB; k++)
                         if (j >> k & 1) D ^= rb2[k];
                     const uint32_t addr = pe ^ swz(D);
-                    sp[addr] = v.get(j);
+                    if (!LAM) sp[addr] = v.get(j);
                     if (ADJ) sl[addr] = l.get(j);
                 }
             }
@@ -1075,7 +1102,27 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
         oc.oi = S.op_begin + (ADJ ? S.n_ops - 1 : 0);
         oc.op = ldu(a.ops + oc.oi);    // a segment holds at least one op
         oc.mat = ldu(mtab + oc.oi);
-        if constexpr (ADJ) {
+        if constexpr (LAM) {
+            // lambda alone: each op's inverse in reverse order (fused-block markers are skipped: the block's
+            // gates follow them); the next op's record and matrix are fetched while this one runs
+            DevOp nop = oc.op;
+            M2<R> nmat = oc.mat;
+            for (int64_t oi = (int64_t)S.op_begin + S.n_ops - 1; oi >= (int64_t)S.op_begin; oi--) {
+                const DevOp op = nop;
+                M2<R> mat = nmat;
+                if (oi > (int64_t)S.op_begin) {
+                    nop = ldu(a.ops + oi - 1);
+                    nmat = ldu(mtab + oi - 1);
+                }
+                if (op.kind == kFusedKind) continue;
+                if (op.gate == C.shift_gate) {
+                    mat = ldu(reinterpret_cast<const M2<R> *>(a.smats) + sg.circ);
+                    scalar_wait(mat);
+                }
+                code_apply<true, RB, R>(lv, op.flags >> kOpCodeShift, op, mat, Et);
+            }
+            store(lv, lv);
+        } else if constexpr (ADJ) {
             Regs<R, N> aw, lw;
             while (oc.k < oc.n) {
                 adj_step<R, RB, NT>(a, C, sg.circ, mtab, oc, Et, active, lane, wave, red, av, lv, aw, lw);
@@ -1110,7 +1157,8 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
     if (ADJ) {
         for (int slot = threadIdx.x; slot < P.n_train; slot += NT) {
             double s = 0.0;
-            for (int w = 0; w < NT / 64; w++) s += red[slot * (NT / 64) + w];
+            if (!LAM)  // a LAM launch has no reduction area: its tiles' inner products are zero
+                for (int w = 0; w < NT / 64; w++) s += red[slot * (NT / 64) + w];
             a.partials[sg.partial_base + tile * P.n_train + slot] = s;
         }
     }
@@ -1130,7 +1178,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
             const uint32_t e = e0 + (uint32_t)u * NT;
             if (e < T) {
                 gi[u] = base | segtab[e >> lowc] | (e & lmask);
-                bp.set(u, sp[swz(e)]);
+                if (!LAM) bp.set(u, sp[swz(e)]);
                 if (ADJ) bl.set(u, sl[swz(e)]);
             }
         }
@@ -1138,7 +1186,7 @@ __device__ __forceinline__ bool rtile_body(const LevelArgs &a, unsigned char *sm
         for (int u = 0; u < TB; u++) {
             const uint32_t e = e0 + (uint32_t)u * NT;
             if (e < T) {
-                gpsi[gi[u]] = bp.get(u);
+                if (!LAM) gpsi[gi[u]] = bp.get(u);
                 if (ADJ) glam[gi[u]] = bl.get(u);
             }
         }
@@ -1167,7 +1215,7 @@ __device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t n)
     return x * q + (x < r ? x : r) + i;
 }
 
-template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg>
+template <typename R, bool ADJ, int RB, int NT, class PROG = InterpProg, bool LAM = false>
 __device__ __forceinline__ void rtile_tiles(const LevelArgs &a, unsigned char *smem)
 {
     const int64_t ch = a.chunk;
@@ -1184,7 +1232,7 @@ __device__ __forceinline__ void rtile_tiles(const LevelArgs &a, unsigned char *s
             const Seg sg = a.segs[si];
             const int64_t send = si + 1 < a.n_segs ? a.segs[si + 1].first_block : a.n_blocks;
             const int64_t nxt = (blk + 1 < b1 && blk + 1 < send) ? blk + 1 : -1;
-            pre = rtile_body<R, ADJ, RB, NT, PROG>(a, smem, blk, sg, pre, nxt);
+            pre = rtile_body<R, ADJ, RB, NT, PROG, LAM>(a, smem, blk, sg, pre, nxt);
             __syncthreads();
         }
     }

@@ -45,7 +45,8 @@ class qv_launch_rec(ctypes.Structure):
 
 KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "finalize", "lambda",
                 "grad_reduce", "shift_combine", "rtile", "rtile_adj", "matrices", "rtile_persist",
-                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum", "sample", "rtile_gen", "rtile_adj_gen"]
+                "rtile_adj_persist", "fuse", "probs", "diag_seed", "diag_expect", "segment_sum", "sample", "rtile_gen", "rtile_adj_gen",
+                "rtile_lam"]
 
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),
