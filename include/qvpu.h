@@ -338,6 +338,8 @@ typedef struct {
     int32_t contiguous_low; /* qubits 0..contiguous_low-1 are all local (length of contiguous runs) */
     int32_t n_fused;      /* fused blocks among the pass's gates */
     int32_t n_folded;     /* CNOTs folded into register-segment LDS addressing ("tiled" engine) */
+    uint64_t zero_mask;   /* qubits outside the tile that no earlier pass touches (bits below n_qubits):
+                             still |0>, so tiles with one of them at 1 hold zeros through the pass */
 } qv_pass_info;
 
 /* Plans one circuit without a device, as qv_batch_create would for a batch with the given engine

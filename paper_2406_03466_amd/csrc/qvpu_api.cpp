@@ -2509,10 +2509,13 @@ qv_status qv_plan_circuit(int32_t n_qubits, int64_t n_gates, const qv_gate *gate
     const int rb = engine == 0 ? (precision == QV_C64 ? kRegBitsC64 : kRegBitsC128) : 0;
     const Plan pl = engine == 2 ? plan_stride(pin) : plan_tiled(pin, t, lowc, rb, engine == 0 ? fuse_min : 0);
     *n_passes = (int32_t)pl.passes.size();
+    const std::vector<uint64_t> zero = pass_zero_masks(pl);
+    const uint64_t width = n_qubits >= 64 ? ~0ull : ((1ull << n_qubits) - 1ull);
     for (int32_t i = 0; i < *n_passes && i < max_passes; i++) {
         const PlanPass &pp = pl.passes[i];
         qv_pass_info &o = out[i];
         o.local_mask = pp.local_mask;
+        o.zero_mask = zero[(size_t)i] & width;
         o.qubits = pp.t;
         int32_t nf = 0;
         for (const PlanOp &op : pp.ops) nf += op.kind == kFusedKind ? 1 : 0;

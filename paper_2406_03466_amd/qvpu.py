@@ -51,7 +51,8 @@ KERNEL_NAMES = ["init", "tile", "tile_adj", "stride", "stride_adj", "expect", "f
 class qv_pass_info(ctypes.Structure):
     _fields_ = [("local_mask", ctypes.c_uint64), ("qubits", ctypes.c_int32), ("n_ops", ctypes.c_int32),
                 ("n_trainable", ctypes.c_int32), ("n_segments", ctypes.c_int32), ("first_gate", ctypes.c_int32),
-                ("contiguous_low", ctypes.c_int32), ("n_fused", ctypes.c_int32), ("n_folded", ctypes.c_int32)]
+                ("contiguous_low", ctypes.c_int32), ("n_fused", ctypes.c_int32), ("n_folded", ctypes.c_int32),
+                ("zero_mask", ctypes.c_uint64)]
 
 
 _lib = None

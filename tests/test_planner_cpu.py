@@ -139,3 +139,41 @@ def test_folded_order_matches_state():
     s0 = oracle.final_state(n, gates, theta)
     s1 = oracle.final_state(n, gates[order], theta)
     assert np.max(np.abs(s0 - s1)) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["hea", "ddcl", "random"])
+def test_zero_masks(case):
+    """A pass's zero mask holds the qubits outside its tile that no gate of an earlier pass acts on
+    (recomputed here from the planned gate order and the passes' tiles). Before the pass those qubits are
+    still |0>, so the state is exactly zero wherever one of them is 1 (oracle state, complex128, after the
+    earlier passes' gates in planned order)."""
+    rng = np.random.default_rng(5)
+    n = 11
+    if case == "hea":
+        gates = np.array(W.hea_layers(n, 3)[0], W.GATE_DTYPE)
+    elif case == "ddcl":
+        gates = np.array(W.ddcl_layers(n, 2)[0], W.GATE_DTYPE)
+    else:
+        gates = W.random_batch(1, n, n, 60, 60, 1, seed_index=51).circuit(0).copy()
+    n_par = int(gates["param"].max()) + 1 if (gates["param"] >= 0).any() else 0
+    theta = rng.uniform(0, 2 * np.pi, size=max(1, n_par))
+    passes, order = qvpu.plan_circuit(n, gates, 6, qvpu.QV_C64, 0, with_order=True)
+    assert len(passes) > 1
+    full = (1 << n) - 1
+    touched, pos, seen_zero = 0, 0, False
+    for p in passes:
+        expect = full & ~p["local_mask"] & ~touched
+        assert p["zero_mask"] == expect, (p["zero_mask"], expect)
+        state = oracle.final_state(n, gates[order[:pos]], theta)
+        idx = np.arange(1 << n)
+        if expect:
+            seen_zero = True
+            assert np.all(state[(idx & expect) != 0] == 0)
+        for gi in order[pos:pos + p["n_ops"]]:
+            g = gates[gi]
+            touched |= 1 << int(g["q0"])
+            if int(g["q1"]) >= 0 and int(g["kind"]) in (W.CNOT, W.CZ):
+                touched |= 1 << int(g["q1"])
+        pos += p["n_ops"]
+    assert pos == len(gates)
+    assert seen_zero
